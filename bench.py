@@ -1,0 +1,163 @@
+"""Benchmark: compact Life on the Sierpinski triangle vs the bounding-box grid.
+
+Workload (N=1): level-16 Sierpinski triangle, replicas (0,0),(1,0),(0,1),
+43,046,721 compact cells, uint8 states from a Bernoulli(0.5) SplitMix64 start
+(seed 2201), B3/S23 steps ping-ponging between two compact buffers.  One
+"step" is one launch of the compact stencil over every cell.  The same steps
+on the 65536 x 65536 bounding-box grid give the speedup; the level-20 triangle
+(3.49e9 cells, 20 steps, Bernoulli(0.3)) gives the HBM-bound figure.
+
+Prints one JSON line.  Inputs are resident in HBM before timing starts.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "compact cell-updates/s vs expanded bounding-box on 1 MI355X; HBM GB/s % of peak"
+TRIANGLE = (2, [(0, 0), (1, 0), (0, 1)])
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+BYTES_PER_UPDATE = 2   # one byte read, one byte written per cell per step
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def time_steps(torch, step, steps: int, warmup: int):
+    """Run `warmup` untimed then `steps` timed calls of step(i); HIP events on the
+    current stream (the stream the library launches on).  Returns seconds."""
+    for i in range(warmup):
+        step(i)
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for i in range(steps):
+        step(warmup + i)
+    end.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / 1e3
+
+
+def compact_run(torch, F, seed, p, steps, warmup, impl="auto"):
+    a = F.fill_bernoulli(seed, p)
+    b = torch.empty_like(a)
+    bufs = (a, b)
+
+    def step(i):
+        F.compact_step(bufs[i & 1], bufs[(i + 1) & 1], impl=impl)
+
+    sec = time_steps(torch, step, steps, warmup)
+    del a, b
+    return sec
+
+
+def bb_run(torch, F, seed, p, steps, warmup):
+    a = F.fill_bernoulli(seed, p, layout="expanded")
+    b = torch.empty_like(a)
+    bufs = (a, b)
+
+    def step(i):
+        F.expanded_step(bufs[i & 1], bufs[(i + 1) & 1])
+
+    sec = time_steps(torch, step, steps, warmup)
+    del a, b
+    torch.cuda.empty_cache()
+    return sec
+
+
+def cpu_baseline(r: int, seed: int, p: float, cells: int) -> dict:
+    """The oracle (plain C, OpenMP) stepping the first `cells` cells of the same workload."""
+    import oracle
+
+    O = oracle.Fractal(*TRIANGLE, r)
+    start = O.fill_compact(seed, p)
+    t0 = time.perf_counter()
+    O.life_compact(start, 0, cells)
+    sec = time.perf_counter() - t0
+    return {"value": cells / sec, "unit": "cell-updates/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"one B3/S23 step of compact cells [0, {cells}) of the level-{r} triangle "
+                      f"(lambda + 8 nu per cell), {sec:.1f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--level", type=int, default=16)
+    ap.add_argument("--impl", default="auto", choices=["auto", "tile", "cell"])
+    ap.add_argument("--bb-steps", type=int, default=10)
+    ap.add_argument("--r20-steps", type=int, default=20)
+    ap.add_argument("--no-bb", action="store_true")
+    ap.add_argument("--no-r20", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-cells", type=int, default=12_000_000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the multi-GPU "
+              "design is described in DESIGN.md, nothing here runs on more than one device)", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_2201_00613_amd as sqz
+
+    torch.cuda.set_device(0)
+    seed, p, r = 2201, 0.5, args.level
+    F = sqz.Fractal(*TRIANGLE, r)
+    log(f"[bench] triangle r={r}: {F.cells} cells, tile level {F.tile_level}, impl {args.impl}")
+    sec = compact_run(torch, F, seed, p, args.steps, args.warmup, args.impl)
+    ups = F.cells * args.steps / sec
+    ms = sec * 1e3 / args.steps
+    gbs = BYTES_PER_UPDATE * F.cells / (sec / args.steps) / 1e9
+    log(f"[bench] compact: {ms:.4f} ms/step, {ups:.4e} cell-updates/s, {gbs:.1f} GB/s algorithmic")
+
+    out = {
+        "metric": METRIC, "value": ups, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": f"sierpinski-triangle-r{r}-life-b3s23", "fractal": "sierpinski triangle s=2 k=3",
+                   "level": r, "cells": F.cells, "bernoulli_p": p, "seed": seed, "impl": args.impl,
+                   "tile_level": F.tile_level, "note": "2 x 43 MB working set is Infinity-Cache resident"},
+        "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs / HBM_PEAK_GBS, "traffic": None},
+    }
+    if not args.no_bb:
+        bsec = bb_run(torch, F, seed, p, args.bb_steps, 2)
+        bb_ups = F.cells * args.bb_steps / bsec
+        bb_ms = bsec * 1e3 / args.bb_steps
+        log(f"[bench] bounding box: {bb_ms:.3f} ms/step, {bb_ups:.4e} useful cell-updates/s")
+        out["bb"] = {"ms_per_step": bb_ms, "useful_cell_updates_per_s": bb_ups,
+                     "expanded_cells_per_s": F.n * F.n * args.bb_steps / bsec,
+                     "algorithmic_gbs": 2 * F.n * F.n / (bsec / args.bb_steps) / 1e9, "steps": args.bb_steps}
+        out["speedup_vs_bb"] = ups / bb_ups
+    del F
+    torch.cuda.empty_cache()
+    if not args.no_r20:
+        F20 = sqz.Fractal(*TRIANGLE, 20)
+        s20 = compact_run(torch, F20, seed, 0.3, args.r20_steps, 2)
+        ms20 = s20 * 1e3 / args.r20_steps
+        gbs20 = BYTES_PER_UPDATE * F20.cells / (s20 / args.r20_steps) / 1e9
+        out["r20"] = {"cells": F20.cells, "steps": args.r20_steps, "ms_per_step": ms20,
+                      "cell_updates_per_s": F20.cells * args.r20_steps / s20, "algorithmic_gbs": gbs20,
+                      "hbm_frac": gbs20 / HBM_PEAK_GBS, "bernoulli_p": 0.3}
+        log(f"[bench] r=20: {ms20:.3f} ms/step, {gbs20:.1f} GB/s ({100 * gbs20 / HBM_PEAK_GBS:.1f}% of HBM peak)")
+        del F20
+        torch.cuda.empty_cache()
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(r, seed, p, min(args.cpu_cells, 3 ** r))
+        log(f"[bench] cpu oracle: {out['cpu_baseline']['value']:.3e} cell-updates/s "
+            f"on {out['cpu_baseline']['cores']} threads")
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,193 @@
+/*
+ * squeeze.h -- C ABI of libsqueeze, a compact-fractal stencil library for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: Quezada, Navarro, Hitschfeld, Bustos, "Squeeze: Efficient Compact
+ * Fractals for Tensor Core GPUs" (arXiv 2201.00613).  A fractal of the
+ * Non-overlapping-Bounding-Boxes (NBB) class is stored in compact form, one
+ * value per fractal cell, and neighbourhood computations run on that form
+ * through two maps: lambda (compact -> expanded) and nu (expanded ->
+ * compact).  The n x n expanded bounding box is never materialised, except
+ * by the bounding-box baseline sqz_expanded_step.
+ *
+ * Conventions for every call:
+ *   - Pointers named d_* are device pointers owned by the caller (for
+ *     example torch tensors); the library never frees them.  Host pointers
+ *     are read before the call returns.
+ *   - `stream` is a hipStream_t passed as void*; NULL is the default stream.
+ *     Kernel work is enqueued asynchronously on that stream.
+ *   - Argument errors are detected on the host before anything is launched
+ *     and leave outputs untouched.  A failed launch returns SQZ_ERR_HIP; a
+ *     fault inside a kernel surfaces at the next synchronisation of the
+ *     stream (or as SQZ_ERR_HIP from a later call).
+ *   - sqz_last_error() returns a message for the calling thread's last
+ *     failure.  No C++ exception crosses this interface.
+ *
+ * Compact layout: the cell with compact index c (0 <= c < N = k^r) has
+ * base-k digits beta_1 (least significant) .. beta_r and sits at expanded
+ * coordinate lambda(c) = sum_mu tau(beta_mu) s^(mu-1) (Section "Revisiting
+ * lambda").  Each level-m subtree is the contiguous range [t k^m, (t+1) k^m).
+ * Expanded layout: n x n row-major, byte (x, y) at y*n + x, origin top-left,
+ * x to the right, y downwards (Section "Formulation of nu").
+ */
+#ifndef SQUEEZE_H
+#define SQUEEZE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Symbols of the library's public interface (everything else is hidden). */
+#if defined(__GNUC__)
+#define SQZ_API __attribute__((visibility("default")))
+#else
+#define SQZ_API
+#endif
+
+typedef enum sqz_status {
+    SQZ_OK = 0,
+    SQZ_ERR_INVALID = 1,     /* malformed argument or descriptor */
+    SQZ_ERR_RANGE = 2,       /* sizes overflow the index types or the device */
+    SQZ_ERR_NOMEM = 3,       /* a device allocation of the library failed */
+    SQZ_ERR_HIP = 4,         /* a HIP runtime call or kernel launch failed */
+    SQZ_ERR_UNSUPPORTED = 5  /* valid request with no implementation here */
+} sqz_status;
+
+/* nu's result for a point that is not a fractal cell (hole or outside the box). */
+#define SQZ_HOLE UINT64_MAX
+
+typedef enum sqz_layout { SQZ_LAYOUT_COMPACT = 0, SQZ_LAYOUT_EXPANDED = 1 } sqz_layout;
+
+/* Implementation of the compact stencil.
+ *   SQZ_IMPL_AUTO: the tiled kernel when one exists for the replica pattern, else CELL.
+ *   SQZ_IMPL_CELL: thread-level Squeeze: one lambda and eight nu per cell
+ *                  (Section "Exploring Compact Fractal Space").
+ *   SQZ_IMPL_TILE: block-level Squeeze (Section "Moving from Thread-level to
+ *                  Block-level"): one coarse map set per level-M subtree, the
+ *                  subtree staged on chip.  SQZ_ERR_UNSUPPORTED if the pattern
+ *                  has no tiled kernel. */
+typedef enum sqz_impl { SQZ_IMPL_AUTO = 0, SQZ_IMPL_CELL = 1, SQZ_IMPL_TILE = 2 } sqz_impl;
+
+typedef struct sqz_fractal sqz_fractal;
+
+typedef struct sqz_info {
+    int32_t s;           /* linear scale factor per level */
+    int32_t k;           /* number of replicas */
+    int32_t r;           /* level */
+    int32_t tile_level;  /* level M of the subtrees the tiled kernel stages (0 if none) */
+    int64_t n;           /* side of the expanded box, s^r */
+    uint64_t cells;      /* N = k^r, the volume V of Eq. V */
+    uint64_t compact_w;  /* width of the paper's compact rectangle, k^ceil(r/2) */
+    uint64_t compact_h;  /* height, k^floor(r/2) (Section "Compacting NBB Fractals") */
+    int32_t has_tile;    /* 1 if SQZ_IMPL_TILE is available for this pattern */
+    int32_t reserved;
+} sqz_info;
+
+/*
+ * Validate an NBB descriptor without touching any device (Introduction:
+ * NBB properties; Section "Overview of Squeeze": F_n^{k,s}, r = log_s n).
+ *   s: 2..16.  k: 1..s*s.  offsets_xy: k pairs (x, y), replica j is pair j,
+ *   each coordinate in [0, s), pairs distinct.  r >= 0 with n = s^r < 2^31
+ *   and N = k^r < 2^62.
+ * Returns SQZ_ERR_INVALID for a malformed descriptor, SQZ_ERR_RANGE when n
+ * or N overflow.  On success fills *out (if not NULL); tile fields are 0.
+ */
+SQZ_API sqz_status sqz_descriptor_check(int32_t s, int32_t k, const int32_t *offsets_xy, int32_t r,
+                                sqz_info *out);
+
+/*
+ * Create a fractal handle on the current HIP device: validates as above,
+ * builds the map tables on the host and uploads them (synchronously).  The
+ * handle owns those device tables; it is immutable and may be used from
+ * several threads and streams afterwards.  *out is written only on success.
+ * Errors: as sqz_descriptor_check, SQZ_ERR_NOMEM, SQZ_ERR_HIP.
+ */
+SQZ_API sqz_status sqz_fractal_create(int32_t s, int32_t k, const int32_t *offsets_xy, int32_t r,
+                              sqz_fractal **out);
+
+/* Release a handle (NULL is allowed).  Work queued with it must have finished. */
+SQZ_API void sqz_fractal_destroy(sqz_fractal *f);
+
+/* Describe a handle. SQZ_ERR_INVALID on NULL arguments. */
+SQZ_API sqz_status sqz_fractal_info(const sqz_fractal *f, sqz_info *out);
+
+/*
+ * lambda (Section "Revisiting lambda"): compact index -> expanded coordinate.
+ *   d_idx: count uint64 compact indices.  d_xy: 2*count int32, (x, y) pairs.
+ *   An index >= N yields (-1, -1).  count == 0 is a no-op; count < 0 or a
+ *   NULL pointer with count > 0 is SQZ_ERR_INVALID.
+ */
+SQZ_API sqz_status sqz_lambda_map(const sqz_fractal *f, const uint64_t *d_idx, int64_t count,
+                          int32_t *d_xy, void *stream);
+
+/*
+ * nu (Section "Formulation of nu"): expanded coordinate -> compact index.
+ *   d_xy: 2*count int32 (x, y) pairs.  d_idx: count uint64 results; a point
+ *   that is a hole or lies outside [0, n)^2 (negative included) yields
+ *   SQZ_HOLE.  Errors as sqz_lambda_map.
+ */
+SQZ_API sqz_status sqz_nu_map(const sqz_fractal *f, const int32_t *d_xy, int64_t count, uint64_t *d_idx,
+                      void *stream);
+
+/*
+ * Seeded Bernoulli(p) start, keyed by the expanded coordinate: the cell at
+ * (x, y) is 1 iff the top 24 bits of output number y*n+x+1 of SplitMix64
+ * seeded with `seed` are below floor(p * 2^24).
+ *   layout COMPACT: d_state holds N bytes.  layout EXPANDED: n*n bytes,
+ *   holes set to 0.  p outside [0, 1] is SQZ_ERR_INVALID.
+ */
+SQZ_API sqz_status sqz_fill_bernoulli(const sqz_fractal *f, uint64_t seed, double p, sqz_layout layout,
+                              uint8_t *d_state, void *stream);
+
+/*
+ * Seeded U(0,1) start in compact layout for the diffusion workload: cell
+ * value = (top 24 bits of the same SplitMix64 output) * 2^-24, stored as
+ * float (exact).  d_u holds N floats.
+ */
+SQZ_API sqz_status sqz_fill_uniform(const sqz_fractal *f, uint64_t seed, float *d_u, void *stream);
+
+/*
+ * One synchronous step of Conway's Life (B3/S23) on the fractal, compact in
+ * and out (Section "Experimental Setup and Results": Moore neighbourhood in
+ * expanded space, holes neither simulated nor counted, no wrap at the box).
+ *   d_in, d_out: N bytes each, states 0/1 (other values: undefined result).
+ *   The two ranges must not overlap (SQZ_ERR_INVALID).
+ * Uses SQZ_IMPL_AUTO.
+ */
+SQZ_API sqz_status sqz_compact_step(const sqz_fractal *f, const uint8_t *d_in, uint8_t *d_out,
+                            void *stream);
+
+/* As sqz_compact_step with an explicit implementation choice. */
+SQZ_API sqz_status sqz_compact_step_impl(const sqz_fractal *f, sqz_impl impl, const uint8_t *d_in,
+                                 uint8_t *d_out, void *stream);
+
+/*
+ * `steps` Life steps ping-ponging between d_a and d_b, starting from d_a.
+ * The result is in d_a when steps is even, in d_b when odd.  steps >= 0.
+ */
+SQZ_API sqz_status sqz_compact_run(const sqz_fractal *f, uint8_t *d_a, uint8_t *d_b, int32_t steps,
+                           void *stream);
+
+/*
+ * Bounding-box baseline (Section "Experimental Setup and Results", approach
+ * BB): the same Life step on the expanded n x n grid, holes written 0.
+ *   d_in, d_out: n*n bytes each, non-overlapping, holes of d_in must be 0.
+ *   SQZ_ERR_RANGE when two n*n buffers cannot fit in the device's memory
+ *   (for example the level-20 triangle: 2 x 1.1 TB).
+ */
+SQZ_API sqz_status sqz_expanded_step(const sqz_fractal *f, const uint8_t *d_in, uint8_t *d_out,
+                             void *stream);
+
+/* Static text for a status code. */
+SQZ_API const char *sqz_status_string(sqz_status st);
+
+/* Message for the calling thread's most recent failure ("" if none). */
+SQZ_API const char *sqz_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SQUEEZE_H */

@@ -1,0 +1,164 @@
+"""Squeeze on MI355X: compact-fractal stencils through the lambda/nu space maps.
+
+Python binding of libsqueeze (include/squeeze.h).  Every call marshals torch
+device tensors to the C ABI and launches on torch's current HIP stream; all
+arithmetic runs in the library's HIP kernels.  There is no CPU fallback: the
+binding raises if the native library is missing or no HIP device is present.
+"""
+from __future__ import annotations
+
+import ctypes
+
+from ._lib import (HOLE, IMPL_AUTO, IMPL_CELL, IMPL_TILE, LAYOUT_COMPACT, LAYOUT_EXPANDED, Info, SqueezeError,
+                   check, lib)
+
+__all__ = ["Fractal", "SqueezeError", "HOLE", "descriptor_check", "IMPLS"]
+
+IMPLS = {"auto": IMPL_AUTO, "cell": IMPL_CELL, "tile": IMPL_TILE}
+
+
+def _offsets_array(offsets):
+    flat = [int(v) for xy in offsets for v in xy]
+    return (ctypes.c_int32 * max(1, len(flat)))(*flat), len(flat) // 2
+
+
+def descriptor_check(s: int, offsets, r: int) -> dict:
+    """Validate (s, offsets, r) on the host only; returns the sqz_info fields."""
+    arr, k = _offsets_array(offsets)
+    info = Info()
+    check(lib().sqz_descriptor_check(s, k, arr, r, ctypes.byref(info)))
+    return {f: getattr(info, f) for f, _ in Info._fields_}
+
+
+def _torch():
+    import torch
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("paper_2201_00613_amd needs a HIP device (torch.cuda.is_available() is False)")
+    return torch
+
+
+def _stream(torch, device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Fractal:
+    """An NBB fractal (s, replica offsets, level r) resident on one HIP device.
+
+    Compact state tensors are uint8 (Life) of length ``cells``; the expanded
+    bounding-box layout is an (n, n) uint8 tensor indexed [y, x].
+    """
+
+    def __init__(self, s: int, offsets, r: int, device=None):
+        torch = _torch()
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
+                                   torch.device(device).index or 0)
+        arr, k = _offsets_array(offsets)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(lib().sqz_fractal_create(s, k, arr, r, ctypes.byref(h)))
+        self._h = h
+        info = Info()
+        check(lib().sqz_fractal_info(h, ctypes.byref(info)))
+        self.s, self.k, self.r = info.s, info.k, info.r
+        self.n, self.cells = info.n, info.cells
+        self.compact_shape = (info.compact_h, info.compact_w)
+        self.has_tile = bool(info.has_tile)
+        self.tile_level = info.tile_level
+        self.offsets = [tuple(map(int, xy)) for xy in offsets]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sqz_fractal_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers ------------------------------------------------------------
+    def _ctx(self):
+        torch = _torch()
+        return torch, torch.cuda.device(self.device), _stream(torch, self.device)
+
+    def _need(self, t, dtype, numel, name):
+        if t.device != self.device or t.dtype != dtype or not t.is_contiguous() or t.numel() != numel:
+            raise ValueError(f"{name}: need a contiguous {dtype} tensor of {numel} elements on {self.device}")
+
+    def empty_state(self, layout: str = "compact"):
+        torch = _torch()
+        numel = self.cells if layout == "compact" else self.n * self.n
+        return torch.empty(numel, dtype=torch.uint8, device=self.device)
+
+    # -- maps -----------------------------------------------------------------
+    def lambda_map(self, idx):
+        """idx: int64 tensor (read as uint64) -> (count, 2) int32 (x, y); (-1,-1) past the end."""
+        torch, dev, st = self._ctx()
+        idx = idx.contiguous()
+        out = torch.empty((idx.numel(), 2), dtype=torch.int32, device=self.device)
+        self._need(idx, torch.int64, idx.numel(), "idx")
+        with dev:
+            check(lib().sqz_lambda_map(self._h, _ptr(idx), idx.numel(), _ptr(out), st))
+        return out
+
+    def nu_map(self, xy):
+        """xy: (count, 2) int32 -> int64 tensor of compact indices, -1 (= SQZ_HOLE) for holes."""
+        torch, dev, st = self._ctx()
+        xy = xy.contiguous()
+        count = xy.numel() // 2
+        self._need(xy, torch.int32, 2 * count, "xy")
+        out = torch.empty(count, dtype=torch.int64, device=self.device)
+        with dev:
+            check(lib().sqz_nu_map(self._h, _ptr(xy), count, _ptr(out), st))
+        return out
+
+    # -- starts ---------------------------------------------------------------
+    def fill_bernoulli(self, seed: int, p: float, layout: str = "compact", out=None):
+        torch, dev, st = self._ctx()
+        out = self.empty_state(layout) if out is None else out
+        numel = self.cells if layout == "compact" else self.n * self.n
+        self._need(out.view(-1), torch.uint8, numel, "out")
+        lay = LAYOUT_COMPACT if layout == "compact" else LAYOUT_EXPANDED
+        with dev:
+            check(lib().sqz_fill_bernoulli(self._h, seed, p, lay, _ptr(out), st))
+        return out
+
+    def fill_uniform(self, seed: int, out=None):
+        torch, dev, st = self._ctx()
+        out = torch.empty(self.cells, dtype=torch.float32, device=self.device) if out is None else out
+        self._need(out, torch.float32, self.cells, "out")
+        with dev:
+            check(lib().sqz_fill_uniform(self._h, seed, _ptr(out), st))
+        return out
+
+    # -- Life -----------------------------------------------------------------
+    def compact_step(self, src, dst, impl: str = "auto"):
+        torch, dev, st = self._ctx()
+        self._need(src, torch.uint8, self.cells, "src")
+        self._need(dst, torch.uint8, self.cells, "dst")
+        with dev:
+            check(lib().sqz_compact_step_impl(self._h, IMPLS[impl], _ptr(src), _ptr(dst), st))
+        return dst
+
+    def compact_run(self, a, b, steps: int):
+        """steps Life steps ping-ponging a -> b -> a ...; returns the tensor holding the result."""
+        torch, dev, st = self._ctx()
+        self._need(a, torch.uint8, self.cells, "a")
+        self._need(b, torch.uint8, self.cells, "b")
+        with dev:
+            check(lib().sqz_compact_run(self._h, _ptr(a), _ptr(b), steps, st))
+        return a if steps % 2 == 0 else b
+
+    def expanded_step(self, src, dst):
+        torch, dev, st = self._ctx()
+        self._need(src.view(-1), torch.uint8, self.n * self.n, "src")
+        self._need(dst.view(-1), torch.uint8, self.n * self.n, "dst")
+        with dev:
+            check(lib().sqz_expanded_step(self._h, _ptr(src), _ptr(dst), st))
+        return dst

@@ -1,0 +1,80 @@
+"""ctypes loader for libsqueeze.so (in-tree build).  Fails loudly when missing."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsqueeze.so")
+
+# sqz_status codes (include/squeeze.h)
+OK, ERR_INVALID, ERR_RANGE, ERR_NOMEM, ERR_HIP, ERR_UNSUPPORTED = range(6)
+HOLE = (1 << 64) - 1
+LAYOUT_COMPACT, LAYOUT_EXPANDED = 0, 1
+IMPL_AUTO, IMPL_CELL, IMPL_TILE = 0, 1, 2
+
+
+class SqueezeError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"[{status}] {message}")
+        self.status = status
+
+
+class Info(ctypes.Structure):
+    _fields_ = [
+        ("s", ctypes.c_int32), ("k", ctypes.c_int32), ("r", ctypes.c_int32),
+        ("tile_level", ctypes.c_int32), ("n", ctypes.c_int64), ("cells", ctypes.c_uint64),
+        ("compact_w", ctypes.c_uint64), ("compact_h", ctypes.c_uint64),
+        ("has_tile", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+# name -> (restype, argtypes); must match include/squeeze.h
+SIGNATURES = {
+    "sqz_descriptor_check": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
+                                            ctypes.POINTER(Info)]),
+    "sqz_fractal_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_void_p)]),
+    "sqz_fractal_destroy": (None, [ctypes.c_void_p]),
+    "sqz_fractal_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Info)]),
+    "sqz_lambda_map": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                      ctypes.c_void_p]),
+    "sqz_nu_map": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                  ctypes.c_void_p]),
+    "sqz_fill_bernoulli": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_double, ctypes.c_int,
+                                          ctypes.c_void_p, ctypes.c_void_p]),
+    "sqz_fill_uniform": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]),
+    "sqz_compact_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "sqz_compact_step_impl": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_void_p]),
+    "sqz_compact_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                       ctypes.c_void_p]),
+    "sqz_expanded_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "sqz_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "sqz_last_error": (ctypes.c_char_p, []),
+}
+
+
+def lib() -> ctypes.CDLL:
+    """Load libsqueeze.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "
+                "(there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status: int) -> None:
+    if status != OK:
+        msg = lib().sqz_last_error().decode(errors="replace")
+        raise SqueezeError(status, msg)

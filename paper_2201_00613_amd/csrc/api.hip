@@ -1,0 +1,440 @@
+// Host side of libsqueeze: descriptor validation, map-table construction,
+// handle management and argument checking for every entry point.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "common.h"
+
+struct sqz_fractal {
+    sqz::FractalHost h;
+    size_t device_mem;  // total memory of the device the handle lives on
+};
+
+namespace sqz {
+
+static thread_local char g_err[512];
+
+sqz_status set_error(sqz_status st, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+sqz_status hip_error(hipError_t e, const char *what)
+{
+    return set_error(SQZ_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+Div32 make_div32(uint32_t d)
+{
+    Div32 D;
+    D.d = d;
+    uint32_t l = 0;
+    while (l < 32 && (1ull << l) < d) ++l;
+    D.m = (uint32_t)((((unsigned __int128)1 << 32) * (((unsigned __int128)1 << l) - d)) / d + 1);
+    D.sh1 = l < 1 ? l : 1;
+    D.sh2 = l > 0 ? l - 1 : 0;
+    return D;
+}
+
+Div64 make_div64(uint64_t d)
+{
+    Div64 D;
+    D.d = d;
+    uint32_t l = 0;
+    while (l < 64 && ((unsigned __int128)1 << l) < d) ++l;
+    D.m = (uint64_t)((((unsigned __int128)1 << 64) * (((unsigned __int128)1 << l) - d)) / d + 1);
+    D.sh1 = l < 1 ? l : 1;
+    D.sh2 = l > 0 ? l - 1 : 0;
+    return D;
+}
+
+static uint64_t upow(uint64_t b, int e)
+{
+    uint64_t p = 1;
+    while (e-- > 0) p *= b;
+    return p;
+}
+
+// Chunk sizes of the map tables: at most 4096 entries per table, lambda
+// offsets packed in 16 bits per axis, nu chunk values below 2^31.
+static int lam_chunk(int s, int k)
+{
+    int c = 1;
+    while (c < 24 && upow(k, c + 1) <= 4096 && upow(s, c + 1) <= 65536) ++c;
+    return c;
+}
+static int nu_chunk(int s, int k)
+{
+    int c = 1;
+    while (c < 24 && upow(s, 2 * (c + 1)) <= 4096 && upow(k, c + 1) < (1ull << 31)) ++c;
+    return c;
+}
+
+sqz_status build_map_params(const FractalHost &F, int level, MapParams &P, void **d_mem)
+{
+    const int s = F.s, k = F.k;
+    memset(&P, 0, sizeof P);
+    P.s = s;
+    P.k = k;
+    P.r = level;
+    P.n = (int32_t)upow(s, level);
+    P.N = upow(k, level);
+    const int CL = lam_chunk(s, k), CN = nu_chunk(s, k);
+    P.nlam = level == 0 ? 0 : (level + CL - 1) / CL;
+    P.nnu = level == 0 ? 0 : (level + CN - 1) / CN;
+    const int TL = level == 0 ? 0 : level - CL * (P.nlam - 1);
+    const int TN = level == 0 ? 0 : level - CN * (P.nnu - 1);
+    P.klam = (uint32_t)upow(k, CL);
+    P.slam = (uint32_t)upow(s, CL);
+    P.snu = (uint32_t)upow(s, CN);
+    P.snu_top = (uint32_t)upow(s, TN);
+    P.knu = upow(k, CN);
+    P.dklam64 = make_div64(P.klam);
+    P.dklam32 = make_div32(P.klam);
+    P.dsnu = make_div32(P.snu);
+
+    // lambda tables: digit chunk -> packed (x | y << 16)
+    auto lam_table = [&](int levels, std::vector<uint32_t> &t) {
+        uint64_t cnt = upow(k, levels);
+        t.resize(cnt);
+        for (uint64_t d = 0; d < cnt; ++d) {
+            uint64_t v = d, sp = 1, x = 0, y = 0;
+            for (int i = 0; i < levels; ++i) {
+                int beta = (int)(v % k);
+                v /= k;
+                x += F.ox[beta] * sp;
+                y += F.oy[beta] * sp;
+                sp *= s;
+            }
+            t[d] = (uint32_t)(x | (y << 16));
+        }
+    };
+    // nu tables: (xc + side*yc) -> base-k replica digits, or hole
+    auto nu_table = [&](int levels, std::vector<uint32_t> &t) {
+        uint64_t side = upow(s, levels);
+        t.resize(side * side);
+        for (uint64_t yc = 0; yc < side; ++yc)
+            for (uint64_t xc = 0; xc < side; ++xc) {
+                uint64_t v = 0, kp = 1, sx = xc, sy = yc;
+                bool hole = false;
+                for (int i = 0; i < levels; ++i) {
+                    int j = F.hnu[(sx % s) + s * (sy % s)];
+                    sx /= s;
+                    sy /= s;
+                    if (j < 0) {
+                        hole = true;
+                        break;
+                    }
+                    v += (uint64_t)j * kp;
+                    kp *= k;
+                }
+                t[xc + side * yc] = hole ? kNuHole32 : (uint32_t)v;
+            }
+    };
+    std::vector<uint32_t> lam_lo, lam_top, nu_lo, nu_top;
+    if (level > 0) {
+        lam_table(CL, lam_lo);
+        lam_table(TL, lam_top);
+        nu_table(CN, nu_lo);
+        nu_table(TN, nu_top);
+    } else {
+        lam_lo.assign(1, 0);
+        lam_top.assign(1, 0);
+        nu_lo.assign(1, 0);
+        nu_top.assign(1, 0);
+    }
+    size_t total = lam_lo.size() + lam_top.size() + nu_lo.size() + nu_top.size();
+    std::vector<uint32_t> all;
+    all.reserve(total);
+    all.insert(all.end(), lam_lo.begin(), lam_lo.end());
+    all.insert(all.end(), lam_top.begin(), lam_top.end());
+    all.insert(all.end(), nu_lo.begin(), nu_lo.end());
+    all.insert(all.end(), nu_top.begin(), nu_top.end());
+    void *mem = nullptr;
+    hipError_t e = hipMalloc(&mem, total * sizeof(uint32_t));
+    if (e != hipSuccess) return set_error(SQZ_ERR_NOMEM, "hipMalloc of map tables: %s", hipGetErrorString(e));
+    e = hipMemcpy(mem, all.data(), total * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(mem);
+        return hip_error(e, "hipMemcpy of map tables");
+    }
+    const uint32_t *base = (const uint32_t *)mem;
+    P.lam_lo = base;
+    P.lam_top = P.lam_lo + lam_lo.size();
+    P.nu_lo = P.lam_top + lam_top.size();
+    P.nu_top = P.nu_lo + nu_lo.size();
+    *d_mem = mem;
+    return SQZ_OK;
+}
+
+}  // namespace sqz
+
+using namespace sqz;
+
+static sqz_status check_descriptor(int32_t s, int32_t k, const int32_t *offs, int32_t r, FractalHost *F)
+{
+    if (s < 2 || s > kMaxS) return set_error(SQZ_ERR_INVALID, "s=%d outside [2, %d]", s, kMaxS);
+    if (k < 1 || k > s * s) return set_error(SQZ_ERR_INVALID, "k=%d outside [1, s*s=%d]", k, s * s);
+    if (!offs) return set_error(SQZ_ERR_INVALID, "offsets_xy is NULL");
+    if (r < 0) return set_error(SQZ_ERR_INVALID, "r=%d is negative", r);
+    int seen[kMaxS * kMaxS];
+    for (int i = 0; i < s * s; ++i) seen[i] = -1;
+    for (int j = 0; j < k; ++j) {
+        int x = offs[2 * j], y = offs[2 * j + 1];
+        if (x < 0 || x >= s || y < 0 || y >= s)
+            return set_error(SQZ_ERR_INVALID, "replica %d offset (%d,%d) outside [0,%d)^2", j, x, y, s);
+        if (seen[x + s * y] >= 0)
+            return set_error(SQZ_ERR_INVALID, "replicas %d and %d share offset (%d,%d)", seen[x + s * y], j, x, y);
+        seen[x + s * y] = j;
+    }
+    // n = s^r < 2^31, N = k^r < 2^62
+    uint64_t n = 1, N = 1;
+    for (int i = 0; i < r; ++i) {
+        n *= (uint64_t)s;
+        if (n >= (1ull << 31)) return set_error(SQZ_ERR_RANGE, "n = %d^%d does not fit in 31 bits", s, r);
+        N *= (uint64_t)k;
+        if (N >= (1ull << 62)) return set_error(SQZ_ERR_RANGE, "N = %d^%d does not fit in 62 bits", k, r);
+    }
+    if (F) {
+        memset(F, 0, sizeof *F);
+        F->s = s;
+        F->k = k;
+        F->r = r;
+        F->n = (int64_t)n;
+        F->N = N;
+        for (int j = 0; j < k; ++j) {
+            F->ox[j] = offs[2 * j];
+            F->oy[j] = offs[2 * j + 1];
+        }
+        for (int i = 0; i < s * s; ++i) F->hnu[i] = seen[i];
+    }
+    return SQZ_OK;
+}
+
+static void fill_info(const FractalHost &F, sqz_info *out)
+{
+    memset(out, 0, sizeof *out);
+    out->s = F.s;
+    out->k = F.k;
+    out->r = F.r;
+    out->n = F.n;
+    out->cells = F.N;
+    out->compact_w = upow(F.k, (F.r + 1) / 2);
+    out->compact_h = upow(F.k, F.r / 2);
+}
+
+extern "C" {
+
+sqz_status sqz_descriptor_check(int32_t s, int32_t k, const int32_t *offsets_xy, int32_t r, sqz_info *out)
+{
+    FractalHost *F = new (std::nothrow) FractalHost;
+    if (!F) return set_error(SQZ_ERR_NOMEM, "host allocation failed");
+    sqz_status st = check_descriptor(s, k, offsets_xy, r, F);
+    if (st == SQZ_OK && out) fill_info(*F, out);
+    delete F;
+    return st;
+}
+
+sqz_status sqz_fractal_create(int32_t s, int32_t k, const int32_t *offsets_xy, int32_t r, sqz_fractal **out)
+{
+    if (!out) return set_error(SQZ_ERR_INVALID, "out is NULL");
+    sqz_fractal *f = new (std::nothrow) sqz_fractal;
+    if (!f) return set_error(SQZ_ERR_NOMEM, "host allocation failed");
+    sqz_status st = check_descriptor(s, k, offsets_xy, r, &f->h);
+    if (st != SQZ_OK) {
+        delete f;
+        return st;
+    }
+    hipError_t e = hipGetDevice(&f->h.device);
+    if (e != hipSuccess) {
+        delete f;
+        return hip_error(e, "hipGetDevice");
+    }
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, f->h.device);
+    if (e != hipSuccess) {
+        delete f;
+        return hip_error(e, "hipGetDeviceProperties");
+    }
+    f->device_mem = prop.totalGlobalMem;
+    st = build_map_params(f->h, r, f->h.P, &f->h.d_tables);
+    if (st != SQZ_OK) {
+        delete f;
+        return st;
+    }
+    f->h.tile_kind = tile_kind_for(f->h);
+    f->h.tile = nullptr;
+    if (f->h.tile_kind) {
+        st = tile_prepare(f->h);
+        if (st != SQZ_OK) {
+            (void)hipFree(f->h.d_tables);
+            delete f;
+            return st;
+        }
+    }
+    *out = f;
+    return SQZ_OK;
+}
+
+void sqz_fractal_destroy(sqz_fractal *f)
+{
+    if (!f) return;
+    tile_release(f->h);
+    if (f->h.d_tables) (void)hipFree(f->h.d_tables);
+    delete f;
+}
+
+sqz_status sqz_fractal_info(const sqz_fractal *f, sqz_info *out)
+{
+    if (!f || !out) return set_error(SQZ_ERR_INVALID, "NULL argument");
+    fill_info(f->h, out);
+    out->has_tile = f->h.tile_kind != 0;
+    out->tile_level = tile_level_of(f->h);
+    return SQZ_OK;
+}
+
+static sqz_status check_handle(const sqz_fractal *f)
+{
+    if (!f) return set_error(SQZ_ERR_INVALID, "fractal handle is NULL");
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_error(e, "hipGetDevice");
+    if (dev != f->h.device)
+        return set_error(SQZ_ERR_INVALID, "current device %d is not the handle's device %d", dev, f->h.device);
+    return SQZ_OK;
+}
+
+sqz_status sqz_lambda_map(const sqz_fractal *f, const uint64_t *d_idx, int64_t count, int32_t *d_xy, void *stream)
+{
+    sqz_status st = check_handle(f);
+    if (st != SQZ_OK) return st;
+    if (count < 0) return set_error(SQZ_ERR_INVALID, "count < 0");
+    if (count == 0) return SQZ_OK;
+    if (!d_idx || !d_xy) return set_error(SQZ_ERR_INVALID, "NULL buffer");
+    return launch_lambda(f->h.P, d_idx, count, d_xy, (hipStream_t)stream);
+}
+
+sqz_status sqz_nu_map(const sqz_fractal *f, const int32_t *d_xy, int64_t count, uint64_t *d_idx, void *stream)
+{
+    sqz_status st = check_handle(f);
+    if (st != SQZ_OK) return st;
+    if (count < 0) return set_error(SQZ_ERR_INVALID, "count < 0");
+    if (count == 0) return SQZ_OK;
+    if (!d_idx || !d_xy) return set_error(SQZ_ERR_INVALID, "NULL buffer");
+    return launch_nu(f->h.P, d_xy, count, d_idx, (hipStream_t)stream);
+}
+
+sqz_status sqz_fill_bernoulli(const sqz_fractal *f, uint64_t seed, double p, sqz_layout layout, uint8_t *d_state,
+                              void *stream)
+{
+    sqz_status st = check_handle(f);
+    if (st != SQZ_OK) return st;
+    if (!d_state) return set_error(SQZ_ERR_INVALID, "d_state is NULL");
+    if (!(p >= 0.0 && p <= 1.0)) return set_error(SQZ_ERR_INVALID, "p=%g outside [0,1]", p);
+    if (layout != SQZ_LAYOUT_COMPACT && layout != SQZ_LAYOUT_EXPANDED)
+        return set_error(SQZ_ERR_INVALID, "unknown layout %d", (int)layout);
+    if (layout == SQZ_LAYOUT_EXPANDED && (uint64_t)f->h.n * (uint64_t)f->h.n > f->device_mem)
+        return set_error(SQZ_ERR_RANGE, "expanded grid of %lld^2 bytes exceeds device memory", (long long)f->h.n);
+    uint32_t thresh = (uint32_t)floor(p * 16777216.0);
+    return launch_fill_bernoulli(f->h.P, seed, thresh, layout == SQZ_LAYOUT_EXPANDED, d_state, (hipStream_t)stream);
+}
+
+sqz_status sqz_fill_uniform(const sqz_fractal *f, uint64_t seed, float *d_u, void *stream)
+{
+    sqz_status st = check_handle(f);
+    if (st != SQZ_OK) return st;
+    if (!d_u) return set_error(SQZ_ERR_INVALID, "d_u is NULL");
+    return launch_fill_uniform(f->h.P, seed, d_u, (hipStream_t)stream);
+}
+
+static bool overlap(const void *a, const void *b, uint64_t bytes)
+{
+    uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + bytes && y < x + bytes;
+}
+
+sqz_status sqz_compact_step_impl(const sqz_fractal *f, sqz_impl impl, const uint8_t *d_in, uint8_t *d_out,
+                                 void *stream)
+{
+    sqz_status st = check_handle(f);
+    if (st != SQZ_OK) return st;
+    if (!d_in || !d_out) return set_error(SQZ_ERR_INVALID, "NULL buffer");
+    if (overlap(d_in, d_out, f->h.N)) return set_error(SQZ_ERR_INVALID, "d_in and d_out overlap");
+    hipStream_t s = (hipStream_t)stream;
+    switch (impl) {
+    case SQZ_IMPL_AUTO:
+        // the tiled kernel moves 16-byte words; unaligned buffers take the thread-level path
+        if (f->h.tile_kind && !(((uintptr_t)d_in | (uintptr_t)d_out) & 15)) return launch_life_tile(f->h, d_in, d_out, s);
+        return launch_life_cell(f->h.P, d_in, d_out, s);
+    case SQZ_IMPL_CELL:
+        return launch_life_cell(f->h.P, d_in, d_out, s);
+    case SQZ_IMPL_TILE:
+        if (!f->h.tile_kind)
+            return set_error(SQZ_ERR_UNSUPPORTED, "no tiled kernel for this replica pattern and level");
+        return launch_life_tile(f->h, d_in, d_out, s);
+    }
+    return set_error(SQZ_ERR_INVALID, "unknown implementation %d", (int)impl);
+}
+
+sqz_status sqz_compact_step(const sqz_fractal *f, const uint8_t *d_in, uint8_t *d_out, void *stream)
+{
+    return sqz_compact_step_impl(f, SQZ_IMPL_AUTO, d_in, d_out, stream);
+}
+
+sqz_status sqz_compact_run(const sqz_fractal *f, uint8_t *d_a, uint8_t *d_b, int32_t steps, void *stream)
+{
+    sqz_status st = check_handle(f);
+    if (st != SQZ_OK) return st;
+    if (steps < 0) return set_error(SQZ_ERR_INVALID, "steps < 0");
+    if (!d_a || !d_b) return set_error(SQZ_ERR_INVALID, "NULL buffer");
+    if (overlap(d_a, d_b, f->h.N)) return set_error(SQZ_ERR_INVALID, "d_a and d_b overlap");
+    for (int32_t i = 0; i < steps; ++i) {
+        const uint8_t *in = (i & 1) ? d_b : d_a;
+        uint8_t *out = (i & 1) ? d_a : d_b;
+        st = sqz_compact_step_impl(f, SQZ_IMPL_AUTO, in, out, stream);
+        if (st != SQZ_OK) return st;
+    }
+    return SQZ_OK;
+}
+
+sqz_status sqz_expanded_step(const sqz_fractal *f, const uint8_t *d_in, uint8_t *d_out, void *stream)
+{
+    sqz_status st = check_handle(f);
+    if (st != SQZ_OK) return st;
+    uint64_t n = (uint64_t)f->h.n;
+    if (2 * n * n > f->device_mem)
+        return set_error(SQZ_ERR_RANGE, "two expanded grids of %llu^2 bytes exceed the device's %zu bytes",
+                         (unsigned long long)n, f->device_mem);
+    if (!d_in || !d_out) return set_error(SQZ_ERR_INVALID, "NULL buffer");
+    if (overlap(d_in, d_out, n * n)) return set_error(SQZ_ERR_INVALID, "d_in and d_out overlap");
+    return launch_life_bb(f->h, d_in, d_out, (hipStream_t)stream);
+}
+
+const char *sqz_status_string(sqz_status st)
+{
+    switch (st) {
+    case SQZ_OK: return "ok";
+    case SQZ_ERR_INVALID: return "invalid argument";
+    case SQZ_ERR_RANGE: return "size out of range";
+    case SQZ_ERR_NOMEM: return "out of memory";
+    case SQZ_ERR_HIP: return "HIP runtime error";
+    case SQZ_ERR_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char *sqz_last_error(void) { return g_err; }
+
+}  // extern "C"

@@ -1,0 +1,202 @@
+// Internal declarations shared by the HIP sources of libsqueeze.
+//
+// Compact storage is one byte (or one float) per fractal cell, in the
+// replica-major order: compact index c has base-k digits beta_1..beta_r
+// (beta_mu = digit mu-1, least significant first) and lives at expanded
+// coordinate lambda(c) = sum_mu tau(beta_mu) * s^(mu-1) (Section
+// "Revisiting lambda").  Every level-m subtree is therefore a contiguous
+// range [t*k^m, (t+1)*k^m) of the compact array.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "squeeze.h"
+
+namespace sqz {
+
+constexpr uint32_t kNuHole32 = 0xFFFFFFFFu;
+constexpr uint64_t kHole64 = ~0ull;
+constexpr int kMaxS = 16;
+constexpr int kMaxK = 256;
+
+// ---------------------------------------------------------------------------
+// Division by a run-time invariant integer (Granlund & Montgomery, "Division
+// by invariant integers using multiplication", PLDI 1994, unsigned case):
+// with l = ceil(log2 d) and m = floor(2^W (2^l - d) / d) + 1,
+// q = (t + ((n - t) >> min(l,1))) >> max(l-1,0), t = mulhi(m, n), exact for
+// every W-bit n.
+// ---------------------------------------------------------------------------
+struct Div32 {
+    uint32_t d, m, sh1, sh2;
+};
+struct Div64 {
+    uint64_t d, m;
+    uint32_t sh1, sh2;
+};
+
+Div32 make_div32(uint32_t d);
+Div64 make_div64(uint64_t d);
+
+__device__ __forceinline__ uint32_t divq(uint32_t n, const Div32 &D)
+{
+    uint32_t t = __umulhi(D.m, n);
+    return (t + ((n - t) >> D.sh1)) >> D.sh2;
+}
+__device__ __forceinline__ uint64_t divq(uint64_t n, const Div64 &D)
+{
+    uint64_t t = __umul64hi(D.m, n);
+    return (t + ((n - t) >> D.sh1)) >> D.sh2;
+}
+
+// ---------------------------------------------------------------------------
+// Chunked look-up tables for the two maps.
+//
+// lambda: a chunk of CL base-k digits d (value < k^CL) maps to the packed
+//   offset (x | y << 16) = sum over the chunk's levels of tau(digit) s^level.
+// nu: a chunk of CN base-s digit pairs (xc, yc), both < s^CN, maps to the
+//   chunk's replica digits read as a base-k number, or kNuHole32 when any
+//   level's digit pair is not a replica offset (explicit hole test; the
+//   paper's arithmetic hash has no hole value).
+// The top chunk of each map covers the remaining r - CL*(chunks-1) levels
+// and has its own table, so digits above level r never contribute.
+// ---------------------------------------------------------------------------
+struct MapParams {
+    int32_t s, k, r, n;       // n = s^r < 2^31
+    uint64_t N;               // k^r
+    int32_t nlam, nnu;        // number of chunks (0 when r == 0)
+    uint32_t klam, slam;      // k^CL, s^CL
+    uint32_t snu, snu_top;    // s^CN, s^(top nu chunk levels)
+    uint64_t knu;             // k^CN
+    Div64 dklam64;
+    Div32 dklam32;
+    Div32 dsnu;
+    const uint32_t *lam_lo, *lam_top, *nu_lo, *nu_top;
+};
+
+// lambda(c) for c < N (Section "Revisiting lambda"); 32-bit index variant
+// for N <= 2^32, 64-bit otherwise.
+__device__ __forceinline__ void lam_map32(const MapParams &P, uint32_t c, uint32_t &x, uint32_t &y)
+{
+    uint32_t px = 0, py = 0, sp = 1;
+    for (int i = 0; i + 1 < P.nlam; ++i) {
+        uint32_t q = divq(c, P.dklam32);
+        uint32_t e = P.lam_lo[c - q * P.klam];
+        c = q;
+        px += (e & 0xFFFFu) * sp;
+        py += (e >> 16) * sp;
+        sp *= P.slam;
+    }
+    if (P.nlam > 0) {
+        uint32_t e = P.lam_top[c];
+        px += (e & 0xFFFFu) * sp;
+        py += (e >> 16) * sp;
+    }
+    x = px;
+    y = py;
+}
+
+__device__ __forceinline__ void lam_map64(const MapParams &P, uint64_t c, uint32_t &x, uint32_t &y)
+{
+    uint32_t px = 0, py = 0, sp = 1;
+    for (int i = 0; i + 1 < P.nlam; ++i) {
+        uint64_t q = divq(c, P.dklam64);
+        uint32_t e = P.lam_lo[(uint32_t)(c - q * P.klam)];
+        c = q;
+        px += (e & 0xFFFFu) * sp;
+        py += (e >> 16) * sp;
+        sp *= P.slam;
+    }
+    if (P.nlam > 0) {
+        uint32_t e = P.lam_top[(uint32_t)c];
+        px += (e & 0xFFFFu) * sp;
+        py += (e >> 16) * sp;
+    }
+    x = px;
+    y = py;
+}
+
+// nu(x, y) (Section "Formulation of nu"), scanning chunks from the least
+// significant level up; kHole64 for holes and for points outside [0,n)^2.
+__device__ __forceinline__ uint64_t nu_map(const MapParams &P, int32_t x, int32_t y)
+{
+    if ((uint32_t)x >= (uint32_t)P.n || (uint32_t)y >= (uint32_t)P.n) return kHole64;
+    uint32_t ux = (uint32_t)x, uy = (uint32_t)y;
+    uint64_t c = 0, kp = 1;
+    for (int i = 0; i + 1 < P.nnu; ++i) {
+        uint32_t qx = divq(ux, P.dsnu), qy = divq(uy, P.dsnu);
+        uint32_t e = P.nu_lo[(ux - qx * P.snu) + P.snu * (uy - qy * P.snu)];
+        if (e == kNuHole32) return kHole64;
+        c += (uint64_t)e * kp;
+        kp *= P.knu;
+        ux = qx;
+        uy = qy;
+    }
+    if (P.nnu > 0) {
+        uint32_t e = P.nu_top[ux + P.snu_top * uy];
+        if (e == kNuHole32) return kHole64;
+        c += (uint64_t)e * kp;
+    }
+    return c;
+}
+
+// ---------------------------------------------------------------------------
+// Seeded starts.  SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): output i+1
+// of the generator seeded with `seed` is the MurmurHash3 variant-13
+// finaliser applied to seed + (i+1) * 0x9E3779B97F4A7C15.  Cells are keyed
+// by their expanded coordinate, i = y*n + x, so compact and expanded
+// layouts start from identical states.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t i)
+{
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// ---------------------------------------------------------------------------
+// Host-side fractal handle.
+// ---------------------------------------------------------------------------
+struct TileConfig;  // defined in life_tile.hip
+
+struct FractalHost {
+    int32_t s, k, r;
+    int64_t n;
+    uint64_t N;
+    int32_t ox[kMaxK], oy[kMaxK];
+    int32_t hnu[kMaxS * kMaxS];  // replica index of digit pair (x + s*y), -1 if none
+    int device;
+    MapParams P;                  // maps at level r
+    void *d_tables;               // device memory holding the chunk tables
+    // tiled stencil (patterns with a specialised kernel), built on demand
+    int tile_kind;                // 0 = none
+    TileConfig *tile;
+};
+
+// Host helpers (api.cpp)
+sqz_status set_error(sqz_status st, const char *fmt, ...);
+sqz_status hip_error(hipError_t e, const char *what);
+sqz_status build_map_params(const FractalHost &F, int level, MapParams &P, void **d_mem);
+
+// Kernel launchers (maps.hip)
+sqz_status launch_lambda(const MapParams &P, const uint64_t *idx, int64_t count, int32_t *xy,
+                         hipStream_t st);
+sqz_status launch_nu(const MapParams &P, const int32_t *xy, int64_t count, uint64_t *idx,
+                     hipStream_t st);
+sqz_status launch_fill_bernoulli(const MapParams &P, uint64_t seed, uint32_t thresh24, int expanded,
+                                 uint8_t *out, hipStream_t st);
+sqz_status launch_fill_uniform(const MapParams &P, uint64_t seed, float *out, hipStream_t st);
+sqz_status launch_life_cell(const MapParams &P, const uint8_t *in, uint8_t *out, hipStream_t st);
+
+// Expanded bounding-box baseline (bb.hip)
+sqz_status launch_life_bb(const FractalHost &F, const uint8_t *in, uint8_t *out, hipStream_t st);
+
+// Tiled compact stencil (life_tile.hip)
+int tile_kind_for(const FractalHost &F);
+sqz_status tile_prepare(FractalHost &F);
+void tile_release(FractalHost &F);
+int32_t tile_level_of(const FractalHost &F);
+sqz_status launch_life_tile(const FractalHost &F, const uint8_t *in, uint8_t *out, hipStream_t st);
+
+}  // namespace sqz

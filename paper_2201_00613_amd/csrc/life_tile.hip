@@ -1,0 +1,633 @@
+// Block-level Squeeze (Section "Moving from Thread-level to Block-level")
+// for Life on compact storage, bit-sliced.
+//
+// Work decomposition
+//   tile  = a level-M subtree: the contiguous compact range [t K^M, (t+1) K^M).
+//           One workgroup per tile.  The coarse maps (lambda/nu at level r-M)
+//           are evaluated once per tile, ahead of time, to find the few cells of
+//           neighbouring tiles that touch it ("tile halo").
+//   block = a level-J subtree of K^J <= 32 cells, held as one 32-bit word
+//           (bit i = state of the block's cell i).  One lane per block.
+// Inside a tile nothing is mapped per cell: the neighbours of a block's cells
+// are either cells of the same block -- a fixed set of (bit shift, bit mask)
+// moves derived from the replica pattern at compile time -- or one of a fixed
+// set of "block halo" cells of the adjacent blocks, found through a table that
+// is the same for every tile (the micro brute force the paper applies inside a
+// block).  Neighbour counts are summed with bit-sliced full adders over up to
+// eight single-bit layers, then B3/S23 is applied to all cells of the block
+// with a few logic operations.
+//
+// Memory path per tile: coalesced 16-byte loads of the tile's bytes, packed to
+// bits in LDS (pack: (d * 0x10204080) >> 28 gathers bit 0 of four bytes);
+// results are OR-ed into an LDS bit array and written back with coalesced
+// 16-byte stores (unpack: (v * 0x204081) & 0x01010101 spreads four bits).  The
+// tile boundaries are not 16-byte aligned: edge words are stored byte by byte
+// so neighbouring tiles never overwrite each other.
+#include <utility>
+#include <vector>
+
+#include "common.h"
+
+namespace sqz {
+
+// ---------------------------------------------------------------------------
+// Replica patterns with a tiled kernel.  Replica j is at (OX[j], OY[j]).
+// ---------------------------------------------------------------------------
+struct PatTriangle {  // Sierpinski triangle, member iff x & y == 0
+    static constexpr int S = 2, K = 3, J = 3, MMAX = 8;
+    static constexpr int OX[3] = {0, 1, 0};
+    static constexpr int OY[3] = {0, 0, 1};
+};
+struct PatTrianglePaper {  // the paper's orientation: top, middle, right
+    static constexpr int S = 2, K = 3, J = 3, MMAX = 8;
+    static constexpr int OX[3] = {0, 0, 1};
+    static constexpr int OY[3] = {0, 1, 1};
+};
+struct PatVicsek {  // Vicsek cross
+    static constexpr int S = 3, K = 5, J = 2, MMAX = 6;
+    static constexpr int OX[5] = {1, 0, 1, 2, 1};
+    static constexpr int OY[5] = {0, 1, 1, 1, 2};
+};
+
+constexpr int cpow(int b, int e)
+{
+    int p = 1;
+    for (int i = 0; i < e; ++i) p *= b;
+    return p;
+}
+
+constexpr int kMaxHalo = 16;      // halo cells per block
+constexpr int kMaxTileHalo = 24;  // halo cells per tile
+constexpr int kBlock = 256;
+
+// ---------------------------------------------------------------------------
+// Compile-time plan of one block's neighbourhood.
+// ---------------------------------------------------------------------------
+struct BlockPlan {
+    int nc, box;
+    int lx[32], ly[32];              // local lambda of the block's cells
+    int nlayer;                      // single-bit layers summed per cell
+    int nterm;                       // in-block moves: L[layer] |= shift(x) & mask
+    int t_layer[128], t_shift[128];  // shift > 0: source bit above target (x >> shift)
+    uint32_t t_mask[128];
+    int nhalo;                       // distinct halo cells (block direction, cell)
+    int h_dx[kMaxHalo], h_dy[kMaxHalo], h_idx[kMaxHalo];
+    int nhterm;                      // L[layer] |= halo_bit[slot] << bit
+    int ht_layer[64], ht_slot[64], ht_bit[64];
+    bool ok;
+};
+
+template <class Pat>
+constexpr int local_nu(int x, int y)
+{
+    int c = 0;
+    for (int mu = Pat::J; mu >= 1; --mu) {
+        const int sc = cpow(Pat::S, mu - 1);
+        const int qx = (x / sc) % Pat::S, qy = (y / sc) % Pat::S;
+        int j = -1;
+        for (int i = 0; i < Pat::K; ++i)
+            if (Pat::OX[i] == qx && Pat::OY[i] == qy) j = i;
+        if (j < 0) return -1;
+        c += j * cpow(Pat::K, mu - 1);
+    }
+    return c;
+}
+
+template <class Pat>
+constexpr BlockPlan derive_plan()
+{
+    BlockPlan p{};
+    p.ok = true;
+    p.nc = cpow(Pat::K, Pat::J);
+    p.box = cpow(Pat::S, Pat::J);
+    if (p.nc > 32) {
+        p.ok = false;
+        return p;
+    }
+    for (int i = 0; i < p.nc; ++i) {
+        int v = i, x = 0, y = 0, sp = 1;
+        for (int mu = 1; mu <= Pat::J; ++mu) {
+            const int b = v % Pat::K;
+            v /= Pat::K;
+            x += Pat::OX[b] * sp;
+            y += Pat::OY[b] * sp;
+            sp *= Pat::S;
+        }
+        p.lx[i] = x;
+        p.ly[i] = y;
+    }
+    for (int i = 0; i < p.nc; ++i) {
+        bool used[8] = {};
+        int nused = 0;
+        int halo_slots[8] = {};
+        int nh = 0;
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                if (!dx && !dy) continue;
+                const int qx = p.lx[i] + dx, qy = p.ly[i] + dy;
+                if (qx >= 0 && qy >= 0 && qx < p.box && qy < p.box) {
+                    const int j = local_nu<Pat>(qx, qy);
+                    if (j < 0) continue;
+                    const int shift = j - i;  // source bit j -> target bit i
+                    int layer = -1;
+                    for (int t = 0; t < p.nterm && layer < 0; ++t)
+                        if (p.t_shift[t] == shift && !used[p.t_layer[t]]) {
+                            layer = p.t_layer[t];
+                            p.t_mask[t] |= 1u << i;
+                        }
+                    if (layer < 0) {
+                        for (int l = 0; l < 8 && layer < 0; ++l)
+                            if (!used[l]) layer = l;
+                        p.t_layer[p.nterm] = layer;
+                        p.t_shift[p.nterm] = shift;
+                        p.t_mask[p.nterm] = 1u << i;
+                        ++p.nterm;
+                    }
+                    used[layer] = true;
+                    ++nused;
+                } else {
+                    const int bdx = qx < 0 ? -1 : (qx >= p.box ? 1 : 0);
+                    const int bdy = qy < 0 ? -1 : (qy >= p.box ? 1 : 0);
+                    const int j = local_nu<Pat>(qx - bdx * p.box, qy - bdy * p.box);
+                    if (j < 0) continue;
+                    int slot = -1;
+                    for (int h = 0; h < p.nhalo; ++h)
+                        if (p.h_dx[h] == bdx && p.h_dy[h] == bdy && p.h_idx[h] == j) slot = h;
+                    if (slot < 0) {
+                        if (p.nhalo == kMaxHalo) {
+                            p.ok = false;
+                            return p;
+                        }
+                        slot = p.nhalo++;
+                        p.h_dx[slot] = bdx;
+                        p.h_dy[slot] = bdy;
+                        p.h_idx[slot] = j;
+                    }
+                    halo_slots[nh++] = slot;
+                }
+            }
+        for (int h = 0; h < nh; ++h) {
+            int layer = -1;
+            for (int l = 0; l < 8 && layer < 0; ++l)
+                if (!used[l]) layer = l;
+            used[layer] = true;
+            ++nused;
+            p.ht_layer[p.nhterm] = layer;
+            p.ht_slot[p.nhterm] = halo_slots[h];
+            p.ht_bit[p.nhterm] = i;
+            ++p.nhterm;
+        }
+        if (nused > p.nlayer) p.nlayer = nused;
+    }
+    return p;
+}
+
+template <class Pat>
+struct PlanOf {
+    static constexpr BlockPlan value = derive_plan<Pat>();
+    static_assert(value.ok, "replica pattern does not fit the bit-sliced block kernel");
+};
+
+// ---------------------------------------------------------------------------
+// Per-tile configuration built on the host.
+// ---------------------------------------------------------------------------
+struct TileConfig {
+    int M;                 // tile level
+    uint32_t tile;         // K^M cells per tile
+    uint32_t nblocks;      // K^(M-J)
+    uint32_t nthalo;       // tile halo slots
+    uint32_t hstride;      // u16 entries per block in the block-halo table (multiple of 8)
+    uint32_t halo_word;    // LDS word index of the halo region
+    uint64_t ntiles;       // K^(r-M)
+    uint16_t *d_block_halo;
+    uint64_t *d_tile_halo;
+    MapParams Pc;          // maps at the coarse level r-M
+    void *d_coarse_tables;
+};
+
+struct TileArgs {
+    uint64_t ntiles, N;
+    uint32_t tile, nblocks, nthalo, hstride, halo_word;
+    const uint16_t *block_halo;
+    const uint64_t *tile_halo;
+};
+
+template <class Pat>
+struct TileLds {
+    static constexpr int TMAX = cpow(Pat::K, Pat::MMAX);
+    static constexpr int WMAX = (TMAX + 31 + 31) / 32;  // words covering o + tile bits
+    static constexpr int HALO_WORD = WMAX + 1;          // 2 words of halo bits after the data
+    static constexpr int IN_WORDS = HALO_WORD + 2;
+};
+
+__device__ __forceinline__ uint32_t pack4(uint32_t d) { return ((d & 0x01010101u) * 0x10204080u) >> 28; }
+__device__ __forceinline__ uint32_t spread4(uint32_t v) { return __umul24(v, 0x204081u) & 0x01010101u; }
+
+template <int Layer, int Shift, uint32_t Mask, int NL>
+__device__ __forceinline__ void move_term(uint32_t x, uint32_t (&L)[NL])
+{
+    if constexpr (Shift > 0)
+        L[Layer] |= (x >> Shift) & Mask;
+    else
+        L[Layer] |= (x << (-Shift)) & Mask;
+}
+
+template <class Pat, int NL, size_t... I>
+__device__ __forceinline__ void apply_moves(uint32_t x, uint32_t (&L)[NL], std::index_sequence<I...>)
+{
+    constexpr const BlockPlan &PL = PlanOf<Pat>::value;
+    (move_term<PL.t_layer[I], PL.t_shift[I], PL.t_mask[I], NL>(x, L), ...);
+}
+
+template <int Layer, int Slot, int Bit, int NL, int NH>
+__device__ __forceinline__ void halo_term(const uint32_t (&hb)[NH], uint32_t (&L)[NL])
+{
+    L[Layer] |= hb[Slot] << Bit;
+}
+
+template <class Pat, int NL, int NH, size_t... I>
+__device__ __forceinline__ void apply_halo(const uint32_t (&hb)[NH], uint32_t (&L)[NL], std::index_sequence<I...>)
+{
+    constexpr const BlockPlan &PL = PlanOf<Pat>::value;
+    (halo_term<PL.ht_layer[I], PL.ht_slot[I], PL.ht_bit[I], NL, NH>(hb, L), ...);
+}
+
+// B3/S23 on all cells of a block: alive' = (count == 3) | (alive & count == 2).
+template <int NL>
+__device__ __forceinline__ uint32_t life_rule(uint32_t x, const uint32_t (&L)[NL])
+{
+    if constexpr (NL <= 5) {
+        const uint32_t a = L[0], b = NL > 1 ? L[1] : 0u, c = NL > 2 ? L[2] : 0u;
+        const uint32_t d = NL > 3 ? L[3] : 0u, e = NL > 4 ? L[4] : 0u;
+        const uint32_t s1 = a ^ b ^ c, c1 = (a & b) | (c & (a ^ b));
+        const uint32_t s2 = s1 ^ d ^ e, c2 = (s1 & d) | (e & (s1 ^ d));
+        // count = s2 + 2 (c1 + c2): 2 or 3 iff exactly one carry
+        return (c1 ^ c2) & (s2 | x);
+    } else {
+        uint32_t b0 = 0, b1 = 0, b2 = 0;  // b2 sticks once the count reaches 4
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+            const uint32_t c0 = b0 & L[l];
+            b0 ^= L[l];
+            b2 |= b1 & c0;
+            b1 ^= c0;
+        }
+        return ~b2 & b1 & (b0 | x);
+    }
+}
+
+// XCD-aware order: workgroups are dealt round-robin to the 8 XCDs; give each
+// XCD a contiguous run of tiles so halo reads of adjacent tiles hit its L2.
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t G)
+{
+    const uint32_t q = G / 8, rem = G % 8, xcd = b % 8, pos = b / 8;
+    return xcd < rem ? xcd * (q + 1) + pos : rem * (q + 1) + (xcd - rem) * q + pos;
+}
+
+template <class Pat>
+__global__ void __launch_bounds__(kBlock) k_life_tile(TileArgs A, const uint8_t *__restrict__ in,
+                                                      uint8_t *__restrict__ out)
+{
+    using LDS = TileLds<Pat>;
+    constexpr const BlockPlan &PL = PlanOf<Pat>::value;
+    constexpr int NC = PL.nc;
+    constexpr uint32_t CELLS = NC == 32 ? 0xFFFFFFFFu : ((1u << NC) - 1u);
+    constexpr int NL = PL.nlayer;
+    constexpr int NH = PL.nhalo;
+
+    __shared__ uint32_t s_in[LDS::IN_WORDS];
+    __shared__ uint32_t s_out[LDS::WMAX];
+
+    const uint32_t tid = threadIdx.x;
+    const uint32_t G = gridDim.x;
+    for (uint64_t round = 0; round * G < A.ntiles; ++round) {
+        const uint64_t t = round * G + xcd_remap(blockIdx.x, G);
+        if (t >= A.ntiles) break;  // uniform across the workgroup
+        const uint64_t S0 = t * A.tile;  // first byte of the tile
+        const uint64_t A0 = S0 & ~31ull;
+        const uint32_t o = (uint32_t)(S0 - A0);
+        const uint32_t W = (o + A.tile + 31) / 32;
+
+        // Phase A: load and pack the tile (plus the bytes of its first and last
+        // 32-byte words that belong to the neighbouring tiles).
+        for (uint32_t w = tid; w < W; w += kBlock) {
+            const uint64_t g = A0 + 32ull * w;
+            uint32_t bits = 0;
+            if (g + 32 <= A.N) {
+                const uint4 a = *reinterpret_cast<const uint4 *>(in + g);
+                const uint4 b = *reinterpret_cast<const uint4 *>(in + g + 16);
+                bits = pack4(a.x) | pack4(a.y) << 4 | pack4(a.z) << 8 | pack4(a.w) << 12 | pack4(b.x) << 16 |
+                       pack4(b.y) << 20 | pack4(b.z) << 24 | pack4(b.w) << 28;
+            } else {
+                for (uint32_t i = 0; i < 32; ++i)
+                    if (g + i < A.N) bits |= (uint32_t)(in[g + i] & 1u) << i;
+            }
+            s_in[w] = bits;
+            s_out[w] = 0;
+        }
+        // Phase B: the tile's halo cells, one lane each, gathered by ballot.
+        if (tid < 64) {
+            uint32_t v = 0;
+            if (tid < A.nthalo) {
+                const uint64_t gi = A.tile_halo[t * A.nthalo + tid];
+                if (gi != kHole64) v = in[gi] & 1u;
+            }
+            const uint64_t m = __ballot(v);
+            if (tid == 0) {
+                const uint64_t sh = (m & 0xFFFFFFull) << o;
+                s_in[A.halo_word] = (uint32_t)sh;
+                s_in[A.halo_word + 1] = (uint32_t)(sh >> 32);
+            }
+        }
+        __syncthreads();
+
+        // Phase C: one lane per level-J block.
+        for (uint32_t b = tid; b < A.nblocks; b += kBlock) {
+            const uint32_t pos = o + b * NC;
+            const uint32_t lo = s_in[pos >> 5], hi = s_in[(pos >> 5) + 1];
+            const uint32_t x = __builtin_amdgcn_alignbit(hi, lo, pos & 31) & CELLS;
+            uint32_t hb[NH > 0 ? NH : 1] = {};
+            const uint16_t *he = A.block_halo + (size_t)b * A.hstride;
+#pragma unroll
+            for (int h0 = 0; h0 < NH; h0 += 8) {
+                const uint4 q = *reinterpret_cast<const uint4 *>(he + h0);
+                const uint32_t qq[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+                for (int h = h0; h < NH && h < h0 + 8; ++h) {
+                    const uint32_t e = ((qq[(h - h0) >> 1] >> (16 * ((h - h0) & 1))) & 0xFFFFu) + o;
+                    hb[h] = __builtin_amdgcn_ubfe(s_in[e >> 5], e, 1);  // bit e mod 32
+                }
+            }
+            uint32_t L[NL];
+#pragma unroll
+            for (int l = 0; l < NL; ++l) L[l] = 0;
+            apply_moves<Pat, NL>(x, L, std::make_index_sequence<PL.nterm>{});
+            apply_halo<Pat, NL, (NH > 0 ? NH : 1)>(hb, L, std::make_index_sequence<PL.nhterm>{});
+            const uint32_t res = life_rule<NL>(x, L) & CELLS;
+            const uint64_t sh = (uint64_t)res << (pos & 31);
+            atomicOr(&s_out[pos >> 5], (uint32_t)sh);
+            if ((uint32_t)(sh >> 32)) atomicOr(&s_out[(pos >> 5) + 1], (uint32_t)(sh >> 32));
+        }
+        __syncthreads();
+
+        // Phase D: unpack and store; edge words byte by byte.
+        for (uint32_t w = tid; w < W; w += kBlock) {
+            const uint32_t v = s_out[w];
+            const uint64_t g = A0 + 32ull * w;
+            if (32 * w >= o && 32 * w + 32 <= o + A.tile) {
+                uint4 a, b;
+                a.x = spread4(v & 15);
+                a.y = spread4((v >> 4) & 15);
+                a.z = spread4((v >> 8) & 15);
+                a.w = spread4((v >> 12) & 15);
+                b.x = spread4((v >> 16) & 15);
+                b.y = spread4((v >> 20) & 15);
+                b.z = spread4((v >> 24) & 15);
+                b.w = spread4(v >> 28);
+                *reinterpret_cast<uint4 *>(out + g) = a;
+                *reinterpret_cast<uint4 *>(out + g + 16) = b;
+            } else {
+                for (uint32_t i = 0; i < 32; ++i) {
+                    const uint32_t lp = 32 * w + i;
+                    if (lp >= o && lp < o + A.tile) out[g + i] = (uint8_t)((v >> i) & 1u);
+                }
+            }
+        }
+        __syncthreads();  // LDS is reused by the next round
+    }
+}
+
+// Tile-halo cells of every tile: global compact index of each slot's cell.
+__global__ void __launch_bounds__(kBlock) k_tile_halo(MapParams Pc, uint64_t ntiles, uint32_t nthalo,
+                                                      uint64_t tile_cells, const int4 *__restrict__ slots,
+                                                      uint64_t *__restrict__ outp)
+{
+    for (uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x; t < ntiles; t += (uint64_t)gridDim.x * kBlock) {
+        uint32_t X, Y;
+        if (Pc.N <= 0x100000000ull)
+            lam_map32(Pc, (uint32_t)t, X, Y);
+        else
+            lam_map64(Pc, t, X, Y);
+        for (uint32_t j = 0; j < nthalo; ++j) {
+            const int4 sl = slots[j];  // (tile dx, tile dy, cell index in that tile, unused)
+            const uint64_t nt = nu_map(Pc, (int32_t)X + sl.x, (int32_t)Y + sl.y);
+            outp[t * nthalo + j] = nt == kHole64 ? kHole64 : nt * tile_cells + (uint64_t)sl.z;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+namespace {
+
+template <class Pat>
+bool matches(const FractalHost &F)
+{
+    if (F.s != Pat::S || F.k != Pat::K) return false;
+    for (int j = 0; j < Pat::K; ++j)
+        if (F.ox[j] != Pat::OX[j] || F.oy[j] != Pat::OY[j]) return false;
+    return true;
+}
+
+// plain host maps of the pattern at a given level (local coordinates)
+void host_lambda(const FractalHost &F, int level, uint64_t c, int64_t &x, int64_t &y)
+{
+    int64_t px = 0, py = 0, sp = 1;
+    for (int mu = 1; mu <= level; ++mu) {
+        const int b = (int)(c % (uint64_t)F.k);
+        c /= (uint64_t)F.k;
+        px += F.ox[b] * sp;
+        py += F.oy[b] * sp;
+        sp *= F.s;
+    }
+    x = px;
+    y = py;
+}
+
+int64_t host_nu(const FractalHost &F, int level, int64_t x, int64_t y)
+{
+    int64_t side = 1;
+    for (int i = 0; i < level; ++i) side *= F.s;
+    if (x < 0 || y < 0 || x >= side || y >= side) return -1;
+    int64_t c = 0, kp = 1;
+    for (int mu = 1; mu <= level; ++mu) {
+        const int j = F.hnu[(int)(x % F.s) + F.s * (int)(y % F.s)];
+        if (j < 0) return -1;
+        c += j * kp;
+        kp *= F.k;
+        x /= F.s;
+        y /= F.s;
+    }
+    return c;
+}
+
+template <class Pat>
+sqz_status prepare(FractalHost &F)
+{
+    constexpr const BlockPlan &PL = PlanOf<Pat>::value;
+    constexpr int J = Pat::J;
+    TileConfig *T = new TileConfig();
+    T->M = F.r < Pat::MMAX ? F.r : Pat::MMAX;
+    const int M = T->M;
+    T->tile = (uint32_t)cpow(Pat::K, M);
+    T->nblocks = (uint32_t)cpow(Pat::K, M - J);
+    T->halo_word = TileLds<Pat>::HALO_WORD;
+    T->hstride = (uint32_t)((PL.nhalo + 7) / 8 * 8);
+    if (T->hstride == 0) T->hstride = 8;
+    const int64_t side = cpow(Pat::S, M);
+
+    // tile halo slots: cells of adjacent tiles that touch a cell of this tile
+    struct Slot {
+        int dx, dy;
+        int64_t idx, px, py;  // cell index in the neighbour tile; position relative to this tile
+    };
+    std::vector<Slot> slots;
+    for (uint64_t c = 0; c < T->tile; ++c) {
+        int64_t x, y;
+        host_lambda(F, M, c, x, y);
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int64_t qx = x + dx, qy = y + dy;
+                if (qx >= 0 && qy >= 0 && qx < side && qy < side) continue;
+                const int tdx = qx < 0 ? -1 : (qx >= side ? 1 : 0), tdy = qy < 0 ? -1 : (qy >= side ? 1 : 0);
+                const int64_t j = host_nu(F, M, qx - tdx * side, qy - tdy * side);
+                if (j < 0) continue;
+                bool seen = false;
+                for (const Slot &s : slots) seen |= s.px == qx && s.py == qy;
+                if (!seen) slots.push_back(Slot{tdx, tdy, j, qx, qy});
+            }
+    }
+    if (slots.size() > (size_t)kMaxTileHalo) {
+        delete T;
+        return set_error(SQZ_ERR_UNSUPPORTED, "tile halo of %zu cells exceeds %d", slots.size(), kMaxTileHalo);
+    }
+    T->nthalo = (uint32_t)slots.size();
+
+    // block halo table: for block b and halo slot h, the bit position (relative to
+    // the tile's first bit) of the source cell, a tile-halo bit, or a zero bit.
+    const uint32_t halo_base = 32u * T->halo_word, zero_bit = halo_base + kMaxTileHalo;
+    std::vector<uint16_t> bh((size_t)T->nblocks * T->hstride, (uint16_t)zero_bit);
+    const int64_t bside = cpow(Pat::S, M - J);
+    for (uint32_t b = 0; b < T->nblocks; ++b) {
+        int64_t bx, by;
+        host_lambda(F, M - J, b, bx, by);
+        for (int h = 0; h < PL.nhalo; ++h) {
+            const int64_t nbx = bx + PL.h_dx[h], nby = by + PL.h_dy[h];
+            uint32_t e = zero_bit;
+            if (nbx >= 0 && nby >= 0 && nbx < bside && nby < bside) {
+                const int64_t nb = host_nu(F, M - J, nbx, nby);
+                if (nb >= 0) e = (uint32_t)(nb * PL.nc + PL.h_idx[h]);
+            } else {
+                const int64_t px = nbx * PL.box + PL.lx[PL.h_idx[h]], py = nby * PL.box + PL.ly[PL.h_idx[h]];
+                for (size_t s = 0; s < slots.size(); ++s)
+                    if (slots[s].px == px && slots[s].py == py) e = halo_base + (uint32_t)s;
+            }
+            bh[(size_t)b * T->hstride + h] = (uint16_t)e;
+        }
+    }
+
+    // coarse maps and per-tile halo indices
+    sqz_status st = build_map_params(F, F.r - M, T->Pc, &T->d_coarse_tables);
+    if (st != SQZ_OK) {
+        delete T;
+        return st;
+    }
+    T->ntiles = T->Pc.N;
+    T->d_block_halo = nullptr;
+    T->d_tile_halo = nullptr;
+    int4 *d_slots = nullptr;
+    std::vector<int4> hs(slots.size() ? slots.size() : 1);
+    for (size_t s = 0; s < slots.size(); ++s) hs[s] = make_int4(slots[s].dx, slots[s].dy, (int)slots[s].idx, 0);
+    hipError_t e = hipMalloc(&T->d_block_halo, bh.size() * sizeof(uint16_t));
+    if (e == hipSuccess) e = hipMemcpy(T->d_block_halo, bh.data(), bh.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&T->d_tile_halo, (size_t)T->ntiles * (T->nthalo ? T->nthalo : 1) * sizeof(uint64_t));
+    if (e == hipSuccess) e = hipMalloc(&d_slots, hs.size() * sizeof(int4));
+    if (e == hipSuccess) e = hipMemcpy(d_slots, hs.data(), hs.size() * sizeof(int4), hipMemcpyHostToDevice);
+    if (e == hipSuccess && T->nthalo) {
+        uint64_t g = (T->ntiles + kBlock - 1) / kBlock;
+        if (g > 16384) g = 16384;
+        hipLaunchKernelGGL(k_tile_halo, dim3((unsigned)g), dim3(kBlock), 0, 0, T->Pc, T->ntiles, T->nthalo,
+                           (uint64_t)T->tile, d_slots, T->d_tile_halo);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+    }
+    if (d_slots) (void)hipFree(d_slots);
+    if (e != hipSuccess) {
+        if (T->d_block_halo) (void)hipFree(T->d_block_halo);
+        if (T->d_tile_halo) (void)hipFree(T->d_tile_halo);
+        (void)hipFree(T->d_coarse_tables);
+        delete T;
+        return hip_error(e, "tile table setup");
+    }
+    F.tile = T;
+    return SQZ_OK;
+}
+
+template <class Pat>
+sqz_status launch(const FractalHost &F, const uint8_t *in, uint8_t *out, hipStream_t st)
+{
+    const TileConfig *T = F.tile;
+    if (((uintptr_t)in & 15) || ((uintptr_t)out & 15))
+        return set_error(SQZ_ERR_INVALID, "tiled kernel needs 16-byte aligned buffers");
+    TileArgs A;
+    A.ntiles = T->ntiles;
+    A.N = F.N;
+    A.tile = T->tile;
+    A.nblocks = T->nblocks;
+    A.nthalo = T->nthalo;
+    A.hstride = T->hstride;
+    A.halo_word = T->halo_word;
+    A.block_halo = T->d_block_halo;
+    A.tile_halo = T->d_tile_halo;
+    const uint64_t grid = T->ntiles < (1ull << 20) ? T->ntiles : (1ull << 20);
+    hipLaunchKernelGGL(k_life_tile<Pat>, dim3((unsigned)grid), dim3(kBlock), 0, st, A, in, out);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SQZ_OK : hip_error(e, "compact_step (tile) launch");
+}
+
+enum { kNone = 0, kTriangle = 1, kTrianglePaper = 2, kVicsek = 3 };
+
+}  // namespace
+
+int tile_kind_for(const FractalHost &F)
+{
+    if (matches<PatTriangle>(F) && F.r >= PatTriangle::J) return kTriangle;
+    if (matches<PatTrianglePaper>(F) && F.r >= PatTrianglePaper::J) return kTrianglePaper;
+    if (matches<PatVicsek>(F) && F.r >= PatVicsek::J) return kVicsek;
+    return kNone;
+}
+
+sqz_status tile_prepare(FractalHost &F)
+{
+    switch (F.tile_kind) {
+    case kTriangle: return prepare<PatTriangle>(F);
+    case kTrianglePaper: return prepare<PatTrianglePaper>(F);
+    case kVicsek: return prepare<PatVicsek>(F);
+    }
+    return set_error(SQZ_ERR_UNSUPPORTED, "no tiled kernel");
+}
+
+void tile_release(FractalHost &F)
+{
+    if (!F.tile) return;
+    (void)hipFree(F.tile->d_block_halo);
+    (void)hipFree(F.tile->d_tile_halo);
+    (void)hipFree(F.tile->d_coarse_tables);
+    delete F.tile;
+    F.tile = nullptr;
+}
+
+int32_t tile_level_of(const FractalHost &F) { return F.tile ? F.tile->M : 0; }
+
+sqz_status launch_life_tile(const FractalHost &F, const uint8_t *in, uint8_t *out, hipStream_t st)
+{
+    switch (F.tile_kind) {
+    case kTriangle: return launch<PatTriangle>(F, in, out, st);
+    case kTrianglePaper: return launch<PatTrianglePaper>(F, in, out, st);
+    case kVicsek: return launch<PatVicsek>(F, in, out, st);
+    }
+    return set_error(SQZ_ERR_UNSUPPORTED, "no tiled kernel");
+}
+
+}  // namespace sqz

@@ -1,0 +1,152 @@
+// Thread-level kernels: the two space maps, the seeded starts and the
+// thread-level Squeeze Life step (one lambda and eight nu per cell,
+// Section "Exploring Compact Fractal Space").
+#include "common.h"
+
+namespace sqz {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+// Grid for a grid-stride loop over `count` items: enough workgroups to fill
+// the device several times over, capped so 64-bit counters stay cheap.
+inline unsigned grid_for(uint64_t count)
+{
+    uint64_t g = (count + kBlock - 1) / kBlock;
+    if (g > 16384) g = 16384;
+    if (g == 0) g = 1;
+    return (unsigned)g;
+}
+
+__device__ __forceinline__ void lam_any(const MapParams &P, uint64_t c, uint32_t &x, uint32_t &y)
+{
+    if (P.N <= 0x100000000ull)
+        lam_map32(P, (uint32_t)c, x, y);
+    else
+        lam_map64(P, c, x, y);
+}
+
+__global__ void __launch_bounds__(kBlock) k_lambda(MapParams P, const uint64_t *__restrict__ idx, int64_t count,
+                                                   int32_t *__restrict__ xy)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += (int64_t)gridDim.x * kBlock) {
+        uint64_t c = idx[i];
+        int2 out = make_int2(-1, -1);
+        if (c < P.N) {
+            uint32_t x, y;
+            lam_any(P, c, x, y);
+            out = make_int2((int)x, (int)y);
+        }
+        reinterpret_cast<int2 *>(xy)[i] = out;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_nu(MapParams P, const int32_t *__restrict__ xy, int64_t count,
+                                               uint64_t *__restrict__ idx)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += (int64_t)gridDim.x * kBlock) {
+        int2 p = reinterpret_cast<const int2 *>(xy)[i];
+        idx[i] = nu_map(P, p.x, p.y);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_fill_compact(MapParams P, uint64_t seed, uint32_t thresh,
+                                                         uint8_t *__restrict__ out)
+{
+    for (uint64_t c = (uint64_t)blockIdx.x * kBlock + threadIdx.x; c < P.N; c += (uint64_t)gridDim.x * kBlock) {
+        uint32_t x, y;
+        lam_any(P, c, x, y);
+        uint64_t h = splitmix64_at(seed, (uint64_t)y * (uint64_t)P.n + x);
+        out[c] = (uint8_t)((uint32_t)(h >> 40) < thresh);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_fill_expanded(MapParams P, uint64_t seed, uint32_t thresh,
+                                                          uint8_t *__restrict__ out)
+{
+    const uint64_t total = (uint64_t)P.n * (uint64_t)P.n;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += (uint64_t)gridDim.x * kBlock) {
+        uint32_t y = (uint32_t)(i / (uint32_t)P.n), x = (uint32_t)(i - (uint64_t)y * P.n);
+        uint8_t v = 0;
+        if (nu_map(P, (int32_t)x, (int32_t)y) != kHole64) v = (uint8_t)((uint32_t)(splitmix64_at(seed, i) >> 40) < thresh);
+        out[i] = v;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_fill_uniform(MapParams P, uint64_t seed, float *__restrict__ out)
+{
+    for (uint64_t c = (uint64_t)blockIdx.x * kBlock + threadIdx.x; c < P.N; c += (uint64_t)gridDim.x * kBlock) {
+        uint32_t x, y;
+        lam_any(P, c, x, y);
+        uint64_t h = splitmix64_at(seed, (uint64_t)y * (uint64_t)P.n + x);
+        out[c] = (float)(uint32_t)(h >> 40) * (1.0f / 16777216.0f);
+    }
+}
+
+// B3/S23 on the fractal: a member neighbour counts its state; a hole or a
+// point outside the box counts nothing.
+__global__ void __launch_bounds__(kBlock) k_life_cell(MapParams P, const uint8_t *__restrict__ in,
+                                                      uint8_t *__restrict__ out)
+{
+    for (uint64_t c = (uint64_t)blockIdx.x * kBlock + threadIdx.x; c < P.N; c += (uint64_t)gridDim.x * kBlock) {
+        uint32_t x, y;
+        lam_any(P, c, x, y);
+        uint32_t cnt = 0;
+#pragma unroll
+        for (int j = 0; j < 9; ++j) {
+            if (j == 4) continue;
+            int dx = j % 3 - 1, dy = j / 3 - 1;
+            uint64_t q = nu_map(P, (int32_t)x + dx, (int32_t)y + dy);
+            if (q != kHole64) cnt += in[q];
+        }
+        uint32_t self = in[c];
+        out[c] = (uint8_t)(cnt == 3 || (self && cnt == 2));
+    }
+}
+
+sqz_status after_launch(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SQZ_OK : hip_error(e, what);
+}
+
+}  // namespace
+
+sqz_status launch_lambda(const MapParams &P, const uint64_t *idx, int64_t count, int32_t *xy, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_lambda, dim3(grid_for((uint64_t)count)), dim3(kBlock), 0, st, P, idx, count, xy);
+    return after_launch("lambda_map launch");
+}
+
+sqz_status launch_nu(const MapParams &P, const int32_t *xy, int64_t count, uint64_t *idx, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_nu, dim3(grid_for((uint64_t)count)), dim3(kBlock), 0, st, P, xy, count, idx);
+    return after_launch("nu_map launch");
+}
+
+sqz_status launch_fill_bernoulli(const MapParams &P, uint64_t seed, uint32_t thresh24, int expanded, uint8_t *out,
+                                 hipStream_t st)
+{
+    if (expanded) {
+        uint64_t total = (uint64_t)P.n * (uint64_t)P.n;
+        hipLaunchKernelGGL(k_fill_expanded, dim3(grid_for(total)), dim3(kBlock), 0, st, P, seed, thresh24, out);
+    } else {
+        hipLaunchKernelGGL(k_fill_compact, dim3(grid_for(P.N)), dim3(kBlock), 0, st, P, seed, thresh24, out);
+    }
+    return after_launch("fill_bernoulli launch");
+}
+
+sqz_status launch_fill_uniform(const MapParams &P, uint64_t seed, float *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fill_uniform, dim3(grid_for(P.N)), dim3(kBlock), 0, st, P, seed, out);
+    return after_launch("fill_uniform launch");
+}
+
+sqz_status launch_life_cell(const MapParams &P, const uint8_t *in, uint8_t *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_life_cell, dim3(grid_for(P.N)), dim3(kBlock), 0, st, P, in, out);
+    return after_launch("compact_step (cell) launch");
+}
+
+}  // namespace sqz

@@ -1,0 +1,219 @@
+"""GPU parity of the Life step (thread-level, tiled, bounding box) against the oracle."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from gpu_common import gpu_fractal, mismatch, oracle_fractal, to_np, torch_or_skip
+
+pytestmark = pytest.mark.gpu
+
+SMALL = [("triangle", r) for r in range(0, 11)] + [("triangle_paper", 5), ("triangle_paper", 9),
+                                                   ("carpet", 1), ("carpet", 3), ("carpet", 5),
+                                                   ("vicsek", 1), ("vicsek", 2), ("vicsek", 4), ("vicsek", 7)]
+
+
+def impls(F):
+    return ["cell", "tile"] if F.has_tile else ["cell"]
+
+
+@pytest.mark.parametrize("name,r", SMALL)
+@pytest.mark.parametrize("seed,p", [(2201, 0.5), (77, 0.3)])
+def test_step_and_run_match_oracle(name, r, seed, p):
+    torch = torch_or_skip()
+    F, O = gpu_fractal(name, r), oracle_fractal(name, r)
+    start = O.fill_compact(seed, p)
+    want1 = O.life_compact(start)
+    want7 = O.life_steps(start, 7)
+    for impl in impls(F):
+        a = F.fill_bernoulli(seed, p)
+        b = torch.empty_like(a)
+        F.compact_step(a, b, impl=impl)
+        mismatch(to_np(b), want1, f"{name} r={r} {impl} 1 step")
+        x, y = a.clone(), torch.empty_like(a)
+        for i in range(7):
+            F.compact_step(x, y, impl=impl)
+            x, y = y, x
+        mismatch(to_np(x), want7, f"{name} r={r} {impl} 7 steps")
+
+
+@pytest.mark.parametrize("name,r", [("triangle", 10), ("carpet", 4)])
+def test_all_alive_and_empty(name, r):
+    torch = torch_or_skip()
+    F, O = gpu_fractal(name, r), oracle_fractal(name, r)
+    for fill in (0, 1):
+        a = torch.full((F.cells,), fill, dtype=torch.uint8, device="cuda")
+        want = O.life_compact(np.full(F.cells, fill, np.uint8))
+        for impl in impls(F):
+            b = torch.empty_like(a)
+            F.compact_step(a, b, impl=impl)
+            mismatch(to_np(b), want, f"{name} all={fill} {impl}")
+    if name == "triangle":
+        assert want.sum() == 26245
+
+
+def test_compact_run_parity_and_placement():
+    torch = torch_or_skip()
+    F, O = gpu_fractal("triangle", 9), oracle_fractal("triangle", 9)
+    start = O.fill_compact(5, 0.5)
+    for steps in (0, 1, 4, 5):
+        a = F.fill_bernoulli(5, 0.5)
+        b = torch.zeros_like(a)
+        res = F.compact_run(a, b, steps)
+        assert res is (a if steps % 2 == 0 else b)
+        mismatch(to_np(res), O.life_steps(start, steps) if steps else start, f"run {steps}")
+
+
+def test_r16_one_step_ranges_and_light_cones():
+    """Level-16 triangle (43M cells): one step compared on the first, a middle and the
+    last 3M cells; 100 steps (tiled) compared on light-cone samples."""
+    torch = torch_or_skip()
+    F, O = gpu_fractal("triangle", 16), oracle_fractal("triangle", 16)
+    seed, p = 2201, 0.5
+    a = F.fill_bernoulli(seed, p)
+    b = torch.empty_like(a)
+    start = O.fill_compact(seed, p)
+    mismatch(to_np(a), start, "fill r=16")
+    F.compact_step(a, b, impl="tile")
+    got = to_np(b)
+    for c0 in (0, F.cells // 2, F.cells - 3_000_000):
+        mismatch(got[c0:c0 + 3_000_000], O.life_compact(start, c0, c0 + 3_000_000), f"r16 range {c0}")
+    res = F.compact_run(a, b, 100)
+    rng = np.random.default_rng(16)
+    c = rng.integers(0, F.cells, 600)
+    c[:3] = [0, F.cells // 2, F.cells - 1]
+    xy = O.lam(c)
+    mismatch(to_np(res[torch.from_numpy(c).cuda()]), O.light_cone(seed, p, xy, 100), "r16 100 steps")
+
+
+def test_r16_tile_equals_cell_and_bb():
+    """Three GPU kernels on the level-16 triangle agree after 10 steps: tiled, thread-level,
+    and the bounding-box grid gathered through lambda."""
+    torch = torch_or_skip()
+    F = gpu_fractal("triangle", 16)
+    a = F.fill_bernoulli(3, 0.5)
+    t1, t2 = a.clone(), torch.empty_like(a)
+    c1, c2 = a.clone(), torch.empty_like(a)
+    rt = F.compact_run(t1, t2, 10)
+    for i in range(10):
+        F.compact_step(c1, c2, impl="cell")
+        c1, c2 = c2, c1
+    assert torch.equal(rt, c1)
+    e1 = F.fill_bernoulli(3, 0.5, layout="expanded")
+    e2 = torch.empty_like(e1)
+    for i in range(10):
+        F.expanded_step(e1, e2)
+        e1, e2 = e2, e1
+    xy = F.lambda_map(torch.arange(F.cells, dtype=torch.int64, device="cuda")).long()
+    gathered = e1[xy[:, 1] * F.n + xy[:, 0]]
+    assert torch.equal(gathered, rt)
+    assert int(e1.sum()) == int(rt.sum())  # holes stayed 0
+    del e1, e2, xy, gathered
+    torch.cuda.empty_cache()
+
+
+def test_r20_light_cones():
+    """Level-20 triangle (3.49e9 cells, expanded form 1.1 TB): one step and 20 steps
+    (tiled) checked on light-cone samples."""
+    torch = torch_or_skip()
+    F, O = gpu_fractal("triangle", 20), oracle_fractal("triangle", 20)
+    seed, p = 2201, 0.3
+    a = F.fill_bernoulli(seed, p)
+    b = torch.empty_like(a)
+    rng = np.random.default_rng(20)
+    c = rng.integers(0, F.cells, 4000)
+    c[:4] = [0, 1, F.cells - 2, F.cells - 1]
+    ct = torch.from_numpy(c).cuda()
+    xy = O.lam(c)
+    F.compact_step(a, b)
+    mismatch(to_np(b[ct]), O.light_cone(seed, p, xy, 1), "r20 1 step")
+    # a contiguous range across many tile boundaries, exhaustively
+    c0 = 1_234_567_891
+    mismatch(to_np(b[c0:c0 + 200_000]), _range_step(O, seed, p, c0, 200_000), "r20 range")
+    res = F.compact_run(a, b, 20)
+    mismatch(to_np(res[ct]), O.light_cone(seed, p, xy, 20), "r20 20 steps")
+    del a, b, res
+    torch.cuda.empty_cache()
+
+
+def _range_step(O, seed, p, c0, count):
+    """Oracle one-step states of cells [c0, c0+count) from the seeded start, without
+    materialising all N cells: each cell's one-step light cone."""
+    xy = O.lam(np.arange(c0, c0 + count, dtype=np.uint64))
+    return O.light_cone(seed, p, xy, 1)
+
+
+@pytest.mark.parametrize("name,r", [("triangle", 4), ("triangle", 10), ("triangle_paper", 7), ("carpet", 3),
+                                    ("carpet", 5), ("vicsek", 5)])
+def test_expanded_step_matches_oracle(name, r):
+    torch = torch_or_skip()
+    import oracle
+
+    F, O = gpu_fractal(name, r), oracle_fractal(name, r)
+    member = O.member()
+    grid = O.fill_expanded(11, 0.5)
+    a = F.fill_bernoulli(11, 0.5, layout="expanded")
+    mismatch(to_np(a).reshape(F.n, F.n), grid, "expanded fill")
+    b = torch.empty_like(a)
+    F.expanded_step(a, b)
+    mismatch(to_np(b).reshape(F.n, F.n), oracle.life_expanded(member, grid), f"BB {name} r={r}")
+
+
+def test_deterministic_and_checkpoint_resume():
+    torch = torch_or_skip()
+    F = gpu_fractal("triangle", 14)
+    a = F.fill_bernoulli(8, 0.5)
+    x1, y1 = a.clone(), torch.empty_like(a)
+    full = F.compact_run(x1, y1, 12).clone()
+    x2, y2 = a.clone(), torch.empty_like(a)
+    again = F.compact_run(x2, y2, 12)
+    assert torch.equal(full, again)
+    x3, y3 = a.clone(), torch.empty_like(a)
+    half = F.compact_run(x3, y3, 6).cpu()  # checkpoint to host
+    x4 = half.cuda()
+    y4 = torch.empty_like(x4)
+    assert torch.equal(F.compact_run(x4, y4, 6), full)
+
+
+def test_error_paths():
+    torch = torch_or_skip()
+    import paper_2201_00613_amd as sqz
+
+    L = sqz._lib.lib()
+    F = gpu_fractal("triangle", 6)
+    a = F.fill_bernoulli(1, 0.5)
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    p = ctypes.c_void_p(a.data_ptr())
+    assert L.sqz_compact_step(F._h, p, p, s) == 1  # aliasing
+    assert L.sqz_compact_step(F._h, p, ctypes.c_void_p(a.data_ptr() + 5), s) == 1  # overlap
+    assert L.sqz_compact_step(F._h, None, p, s) == 1
+    assert L.sqz_lambda_map(F._h, p, -1, p, s) == 1
+    assert L.sqz_lambda_map(F._h, None, 0, None, s) == 0
+    assert L.sqz_compact_run(F._h, p, p, 3, s) == 1
+    assert L.sqz_compact_run(F._h, p, ctypes.c_void_p(a.data_ptr() + 4096), -1, s) == 1
+    assert L.sqz_fill_bernoulli(F._h, 1, 1.5, 0, p, s) == 1
+    # misaligned buffers: the tiled kernel refuses, AUTO takes the thread-level path
+    big = torch.zeros(2 * F.cells + 64, dtype=torch.uint8, device="cuda")
+    src = big[1:1 + F.cells]
+    src.copy_(a)
+    dst = big[F.cells + 33:2 * F.cells + 33]
+    assert L.sqz_compact_step_impl(F._h, 2, ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), s) == 1
+    F.compact_step(src, dst)
+    ref = torch.empty_like(a)
+    F.compact_step(a, ref, impl="cell")
+    assert torch.equal(dst, ref)
+    # patterns without a tiled kernel
+    C = gpu_fractal("carpet", 3)
+    assert not C.has_tile
+    c = C.fill_bernoulli(1, 0.5)
+    with pytest.raises(sqz.SqueezeError) as e:
+        C.compact_step(c, torch.empty_like(c), impl="tile")
+    assert e.value.status == 5
+    # bounding box at r=20 cannot fit: refused before any allocation or launch
+    T20 = gpu_fractal("triangle", 20)
+    q = ctypes.c_void_p(16)
+    assert L.sqz_expanded_step(T20._h, q, ctypes.c_void_p(32), s) == 2
+    assert b"exceed" in L.sqz_last_error()
+    # a handle used on the wrong device is refused (only one device here: nothing to test)
+    info = sqz._lib.Info()
+    assert L.sqz_fractal_info(F._h, ctypes.byref(info)) == 0 and info.cells == 3 ** 6
