@@ -72,18 +72,42 @@ def bb_run(torch, F, seed, p, steps, warmup):
     return sec
 
 
-def cpu_baseline(r: int, seed: int, p: float, cells: int) -> dict:
-    """The oracle (plain C, OpenMP) stepping the first `cells` cells of the same workload."""
+def profiled_traffic(workload: str):
+    """Counter-measured bytes per launch of the tiled kernel, from the committed
+    rocprofv3 summary, if the kernel source is unchanged since it was taken."""
+    import hashlib
+    import re
+
+    src = os.path.join(ROOT, "paper_2201_00613_amd", "csrc")
+    h = hashlib.sha256()
+    for f in ("life_tile.hip", "common.h"):
+        h.update(open(os.path.join(src, f), "rb").read())
+    path = os.path.join(ROOT, "profiles", "k_life_tile_triangle_r16.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    if rec["workload"] != workload or rec["source_sha256_16"] != h.hexdigest()[:16]:
+        return None
+    return rec
+
+
+def cpu_baseline(r: int, seed: int, p: float, min_sec: float, max_steps: int) -> dict:
+    """The oracle (plain C, OpenMP, lambda + 8 nu per cell) stepping the same workload:
+    whole steps from the same start until min_sec have elapsed (at most max_steps)."""
     import oracle
 
     O = oracle.Fractal(*TRIANGLE, r)
-    start = O.fill_compact(seed, p)
-    t0 = time.perf_counter()
-    O.life_compact(start, 0, cells)
+    state = O.fill_compact(seed, p)
+    steps, t0 = 0, time.perf_counter()
+    while steps < max_steps and (steps == 0 or time.perf_counter() - t0 < min_sec):
+        state = O.life_compact(state)
+        steps += 1
     sec = time.perf_counter() - t0
-    return {"value": cells / sec, "unit": "cell-updates/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"one B3/S23 step of compact cells [0, {cells}) of the level-{r} triangle "
-                      f"(lambda + 8 nu per cell), {sec:.1f} s"}
+    return {"value": O.N * steps / sec, "unit": "cell-updates/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{steps} full B3/S23 step(s) of the level-{r} triangle ({O.N} cells each), {sec:.1f} s"}
 
 
 def main() -> int:
@@ -98,7 +122,10 @@ def main() -> int:
     ap.add_argument("--no-bb", action="store_true")
     ap.add_argument("--no-r20", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-cells", type=int, default=12_000_000)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--cpu-max-steps", type=int, default=8)
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only time a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the multi-GPU "
@@ -110,6 +137,14 @@ def main() -> int:
     import paper_2201_00613_amd as sqz
 
     torch.cuda.set_device(0)
+    if args.copy_bytes:
+        src = torch.ones(args.copy_bytes, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        sec = time_steps(torch, lambda i: dst.copy_(src), args.steps, args.warmup)
+        gbs = 2 * args.copy_bytes / (sec / args.steps) / 1e9
+        print(json.dumps({"copy_bytes": args.copy_bytes, "ms_per_copy": sec * 1e3 / args.steps,
+                          "gbs_read_plus_write": gbs}), flush=True)
+        return 0
     seed, p, r = 2201, 0.5, args.level
     F = sqz.Fractal(*TRIANGLE, r)
     log(f"[bench] triangle r={r}: {F.cells} cells, tile level {F.tile_level}, impl {args.impl}")
@@ -129,6 +164,11 @@ def main() -> int:
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs / HBM_PEAK_GBS, "traffic": None},
     }
+    rec = profiled_traffic(out["config"]["workload"]) if args.impl == "auto" else None
+    if rec:
+        out["roofline"]["traffic"] = rec["traffic_bytes_per_launch"] / (sec / args.steps) / 1e9
+        out["roofline"]["traffic_bytes_per_launch"] = rec["traffic_bytes_per_launch"]
+        out["roofline"]["traffic_vs_algorithmic"] = rec["traffic_bytes_per_launch"] / (BYTES_PER_UPDATE * F.cells)
     if not args.no_bb:
         bsec = bb_run(torch, F, seed, p, args.bb_steps, 2)
         bb_ups = F.cells * args.bb_steps / bsec
@@ -152,7 +192,7 @@ def main() -> int:
         del F20
         torch.cuda.empty_cache()
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(r, seed, p, min(args.cpu_cells, 3 ** r))
+        out["cpu_baseline"] = cpu_baseline(r, seed, p, args.cpu_seconds, args.cpu_max_steps)
         log(f"[bench] cpu oracle: {out['cpu_baseline']['value']:.3e} cell-updates/s "
             f"on {out['cpu_baseline']['cores']} threads")
     print(json.dumps(out), flush=True)

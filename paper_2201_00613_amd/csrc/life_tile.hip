@@ -18,11 +18,13 @@
 // with a few logic operations.
 //
 // Memory path per tile: coalesced 16-byte loads of the tile's bytes, packed to
-// bits in LDS (pack: (d * 0x10204080) >> 28 gathers bit 0 of four bytes);
-// results are OR-ed into an LDS bit array and written back with coalesced
-// 16-byte stores (unpack: (v * 0x204081) & 0x01010101 spreads four bits).  The
-// tile boundaries are not 16-byte aligned: edge words are stored byte by byte
-// so neighbouring tiles never overwrite each other.
+// bits in LDS (pack: a 4-byte dot product with byte weights 1,2,4,8 (then
+// 16..128) turns eight 0/1 bytes into one byte of bits); results are OR-ed into
+// an LDS bit array and written back with coalesced 16-byte stores (unpack:
+// (v * 0x204081) & 0x01010101 spreads four bits over four bytes).  Tile
+// boundaries are not 16-byte aligned: the two edge words of a tile are stored
+// byte by byte, one byte per lane, so neighbouring tiles never overwrite each
+// other.
 #include <utility>
 #include <vector>
 
@@ -57,7 +59,7 @@ constexpr int cpow(int b, int e)
 }
 
 constexpr int kMaxHalo = 16;      // halo cells per block
-constexpr int kMaxTileHalo = 24;  // halo cells per tile
+constexpr int kMaxTileHalo = 32;  // halo cells per tile (one LDS word of bits)
 constexpr int kBlock = 256;
 
 // ---------------------------------------------------------------------------
@@ -196,10 +198,10 @@ struct TileConfig {
     uint32_t tile;         // K^M cells per tile
     uint32_t nblocks;      // K^(M-J)
     uint32_t nthalo;       // tile halo slots
-    uint32_t hstride;      // u16 entries per block in the block-halo table (multiple of 8)
-    uint32_t halo_word;    // LDS word index of the halo region
+    uint32_t hstride;      // u32 entries per block in the block-halo table (multiple of 4)
+    uint32_t halo_word;    // LDS word index of the tile-halo bits (the next word is all zero)
     uint64_t ntiles;       // K^(r-M)
-    uint16_t *d_block_halo;
+    uint32_t *d_block_halo;  // [32 alignments][nblocks][hstride]
     uint64_t *d_tile_halo;
     MapParams Pc;          // maps at the coarse level r-M
     void *d_coarse_tables;
@@ -208,7 +210,7 @@ struct TileConfig {
 struct TileArgs {
     uint64_t ntiles, N;
     uint32_t tile, nblocks, nthalo, hstride, halo_word;
-    const uint16_t *block_halo;
+    const uint32_t *block_halo;
     const uint64_t *tile_halo;
 };
 
@@ -216,11 +218,15 @@ template <class Pat>
 struct TileLds {
     static constexpr int TMAX = cpow(Pat::K, Pat::MMAX);
     static constexpr int WMAX = (TMAX + 31 + 31) / 32;  // words covering o + tile bits
-    static constexpr int HALO_WORD = WMAX + 1;          // 2 words of halo bits after the data
+    static constexpr int HALO_WORD = WMAX + 1;          // tile-halo bits, then one zero word
     static constexpr int IN_WORDS = HALO_WORD + 2;
 };
 
-__device__ __forceinline__ uint32_t pack4(uint32_t d) { return ((d & 0x01010101u) * 0x10204080u) >> 28; }
+// Bit 0 of eight bytes (two words) -> one byte of bits, via 4-byte dot products.
+__device__ __forceinline__ uint32_t pack8(uint32_t d0, uint32_t d1)
+{
+    return __builtin_amdgcn_udot4(d1, 0x80402010u, __builtin_amdgcn_udot4(d0, 0x08040201u, 0u, false), false);
+}
 __device__ __forceinline__ uint32_t spread4(uint32_t v) { return __umul24(v, 0x204081u) & 0x01010101u; }
 
 template <int Layer, int Shift, uint32_t Mask, int NL>
@@ -296,7 +302,7 @@ __global__ void __launch_bounds__(kBlock) k_life_tile(TileArgs A, const uint8_t 
     constexpr int NH = PL.nhalo;
 
     __shared__ uint32_t s_in[LDS::IN_WORDS];
-    __shared__ uint32_t s_out[LDS::WMAX];
+    __shared__ uint32_t s_out[LDS::WMAX + 1];  // +1: a block's high half may land one word past the tile
 
     const uint32_t tid = threadIdx.x;
     const uint32_t G = gridDim.x;
@@ -308,6 +314,8 @@ __global__ void __launch_bounds__(kBlock) k_life_tile(TileArgs A, const uint8_t 
         const uint32_t o = (uint32_t)(S0 - A0);
         const uint32_t W = (o + A.tile + 31) / 32;
 
+        const uint32_t *bh_o = A.block_halo + (size_t)o * A.nblocks * A.hstride;
+
         // Phase A: load and pack the tile (plus the bytes of its first and last
         // 32-byte words that belong to the neighbouring tiles).
         for (uint32_t w = tid; w < W; w += kBlock) {
@@ -316,8 +324,7 @@ __global__ void __launch_bounds__(kBlock) k_life_tile(TileArgs A, const uint8_t 
             if (g + 32 <= A.N) {
                 const uint4 a = *reinterpret_cast<const uint4 *>(in + g);
                 const uint4 b = *reinterpret_cast<const uint4 *>(in + g + 16);
-                bits = pack4(a.x) | pack4(a.y) << 4 | pack4(a.z) << 8 | pack4(a.w) << 12 | pack4(b.x) << 16 |
-                       pack4(b.y) << 20 | pack4(b.z) << 24 | pack4(b.w) << 28;
+                bits = pack8(a.x, a.y) | pack8(a.z, a.w) << 8 | pack8(b.x, b.y) << 16 | pack8(b.z, b.w) << 24;
             } else {
                 for (uint32_t i = 0; i < 32; ++i)
                     if (g + i < A.N) bits |= (uint32_t)(in[g + i] & 1u) << i;
@@ -334,9 +341,8 @@ __global__ void __launch_bounds__(kBlock) k_life_tile(TileArgs A, const uint8_t 
             }
             const uint64_t m = __ballot(v);
             if (tid == 0) {
-                const uint64_t sh = (m & 0xFFFFFFull) << o;
-                s_in[A.halo_word] = (uint32_t)sh;
-                s_in[A.halo_word + 1] = (uint32_t)(sh >> 32);
+                s_in[A.halo_word] = (uint32_t)m;
+                s_in[A.halo_word + 1] = 0u;
             }
         }
         __syncthreads();
@@ -345,17 +351,20 @@ __global__ void __launch_bounds__(kBlock) k_life_tile(TileArgs A, const uint8_t 
         for (uint32_t b = tid; b < A.nblocks; b += kBlock) {
             const uint32_t pos = o + b * NC;
             const uint32_t lo = s_in[pos >> 5], hi = s_in[(pos >> 5) + 1];
-            const uint32_t x = __builtin_amdgcn_alignbit(hi, lo, pos & 31) & CELLS;
+            const uint32_t x = __builtin_amdgcn_alignbit(hi, lo, pos) & CELLS;  // shift = pos mod 32
             uint32_t hb[NH > 0 ? NH : 1] = {};
-            const uint16_t *he = A.block_halo + (size_t)b * A.hstride;
+            const uint32_t *he = bh_o + (size_t)b * A.hstride;
 #pragma unroll
-            for (int h0 = 0; h0 < NH; h0 += 8) {
+            for (int h0 = 0; h0 < NH; h0 += 4) {
                 const uint4 q = *reinterpret_cast<const uint4 *>(he + h0);
                 const uint32_t qq[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
-                for (int h = h0; h < NH && h < h0 + 8; ++h) {
-                    const uint32_t e = ((qq[(h - h0) >> 1] >> (16 * ((h - h0) & 1))) & 0xFFFFu) + o;
-                    hb[h] = __builtin_amdgcn_ubfe(s_in[e >> 5], e, 1);  // bit e mod 32
+                for (int h = h0; h < NH && h < h0 + 4; ++h) {
+                    // entry: LDS byte address of the word << 16 | bit within the word
+                    const uint32_t e = qq[h - h0];
+                    const uint32_t word = *reinterpret_cast<const uint32_t *>(
+                        reinterpret_cast<const char *>(s_in) + (e >> 16));
+                    hb[h] = __builtin_amdgcn_ubfe(word, e, 1);
                 }
             }
             uint32_t L[NL];
@@ -366,15 +375,18 @@ __global__ void __launch_bounds__(kBlock) k_life_tile(TileArgs A, const uint8_t 
             const uint32_t res = life_rule<NL>(x, L) & CELLS;
             const uint64_t sh = (uint64_t)res << (pos & 31);
             atomicOr(&s_out[pos >> 5], (uint32_t)sh);
-            if ((uint32_t)(sh >> 32)) atomicOr(&s_out[(pos >> 5) + 1], (uint32_t)(sh >> 32));
+            atomicOr(&s_out[(pos >> 5) + 1], (uint32_t)(sh >> 32));
         }
         __syncthreads();
 
-        // Phase D: unpack and store; edge words byte by byte.
+        // Phase D: unpack and store whole words; the (at most two) edge words
+        // of the tile go out byte by byte, one byte per lane of wave 0.
+        const uint32_t last = W - 1;
+        const bool first_partial = o != 0, last_partial = ((o + A.tile) & 31) != 0;
         for (uint32_t w = tid; w < W; w += kBlock) {
             const uint32_t v = s_out[w];
             const uint64_t g = A0 + 32ull * w;
-            if (32 * w >= o && 32 * w + 32 <= o + A.tile) {
+            if (!((w == 0 && first_partial) || (w == last && last_partial))) {
                 uint4 a, b;
                 a.x = spread4(v & 15);
                 a.y = spread4((v >> 4) & 15);
@@ -386,12 +398,12 @@ __global__ void __launch_bounds__(kBlock) k_life_tile(TileArgs A, const uint8_t 
                 b.w = spread4(v >> 28);
                 *reinterpret_cast<uint4 *>(out + g) = a;
                 *reinterpret_cast<uint4 *>(out + g + 16) = b;
-            } else {
-                for (uint32_t i = 0; i < 32; ++i) {
-                    const uint32_t lp = 32 * w + i;
-                    if (lp >= o && lp < o + A.tile) out[g + i] = (uint8_t)((v >> i) & 1u);
-                }
             }
+        }
+        if (tid < 64) {
+            const uint32_t w = tid < 32 ? 0u : last, i = tid & 31u, lp = 32 * w + i;
+            const bool mine = tid < 32 ? first_partial : (last_partial && (last != 0 || !first_partial));
+            if (mine && lp >= o && lp < o + A.tile) out[A0 + lp] = (uint8_t)((s_out[w] >> i) & 1u);
         }
         __syncthreads();  // LDS is reused by the next round
     }
@@ -473,8 +485,8 @@ sqz_status prepare(FractalHost &F)
     T->tile = (uint32_t)cpow(Pat::K, M);
     T->nblocks = (uint32_t)cpow(Pat::K, M - J);
     T->halo_word = TileLds<Pat>::HALO_WORD;
-    T->hstride = (uint32_t)((PL.nhalo + 7) / 8 * 8);
-    if (T->hstride == 0) T->hstride = 8;
+    T->hstride = (uint32_t)((PL.nhalo + 3) / 4 * 4);
+    if (T->hstride == 0) T->hstride = 4;
     const int64_t side = cpow(Pat::S, M);
 
     // tile halo slots: cells of adjacent tiles that touch a cell of this tile
@@ -504,28 +516,47 @@ sqz_status prepare(FractalHost &F)
     }
     T->nthalo = (uint32_t)slots.size();
 
-    // block halo table: for block b and halo slot h, the bit position (relative to
-    // the tile's first bit) of the source cell, a tile-halo bit, or a zero bit.
-    const uint32_t halo_base = 32u * T->halo_word, zero_bit = halo_base + kMaxTileHalo;
-    std::vector<uint16_t> bh((size_t)T->nblocks * T->hstride, (uint16_t)zero_bit);
+    // block halo table: for block b and halo slot h, the source cell's bit
+    // position relative to the tile's first bit (< 2^20), a tile-halo slot, or
+    // nothing.  Expanded below into LDS (word address << 16 | bit) entries for
+    // each of the 32 possible alignments o of a tile's first bit.
+    const uint32_t kSlot = 1u << 20, kZero = 1u << 21;
+    std::vector<uint32_t> bh((size_t)T->nblocks * T->hstride, kZero);
     const int64_t bside = cpow(Pat::S, M - J);
     for (uint32_t b = 0; b < T->nblocks; ++b) {
         int64_t bx, by;
         host_lambda(F, M - J, b, bx, by);
         for (int h = 0; h < PL.nhalo; ++h) {
             const int64_t nbx = bx + PL.h_dx[h], nby = by + PL.h_dy[h];
-            uint32_t e = zero_bit;
+            uint32_t e = kZero;
             if (nbx >= 0 && nby >= 0 && nbx < bside && nby < bside) {
                 const int64_t nb = host_nu(F, M - J, nbx, nby);
                 if (nb >= 0) e = (uint32_t)(nb * PL.nc + PL.h_idx[h]);
             } else {
                 const int64_t px = nbx * PL.box + PL.lx[PL.h_idx[h]], py = nby * PL.box + PL.ly[PL.h_idx[h]];
                 for (size_t s = 0; s < slots.size(); ++s)
-                    if (slots[s].px == px && slots[s].py == py) e = halo_base + (uint32_t)s;
+                    if (slots[s].px == px && slots[s].py == py) e = kSlot + (uint32_t)s;
             }
-            bh[(size_t)b * T->hstride + h] = (uint16_t)e;
+            bh[(size_t)b * T->hstride + h] = e;
         }
     }
+    std::vector<uint32_t> bho((size_t)32 * bh.size());
+    for (uint32_t o = 0; o < 32; ++o)
+        for (size_t i = 0; i < bh.size(); ++i) {
+            const uint32_t e = bh[i];
+            uint32_t word, bit;
+            if (e & kZero) {
+                word = T->halo_word + 1;
+                bit = 0;
+            } else if (e & kSlot) {
+                word = T->halo_word;
+                bit = e - kSlot;
+            } else {
+                word = (e + o) >> 5;
+                bit = (e + o) & 31;
+            }
+            bho[o * bh.size() + i] = ((4 * word) << 16) | bit;
+        }
 
     // coarse maps and per-tile halo indices
     sqz_status st = build_map_params(F, F.r - M, T->Pc, &T->d_coarse_tables);
@@ -539,8 +570,8 @@ sqz_status prepare(FractalHost &F)
     int4 *d_slots = nullptr;
     std::vector<int4> hs(slots.size() ? slots.size() : 1);
     for (size_t s = 0; s < slots.size(); ++s) hs[s] = make_int4(slots[s].dx, slots[s].dy, (int)slots[s].idx, 0);
-    hipError_t e = hipMalloc(&T->d_block_halo, bh.size() * sizeof(uint16_t));
-    if (e == hipSuccess) e = hipMemcpy(T->d_block_halo, bh.data(), bh.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
+    hipError_t e = hipMalloc(&T->d_block_halo, bho.size() * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMemcpy(T->d_block_halo, bho.data(), bho.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMalloc(&T->d_tile_halo, (size_t)T->ntiles * (T->nthalo ? T->nthalo : 1) * sizeof(uint64_t));
     if (e == hipSuccess) e = hipMalloc(&d_slots, hs.size() * sizeof(int4));
     if (e == hipSuccess) e = hipMemcpy(d_slots, hs.data(), hs.size() * sizeof(int4), hipMemcpyHostToDevice);
