@@ -21,9 +21,10 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found (ROCm is required to build libsqueeze)")
 
 
-def compile_command(out: str) -> list[str]:
+def compile_command(out: str, defines=()) -> list[str]:
     return [
         hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+        *[f"-D{d}" for d in defines],
         "-fvisibility=hidden", "-Wall", "-Wno-unused-function",
         # keep the compiler from forming packed-FP32 instructions
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -35,13 +35,24 @@ namespace sqz {
 // ---------------------------------------------------------------------------
 // Replica patterns with a tiled kernel.  Replica j is at (OX[j], OY[j]).
 // ---------------------------------------------------------------------------
+// Build-time knobs (defaults are the tuned values).
+#ifndef SQZ_TRI_TILE_LEVEL
+#define SQZ_TRI_TILE_LEVEL 8
+#endif
+#ifndef SQZ_NT_LOAD
+#define SQZ_NT_LOAD 0
+#endif
+#ifndef SQZ_NT_STORE
+#define SQZ_NT_STORE 0
+#endif
+
 struct PatTriangle {  // Sierpinski triangle, member iff x & y == 0
-    static constexpr int S = 2, K = 3, J = 3, MMAX = 8;
+    static constexpr int S = 2, K = 3, J = 3, MMAX = SQZ_TRI_TILE_LEVEL;
     static constexpr int OX[3] = {0, 1, 0};
     static constexpr int OY[3] = {0, 0, 1};
 };
 struct PatTrianglePaper {  // the paper's orientation: top, middle, right
-    static constexpr int S = 2, K = 3, J = 3, MMAX = 8;
+    static constexpr int S = 2, K = 3, J = 3, MMAX = SQZ_TRI_TILE_LEVEL;
     static constexpr int OX[3] = {0, 0, 1};
     static constexpr int OY[3] = {0, 1, 1};
 };
@@ -229,6 +240,27 @@ __device__ __forceinline__ uint32_t pack8(uint32_t d0, uint32_t d1)
 }
 __device__ __forceinline__ uint32_t spread4(uint32_t v) { return __umul24(v, 0x204081u) & 0x01010101u; }
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint4 load16(const uint8_t *p)
+{
+#if SQZ_NT_LOAD
+    const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
+    return make_uint4(v.x, v.y, v.z, v.w);
+#else
+    return *reinterpret_cast<const uint4 *>(p);
+#endif
+}
+__device__ __forceinline__ void store16(uint8_t *p, uint4 v)
+{
+#if SQZ_NT_STORE
+    u32x4 w = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(w, reinterpret_cast<u32x4 *>(p));
+#else
+    *reinterpret_cast<uint4 *>(p) = v;
+#endif
+}
+
 template <int Layer, int Shift, uint32_t Mask, int NL>
 __device__ __forceinline__ void move_term(uint32_t x, uint32_t (&L)[NL])
 {
@@ -263,8 +295,10 @@ template <int NL>
 __device__ __forceinline__ uint32_t life_rule(uint32_t x, const uint32_t (&L)[NL])
 {
     if constexpr (NL <= 5) {
-        const uint32_t a = L[0], b = NL > 1 ? L[1] : 0u, c = NL > 2 ? L[2] : 0u;
-        const uint32_t d = NL > 3 ? L[3] : 0u, e = NL > 4 ? L[4] : 0u;
+        uint32_t v[5] = {0u, 0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int l = 0; l < NL; ++l) v[l] = L[l];
+        const uint32_t a = v[0], b = v[1], c = v[2], d = v[3], e = v[4];
         const uint32_t s1 = a ^ b ^ c, c1 = (a & b) | (c & (a ^ b));
         const uint32_t s2 = s1 ^ d ^ e, c2 = (s1 & d) | (e & (s1 ^ d));
         // count = s2 + 2 (c1 + c2): 2 or 3 iff exactly one carry
@@ -316,14 +350,19 @@ __global__ void __launch_bounds__(kBlock) k_life_tile(TileArgs A, const uint8_t 
 
         const uint32_t *bh_o = A.block_halo + (size_t)o * A.nblocks * A.hstride;
 
+        // Phase B, first half: the global indices of the tile's halo cells are
+        // requested before the tile's own bytes so the two latencies overlap.
+        uint64_t gi = kHole64;
+        if (tid < A.nthalo) gi = A.tile_halo[t * A.nthalo + tid];
+
         // Phase A: load and pack the tile (plus the bytes of its first and last
         // 32-byte words that belong to the neighbouring tiles).
         for (uint32_t w = tid; w < W; w += kBlock) {
             const uint64_t g = A0 + 32ull * w;
             uint32_t bits = 0;
             if (g + 32 <= A.N) {
-                const uint4 a = *reinterpret_cast<const uint4 *>(in + g);
-                const uint4 b = *reinterpret_cast<const uint4 *>(in + g + 16);
+                const uint4 a = load16(in + g);
+                const uint4 b = load16(in + g + 16);
                 bits = pack8(a.x, a.y) | pack8(a.z, a.w) << 8 | pack8(b.x, b.y) << 16 | pack8(b.z, b.w) << 24;
             } else {
                 for (uint32_t i = 0; i < 32; ++i)
@@ -332,13 +371,9 @@ __global__ void __launch_bounds__(kBlock) k_life_tile(TileArgs A, const uint8_t 
             s_in[w] = bits;
             s_out[w] = 0;
         }
-        // Phase B: the tile's halo cells, one lane each, gathered by ballot.
+        // Phase B, second half: the halo cells themselves, gathered by ballot.
         if (tid < 64) {
-            uint32_t v = 0;
-            if (tid < A.nthalo) {
-                const uint64_t gi = A.tile_halo[t * A.nthalo + tid];
-                if (gi != kHole64) v = in[gi] & 1u;
-            }
+            const uint32_t v = gi != kHole64 ? (in[gi] & 1u) : 0u;
             const uint64_t m = __ballot(v);
             if (tid == 0) {
                 s_in[A.halo_word] = (uint32_t)m;
@@ -396,8 +431,8 @@ __global__ void __launch_bounds__(kBlock) k_life_tile(TileArgs A, const uint8_t 
                 b.y = spread4((v >> 20) & 15);
                 b.z = spread4((v >> 24) & 15);
                 b.w = spread4(v >> 28);
-                *reinterpret_cast<uint4 *>(out + g) = a;
-                *reinterpret_cast<uint4 *>(out + g + 16) = b;
+                store16(out + g, a);
+                store16(out + g + 16, b);
             }
         }
         if (tid < 64) {
