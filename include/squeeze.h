@@ -68,7 +68,33 @@ typedef enum sqz_layout { SQZ_LAYOUT_COMPACT = 0, SQZ_LAYOUT_EXPANDED = 1 } sqz_
  *                  Block-level"): one coarse map set per level-M subtree, the
  *                  subtree staged on chip.  SQZ_ERR_UNSUPPORTED if the pattern
  *                  has no tiled kernel. */
-typedef enum sqz_impl { SQZ_IMPL_AUTO = 0, SQZ_IMPL_CELL = 1, SQZ_IMPL_TILE = 2 } sqz_impl;
+/*   SQZ_IMPL_XTILE: block-level Squeeze with the level-M subtree expanded on chip
+ *                  (any replica pattern; SQZ_ERR_UNSUPPORTED when no level fits). */
+typedef enum sqz_impl { SQZ_IMPL_AUTO = 0, SQZ_IMPL_CELL = 1, SQZ_IMPL_TILE = 2, SQZ_IMPL_XTILE = 3 } sqz_impl;
+
+/* Storage type of the diffusion field. */
+typedef enum sqz_dtype { SQZ_F32 = 0, SQZ_BF16 = 1 } sqz_dtype;
+
+/* Rounding of a binary32 result to bfloat16 storage. */
+typedef enum sqz_rounding { SQZ_ROUND_NEAREST_EVEN = 0, SQZ_ROUND_STOCHASTIC = 1 } sqz_rounding;
+
+/* Doubles of caller-provided workspace for sqz_mass_f64 (result in element 0). */
+#define SQZ_MASS_WORK_DOUBLES 1025
+
+/* Explicit diffusion on the fractal:
+ *   u'_p = u_p + coef * sum over member Moore neighbours q of (u_q - u_p),
+ * no flux through holes or the box edge; binary32 arithmetic in a fixed order.
+ * SQZ_BF16 storage holds delta = u - offset as bfloat16 (the caller keeps the
+ * offset, normally the mean, which the update conserves); the update runs on
+ * delta, accumulates in binary32 and rounds per `rounding`, stochastic rounding
+ * drawing 16 bits from a counter hash of (seed, step, cell). */
+typedef struct sqz_diffusion {
+    sqz_dtype dtype;
+    sqz_rounding rounding;  /* bfloat16 only */
+    float coef;             /* a = dt * alpha; the update is stable for coef <= 1/8 */
+    sqz_impl impl;          /* AUTO (= XTILE when available) / CELL / XTILE */
+    uint64_t seed;
+} sqz_diffusion;
 
 typedef struct sqz_fractal sqz_fractal;
 
@@ -82,7 +108,7 @@ typedef struct sqz_info {
     uint64_t compact_w;  /* width of the paper's compact rectangle, k^ceil(r/2) */
     uint64_t compact_h;  /* height, k^floor(r/2) (Section "Compacting NBB Fractals") */
     int32_t has_tile;    /* 1 if SQZ_IMPL_TILE is available for this pattern */
-    int32_t reserved;
+    int32_t xtile_level; /* level of the expanded tiles of SQZ_IMPL_XTILE (0 if none) */
 } sqz_info;
 
 /*
@@ -179,6 +205,36 @@ SQZ_API sqz_status sqz_compact_run(const sqz_fractal *f, uint8_t *d_a, uint8_t *
  */
 SQZ_API sqz_status sqz_expanded_step(const sqz_fractal *f, const uint8_t *d_in, uint8_t *d_out,
                              void *stream);
+
+/*
+ * One diffusion step (see sqz_diffusion).  d_in, d_out: N values of the
+ * storage type, non-overlapping.  `step` feeds stochastic rounding only.
+ * coef outside [0, 1/8] or an unknown dtype/rounding/impl: SQZ_ERR_INVALID.
+ */
+SQZ_API sqz_status sqz_diffuse_step(const sqz_fractal *f, const sqz_diffusion *d, uint64_t step, const void *d_in,
+                                    void *d_out, void *stream);
+
+/* `steps` diffusion steps ping-ponging from d_a (steps numbered first_step,
+ * first_step+1, ...); the result is in d_a when steps is even, else in d_b. */
+SQZ_API sqz_status sqz_diffuse_run(const sqz_fractal *f, const sqz_diffusion *d, uint64_t first_step,
+                                   int32_t steps, void *d_a, void *d_b, void *stream);
+
+/*
+ * Total mass sum_c (offset + u_c) in binary64 on the device, deterministic
+ * (fixed reduction tree).  d_u: N values of `dtype`.  d_work: caller-provided
+ * device buffer of SQZ_MASS_WORK_DOUBLES doubles; the sum is written to
+ * d_work[0], the rest is scratch.  Calls sharing one d_work must not overlap.
+ */
+SQZ_API sqz_status sqz_mass_f64(const sqz_fractal *f, sqz_dtype dtype, const void *d_u, double offset,
+                                double *d_work, void *stream);
+
+/* bfloat16 storage conversion: d_b[c] = bf16_nearest_even(d_u[c] - offset). */
+SQZ_API sqz_status sqz_bf16_encode(const sqz_fractal *f, const float *d_u, float offset, uint16_t *d_b,
+                                   void *stream);
+
+/* d_u[c] = offset + float(d_b[c]). */
+SQZ_API sqz_status sqz_bf16_decode(const sqz_fractal *f, const uint16_t *d_b, float offset, float *d_u,
+                                   void *stream);
 
 /* Static text for a status code. */
 SQZ_API const char *sqz_status_string(sqz_status st);

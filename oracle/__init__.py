@@ -69,6 +69,7 @@ def lib() -> ctypes.CDLL:
             "orc_life_compact": (c_i64, [c_int, c_int, i32p, c_int, u8p, c_u64, c_u64, u8p]),
             "orc_light_cone": (None, [c_int, c_int, i32p, c_int, c_u64, c_u32, i64p, c_i64, c_int, u8p]),
             "orc_diffuse_compact": (None, [c_int, c_int, i32p, c_int, c_dbl, f64p, c_u64, c_u64, f64p]),
+            "orc_diffuse_cone": (None, [c_int, c_int, i32p, c_int, c_u64, c_dbl, i64p, c_i64, c_int, f64p]),
             "orc_neighbour_table": (None, [c_int, c_int, i32p, c_int, c_u64, c_u64, i64p]),
             "orc_diffuse_table": (None, [c_i64, i64p, c_dbl, c_int, f64p, f64p]),
             "orc_life_table": (None, [c_i64, i64p, c_int, u8p, u8p]),
@@ -196,6 +197,14 @@ class Fractal:
         out = np.empty(c1 - c0, dtype=np.float64)
         lib().orc_diffuse_compact(*self._a(), a, _ptr(u, ctypes.c_double), c0, c1,
                                   _ptr(out, ctypes.c_double))
+        return out
+
+    def diffuse_cone(self, seed: int, a: float, xy, t: int) -> np.ndarray:
+        """Values of cells xy after t diffusion steps from fill_uniform(seed), one window per cell."""
+        xy = np.ascontiguousarray(np.asarray(xy, dtype=np.int64).reshape(-1, 2))
+        out = np.empty(xy.shape[0], dtype=np.float64)
+        lib().orc_diffuse_cone(*self._a(), seed, a, _ptr(xy, ctypes.c_int64), xy.shape[0], t,
+                               _ptr(out, ctypes.c_double))
         return out
 
     def diffuse_steps(self, u: np.ndarray, a: float, steps: int, nb: np.ndarray | None = None) -> np.ndarray:

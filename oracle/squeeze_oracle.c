@@ -356,6 +356,65 @@ void orc_diffuse_compact(int s, int k, const int32_t *offs, int r, double a, con
     }
 }
 
+/*
+ * Light cone of the diffusion update: the value of cell (x,y) after t steps
+ * depends only on starting values within Chebyshev distance t.  The window of
+ * side 2t+1 around it is filled from the U(0,1) start (non-members absent),
+ * advanced t steps with no flux out of the window, and the centre is read;
+ * the window edge's error moves inward one cell per step.
+ */
+static double diffuse_cone_one(int s, int k, const int32_t *offs, int r, uint64_t seed, double a, int64_t x,
+                               int64_t y, int t, uint8_t *mem, double *cur, double *nxt)
+{
+    int64_t n = ipow(s, r);
+    int w = 2 * t + 1;
+    for (int j = 0; j < w; ++j)
+        for (int i = 0; i < w; ++i) {
+            int64_t px = x - t + i, py = y - t + j;
+            int m = orc_nu(s, k, offs, r, px, py) != ORC_HOLE;
+            mem[j * w + i] = (uint8_t)m;
+            cur[j * w + i] = m ? (double)(orc_splitmix64(seed, (uint64_t)(py * n + px)) >> 40) / 16777216.0 : 0.0;
+        }
+    for (int step = 0; step < t; ++step) {
+        for (int j = 0; j < w; ++j)
+            for (int i = 0; i < w; ++i) {
+                if (!mem[j * w + i]) {
+                    nxt[j * w + i] = 0.0;
+                    continue;
+                }
+                double acc = 0.0;
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        if (!dx && !dy) continue;
+                        int qi = i + dx, qj = j + dy;
+                        if (qi < 0 || qj < 0 || qi >= w || qj >= w || !mem[qj * w + qi]) continue;
+                        acc += cur[qj * w + qi] - cur[j * w + i];
+                    }
+                nxt[j * w + i] = cur[j * w + i] + a * acc;
+            }
+        double *tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+    }
+    return cur[t * w + t];
+}
+
+void orc_diffuse_cone(int s, int k, const int32_t *offs, int r, uint64_t seed, double a, const int64_t *xy,
+                      int64_t count, int t, double *out)
+{
+    int w = 2 * t + 1;
+#pragma omp parallel
+    {
+        uint8_t *mem = (uint8_t *)malloc((size_t)w * w);
+        double *buf = (double *)malloc((size_t)2 * w * w * sizeof(double));
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t i = 0; i < count; ++i)
+            out[i] = diffuse_cone_one(s, k, offs, r, seed, a, xy[2 * i], xy[2 * i + 1], t, mem, buf, buf + w * w);
+        free(mem);
+        free(buf);
+    }
+}
+
 /* Neighbour table for repeated diffusion steps: nb[8c+j] = compact index of
    the j-th Moore neighbour (raster order dy, dx) or -1.  Same maps as above,
    evaluated once. */

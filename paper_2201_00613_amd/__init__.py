@@ -9,12 +9,14 @@ from __future__ import annotations
 
 import ctypes
 
-from ._lib import (HOLE, IMPL_AUTO, IMPL_CELL, IMPL_TILE, LAYOUT_COMPACT, LAYOUT_EXPANDED, Info, SqueezeError,
-                   check, lib)
+from ._lib import (BF16, F32, HOLE, IMPL_AUTO, IMPL_CELL, IMPL_TILE, IMPL_XTILE, LAYOUT_COMPACT, LAYOUT_EXPANDED,
+                   MASS_WORK_DOUBLES, ROUND_NEAREST_EVEN, ROUND_STOCHASTIC, Diffusion, Info, SqueezeError, check, lib)
 
 __all__ = ["Fractal", "SqueezeError", "HOLE", "descriptor_check", "IMPLS"]
 
-IMPLS = {"auto": IMPL_AUTO, "cell": IMPL_CELL, "tile": IMPL_TILE}
+IMPLS = {"auto": IMPL_AUTO, "cell": IMPL_CELL, "tile": IMPL_TILE, "xtile": IMPL_XTILE}
+DTYPES = {"f32": F32, "bf16": BF16}
+ROUNDINGS = {"nearest": ROUND_NEAREST_EVEN, "stochastic": ROUND_STOCHASTIC}
 
 
 def _offsets_array(offsets):
@@ -69,6 +71,7 @@ class Fractal:
         self.compact_shape = (info.compact_h, info.compact_w)
         self.has_tile = bool(info.has_tile)
         self.tile_level = info.tile_level
+        self.xtile_level = info.xtile_level
         self.offsets = [tuple(map(int, xy)) for xy in offsets]
 
     def close(self):
@@ -162,3 +165,59 @@ class Fractal:
         with dev:
             check(lib().sqz_expanded_step(self._h, _ptr(src), _ptr(dst), st))
         return dst
+
+    # -- diffusion ------------------------------------------------------------
+    def _diffusion(self, dtype, coef, rounding, impl, seed):
+        return Diffusion(DTYPES[dtype], ROUNDINGS[rounding], coef, IMPLS[impl], seed)
+
+    def _field_dtype(self, dtype):
+        torch = _torch()
+        return torch.float32 if dtype == "f32" else torch.uint16
+
+    def diffuse_step(self, src, dst, coef: float, dtype: str = "f32", step: int = 0, rounding: str = "nearest",
+                     impl: str = "auto", seed: int = 0):
+        torch, dev, st = self._ctx()
+        td = self._field_dtype(dtype)
+        self._need(src, td, self.cells, "src")
+        self._need(dst, td, self.cells, "dst")
+        d = self._diffusion(dtype, coef, rounding, impl, seed)
+        with dev:
+            check(lib().sqz_diffuse_step(self._h, ctypes.byref(d), step, _ptr(src), _ptr(dst), st))
+        return dst
+
+    def diffuse_run(self, a, b, steps: int, coef: float, dtype: str = "f32", first_step: int = 0,
+                    rounding: str = "nearest", impl: str = "auto", seed: int = 0):
+        """steps diffusion steps ping-ponging a -> b -> ...; returns the tensor holding the result."""
+        torch, dev, st = self._ctx()
+        td = self._field_dtype(dtype)
+        self._need(a, td, self.cells, "a")
+        self._need(b, td, self.cells, "b")
+        d = self._diffusion(dtype, coef, rounding, impl, seed)
+        with dev:
+            check(lib().sqz_diffuse_run(self._h, ctypes.byref(d), first_step, steps, _ptr(a), _ptr(b), st))
+        return a if steps % 2 == 0 else b
+
+    def mass_f64(self, u, dtype: str = "f32", offset: float = 0.0, work=None):
+        """Binary64 sum of offset + u on the device; returns a 0-d float64 device tensor."""
+        torch, dev, st = self._ctx()
+        self._need(u, self._field_dtype(dtype), self.cells, "u")
+        work = torch.empty(MASS_WORK_DOUBLES, dtype=torch.float64, device=self.device) if work is None else work
+        with dev:
+            check(lib().sqz_mass_f64(self._h, DTYPES[dtype], _ptr(u), offset, _ptr(work), st))
+        return work[0]
+
+    def bf16_encode(self, u, offset: float, out=None):
+        torch, dev, st = self._ctx()
+        self._need(u, torch.float32, self.cells, "u")
+        out = torch.empty(self.cells, dtype=torch.uint16, device=self.device) if out is None else out
+        with dev:
+            check(lib().sqz_bf16_encode(self._h, _ptr(u), offset, _ptr(out), st))
+        return out
+
+    def bf16_decode(self, b, offset: float, out=None):
+        torch, dev, st = self._ctx()
+        self._need(b, torch.uint16, self.cells, "b")
+        out = torch.empty(self.cells, dtype=torch.float32, device=self.device) if out is None else out
+        with dev:
+            check(lib().sqz_bf16_decode(self._h, _ptr(b), offset, _ptr(out), st))
+        return out

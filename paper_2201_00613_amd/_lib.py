@@ -11,7 +11,10 @@ LIB_PATH = os.path.join(_HERE, "libsqueeze.so")
 OK, ERR_INVALID, ERR_RANGE, ERR_NOMEM, ERR_HIP, ERR_UNSUPPORTED = range(6)
 HOLE = (1 << 64) - 1
 LAYOUT_COMPACT, LAYOUT_EXPANDED = 0, 1
-IMPL_AUTO, IMPL_CELL, IMPL_TILE = 0, 1, 2
+IMPL_AUTO, IMPL_CELL, IMPL_TILE, IMPL_XTILE = 0, 1, 2, 3
+F32, BF16 = 0, 1
+ROUND_NEAREST_EVEN, ROUND_STOCHASTIC = 0, 1
+MASS_WORK_DOUBLES = 1025
 
 
 class SqueezeError(RuntimeError):
@@ -25,8 +28,13 @@ class Info(ctypes.Structure):
         ("s", ctypes.c_int32), ("k", ctypes.c_int32), ("r", ctypes.c_int32),
         ("tile_level", ctypes.c_int32), ("n", ctypes.c_int64), ("cells", ctypes.c_uint64),
         ("compact_w", ctypes.c_uint64), ("compact_h", ctypes.c_uint64),
-        ("has_tile", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("has_tile", ctypes.c_int32), ("xtile_level", ctypes.c_int32),
     ]
+
+
+class Diffusion(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int), ("rounding", ctypes.c_int), ("coef", ctypes.c_float),
+                ("impl", ctypes.c_int), ("seed", ctypes.c_uint64)]
 
 
 _lib = None
@@ -52,6 +60,16 @@ SIGNATURES = {
     "sqz_compact_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                        ctypes.c_void_p]),
     "sqz_expanded_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "sqz_diffuse_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Diffusion), ctypes.c_uint64, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p]),
+    "sqz_diffuse_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Diffusion), ctypes.c_uint64, ctypes.c_int32,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "sqz_mass_f64": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
+                                    ctypes.c_void_p]),
+    "sqz_bf16_encode": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_float, ctypes.c_void_p,
+                                       ctypes.c_void_p]),
+    "sqz_bf16_decode": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_float, ctypes.c_void_p,
+                                       ctypes.c_void_p]),
     "sqz_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "sqz_last_error": (ctypes.c_char_p, []),
 }

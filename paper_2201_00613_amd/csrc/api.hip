@@ -179,6 +179,39 @@ sqz_status build_map_params(const FractalHost &F, int level, MapParams &P, void 
     return SQZ_OK;
 }
 
+// Plain host maps of the pattern at a given level (local coordinates), used to
+// build the tiled kernels' tables: lambda as a digit sum, nu as a level scan.
+void host_lambda(const FractalHost &F, int level, uint64_t c, int64_t &x, int64_t &y)
+{
+    int64_t px = 0, py = 0, sp = 1;
+    for (int mu = 1; mu <= level; ++mu) {
+        const int b = (int)(c % (uint64_t)F.k);
+        c /= (uint64_t)F.k;
+        px += F.ox[b] * sp;
+        py += F.oy[b] * sp;
+        sp *= F.s;
+    }
+    x = px;
+    y = py;
+}
+
+int64_t host_nu(const FractalHost &F, int level, int64_t x, int64_t y)
+{
+    int64_t side = 1;
+    for (int i = 0; i < level; ++i) side *= F.s;
+    if (x < 0 || y < 0 || x >= side || y >= side) return -1;
+    int64_t c = 0, kp = 1;
+    for (int mu = 1; mu <= level; ++mu) {
+        const int j = F.hnu[(int)(x % F.s) + F.s * (int)(y % F.s)];
+        if (j < 0) return -1;
+        c += j * kp;
+        kp *= F.k;
+        x /= F.s;
+        y /= F.s;
+    }
+    return c;
+}
+
 }  // namespace sqz
 
 using namespace sqz;
@@ -276,13 +309,14 @@ sqz_status sqz_fractal_create(int32_t s, int32_t k, const int32_t *offsets_xy, i
     }
     f->h.tile_kind = tile_kind_for(f->h);
     f->h.tile = nullptr;
-    if (f->h.tile_kind) {
-        st = tile_prepare(f->h);
-        if (st != SQZ_OK) {
-            (void)hipFree(f->h.d_tables);
-            delete f;
-            return st;
-        }
+    f->h.xtile = nullptr;
+    if (f->h.tile_kind) st = tile_prepare(f->h);
+    if (st == SQZ_OK) st = xtile_prepare(f->h);
+    if (st != SQZ_OK) {
+        tile_release(f->h);
+        (void)hipFree(f->h.d_tables);
+        delete f;
+        return st;
     }
     *out = f;
     return SQZ_OK;
@@ -292,6 +326,7 @@ void sqz_fractal_destroy(sqz_fractal *f)
 {
     if (!f) return;
     tile_release(f->h);
+    xtile_release(f->h);
     if (f->h.d_tables) (void)hipFree(f->h.d_tables);
     delete f;
 }
@@ -302,6 +337,7 @@ sqz_status sqz_fractal_info(const sqz_fractal *f, sqz_info *out)
     fill_info(f->h, out);
     out->has_tile = f->h.tile_kind != 0;
     out->tile_level = tile_level_of(f->h);
+    out->xtile_level = xtile_level_of(f->h);
     return SQZ_OK;
 }
 
@@ -359,11 +395,13 @@ sqz_status sqz_fill_uniform(const sqz_fractal *f, uint64_t seed, float *d_u, voi
     return launch_fill_uniform(f->h.P, seed, d_u, (hipStream_t)stream);
 }
 
-static bool overlap(const void *a, const void *b, uint64_t bytes)
+static bool ranges_overlap(const void *a, uint64_t na, const void *b, uint64_t nb)
 {
     uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
-    return x < y + bytes && y < x + bytes;
+    return x < y + nb && y < x + na;
 }
+
+static bool overlap(const void *a, const void *b, uint64_t bytes) { return ranges_overlap(a, bytes, b, bytes); }
 
 sqz_status sqz_compact_step_impl(const sqz_fractal *f, sqz_impl impl, const uint8_t *d_in, uint8_t *d_out,
                                  void *stream)
@@ -373,17 +411,22 @@ sqz_status sqz_compact_step_impl(const sqz_fractal *f, sqz_impl impl, const uint
     if (!d_in || !d_out) return set_error(SQZ_ERR_INVALID, "NULL buffer");
     if (overlap(d_in, d_out, f->h.N)) return set_error(SQZ_ERR_INVALID, "d_in and d_out overlap");
     hipStream_t s = (hipStream_t)stream;
+    const bool aligned = !(((uintptr_t)d_in | (uintptr_t)d_out) & 15);
     switch (impl) {
     case SQZ_IMPL_AUTO:
-        // the tiled kernel moves 16-byte words; unaligned buffers take the thread-level path
-        if (f->h.tile_kind && !(((uintptr_t)d_in | (uintptr_t)d_out) & 15)) return launch_life_tile(f->h, d_in, d_out, s);
+        // the bit-sliced tiled kernel moves 16-byte words; unaligned buffers skip it
+        if (f->h.tile_kind && aligned) return launch_life_tile(f->h, d_in, d_out, s);
+        if (f->h.xtile) return launch_life_xtile(f->h, d_in, d_out, s);
         return launch_life_cell(f->h.P, d_in, d_out, s);
     case SQZ_IMPL_CELL:
         return launch_life_cell(f->h.P, d_in, d_out, s);
     case SQZ_IMPL_TILE:
         if (!f->h.tile_kind)
-            return set_error(SQZ_ERR_UNSUPPORTED, "no tiled kernel for this replica pattern and level");
+            return set_error(SQZ_ERR_UNSUPPORTED, "no bit-sliced tiled kernel for this replica pattern and level");
         return launch_life_tile(f->h, d_in, d_out, s);
+    case SQZ_IMPL_XTILE:
+        if (!f->h.xtile) return set_error(SQZ_ERR_UNSUPPORTED, "no expanded tile fits this fractal");
+        return launch_life_xtile(f->h, d_in, d_out, s);
     }
     return set_error(SQZ_ERR_INVALID, "unknown implementation %d", (int)impl);
 }
@@ -420,6 +463,78 @@ sqz_status sqz_expanded_step(const sqz_fractal *f, const uint8_t *d_in, uint8_t 
     if (!d_in || !d_out) return set_error(SQZ_ERR_INVALID, "NULL buffer");
     if (overlap(d_in, d_out, n * n)) return set_error(SQZ_ERR_INVALID, "d_in and d_out overlap");
     return launch_life_bb(f->h, d_in, d_out, (hipStream_t)stream);
+}
+
+static sqz_status check_diffusion(const sqz_fractal *f, const sqz_diffusion *d)
+{
+    sqz_status st = check_handle(f);
+    if (st != SQZ_OK) return st;
+    if (!d) return set_error(SQZ_ERR_INVALID, "diffusion parameters are NULL");
+    if (d->dtype != SQZ_F32 && d->dtype != SQZ_BF16) return set_error(SQZ_ERR_INVALID, "unknown dtype %d", (int)d->dtype);
+    if (d->rounding != SQZ_ROUND_NEAREST_EVEN && d->rounding != SQZ_ROUND_STOCHASTIC)
+        return set_error(SQZ_ERR_INVALID, "unknown rounding %d", (int)d->rounding);
+    if (!(d->coef >= 0.0f && d->coef <= 0.125f)) return set_error(SQZ_ERR_INVALID, "coef=%g outside [0, 1/8]", d->coef);
+    if (d->impl != SQZ_IMPL_AUTO && d->impl != SQZ_IMPL_CELL && d->impl != SQZ_IMPL_XTILE)
+        return set_error(SQZ_ERR_INVALID, "diffusion implementation %d is not AUTO, CELL or XTILE", (int)d->impl);
+    if (d->impl == SQZ_IMPL_XTILE && !f->h.xtile) return set_error(SQZ_ERR_UNSUPPORTED, "no expanded tile fits this fractal");
+    return SQZ_OK;
+}
+
+static size_t dtype_size(sqz_dtype t) { return t == SQZ_F32 ? 4 : 2; }
+
+sqz_status sqz_diffuse_step(const sqz_fractal *f, const sqz_diffusion *d, uint64_t step, const void *d_in, void *d_out,
+                            void *stream)
+{
+    sqz_status st = check_diffusion(f, d);
+    if (st != SQZ_OK) return st;
+    if (!d_in || !d_out) return set_error(SQZ_ERR_INVALID, "NULL buffer");
+    if (overlap(d_in, d_out, f->h.N * dtype_size(d->dtype))) return set_error(SQZ_ERR_INVALID, "d_in and d_out overlap");
+    return launch_diffuse(f->h, d->dtype, d->coef, d->rounding, d->seed, step, d_in, d_out, d->impl != SQZ_IMPL_CELL,
+                          (hipStream_t)stream);
+}
+
+sqz_status sqz_diffuse_run(const sqz_fractal *f, const sqz_diffusion *d, uint64_t first_step, int32_t steps, void *d_a,
+                           void *d_b, void *stream)
+{
+    sqz_status st = check_diffusion(f, d);
+    if (st != SQZ_OK) return st;
+    if (steps < 0) return set_error(SQZ_ERR_INVALID, "steps < 0");
+    if (!d_a || !d_b) return set_error(SQZ_ERR_INVALID, "NULL buffer");
+    if (overlap(d_a, d_b, f->h.N * dtype_size(d->dtype))) return set_error(SQZ_ERR_INVALID, "d_a and d_b overlap");
+    for (int32_t i = 0; i < steps; ++i) {
+        st = launch_diffuse(f->h, d->dtype, d->coef, d->rounding, d->seed, first_step + (uint64_t)i, (i & 1) ? d_b : d_a,
+                            (i & 1) ? d_a : d_b, d->impl != SQZ_IMPL_CELL, (hipStream_t)stream);
+        if (st != SQZ_OK) return st;
+    }
+    return SQZ_OK;
+}
+
+sqz_status sqz_mass_f64(const sqz_fractal *f, sqz_dtype dtype, const void *d_u, double offset, double *d_work,
+                        void *stream)
+{
+    sqz_status st = check_handle(f);
+    if (st != SQZ_OK) return st;
+    if (dtype != SQZ_F32 && dtype != SQZ_BF16) return set_error(SQZ_ERR_INVALID, "unknown dtype %d", (int)dtype);
+    if (!d_u || !d_work) return set_error(SQZ_ERR_INVALID, "NULL buffer");
+    if (ranges_overlap(d_u, f->h.N * dtype_size(dtype), d_work, SQZ_MASS_WORK_DOUBLES * sizeof(double)))
+        return set_error(SQZ_ERR_INVALID, "d_u and d_work overlap");
+    return launch_mass(f->h, dtype, d_u, offset, d_work, (hipStream_t)stream);
+}
+
+sqz_status sqz_bf16_encode(const sqz_fractal *f, const float *d_u, float offset, uint16_t *d_b, void *stream)
+{
+    sqz_status st = check_handle(f);
+    if (st != SQZ_OK) return st;
+    if (!d_u || !d_b) return set_error(SQZ_ERR_INVALID, "NULL buffer");
+    return launch_bf16_convert(f->h, 1, d_u, offset, d_b, (hipStream_t)stream);
+}
+
+sqz_status sqz_bf16_decode(const sqz_fractal *f, const uint16_t *d_b, float offset, float *d_u, void *stream)
+{
+    sqz_status st = check_handle(f);
+    if (st != SQZ_OK) return st;
+    if (!d_u || !d_b) return set_error(SQZ_ERR_INVALID, "NULL buffer");
+    return launch_bf16_convert(f->h, 0, d_u, offset, (uint16_t *)d_b, (hipStream_t)stream);
 }
 
 const char *sqz_status_string(sqz_status st)

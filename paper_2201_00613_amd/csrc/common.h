@@ -158,7 +158,8 @@ __device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t i)
 // ---------------------------------------------------------------------------
 // Host-side fractal handle.
 // ---------------------------------------------------------------------------
-struct TileConfig;  // defined in life_tile.hip
+struct TileConfig;   // defined in life_tile.hip
+struct XTileConfig;  // defined in xtile.hip
 
 struct FractalHost {
     int32_t s, k, r;
@@ -172,12 +173,15 @@ struct FractalHost {
     // tiled stencil (patterns with a specialised kernel), built on demand
     int tile_kind;                // 0 = none
     TileConfig *tile;
+    XTileConfig *xtile;           // expanded-tile kernels (any pattern), null if none
 };
 
 // Host helpers (api.cpp)
 sqz_status set_error(sqz_status st, const char *fmt, ...);
 sqz_status hip_error(hipError_t e, const char *what);
 sqz_status build_map_params(const FractalHost &F, int level, MapParams &P, void **d_mem);
+void host_lambda(const FractalHost &F, int level, uint64_t c, int64_t &x, int64_t &y);
+int64_t host_nu(const FractalHost &F, int level, int64_t x, int64_t y);  // -1 for holes / outside
 
 // Kernel launchers (maps.hip)
 sqz_status launch_lambda(const MapParams &P, const uint64_t *idx, int64_t count, int32_t *xy,
@@ -197,6 +201,18 @@ int tile_kind_for(const FractalHost &F);
 sqz_status tile_prepare(FractalHost &F);
 void tile_release(FractalHost &F);
 int32_t tile_level_of(const FractalHost &F);
+
+// Expanded-tile kernels (xtile.hip)
+sqz_status xtile_prepare(FractalHost &F);
+void xtile_release(FractalHost &F);
+int32_t xtile_level_of(const FractalHost &F);
+sqz_status launch_life_xtile(const FractalHost &F, const uint8_t *in, uint8_t *out, hipStream_t st);
+sqz_status launch_diffuse(const FractalHost &F, int dtype, float coef, int rounding, uint64_t seed, uint64_t step,
+                          const void *in, void *out, int use_tile, hipStream_t st);
+sqz_status launch_mass(const FractalHost &F, int dtype, const void *u, double offset, double *work, hipStream_t st);
+sqz_status launch_bf16_convert(const FractalHost &F, int encode, const float *u, float offset, uint16_t *b,
+                               hipStream_t st);
+int mass_grid();
 sqz_status launch_life_tile(const FractalHost &F, const uint8_t *in, uint8_t *out, hipStream_t st);
 
 }  // namespace sqz

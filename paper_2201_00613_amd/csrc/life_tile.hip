@@ -477,38 +477,6 @@ bool matches(const FractalHost &F)
     return true;
 }
 
-// plain host maps of the pattern at a given level (local coordinates)
-void host_lambda(const FractalHost &F, int level, uint64_t c, int64_t &x, int64_t &y)
-{
-    int64_t px = 0, py = 0, sp = 1;
-    for (int mu = 1; mu <= level; ++mu) {
-        const int b = (int)(c % (uint64_t)F.k);
-        c /= (uint64_t)F.k;
-        px += F.ox[b] * sp;
-        py += F.oy[b] * sp;
-        sp *= F.s;
-    }
-    x = px;
-    y = py;
-}
-
-int64_t host_nu(const FractalHost &F, int level, int64_t x, int64_t y)
-{
-    int64_t side = 1;
-    for (int i = 0; i < level; ++i) side *= F.s;
-    if (x < 0 || y < 0 || x >= side || y >= side) return -1;
-    int64_t c = 0, kp = 1;
-    for (int mu = 1; mu <= level; ++mu) {
-        const int j = F.hnu[(int)(x % F.s) + F.s * (int)(y % F.s)];
-        if (j < 0) return -1;
-        c += j * kp;
-        kp *= F.k;
-        x /= F.s;
-        y /= F.s;
-    }
-    return c;
-}
-
 template <class Pat>
 sqz_status prepare(FractalHost &F)
 {

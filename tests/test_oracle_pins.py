@@ -377,3 +377,14 @@ def test_diffusion_single_step_forms_agree(oracle_lib):
     assert np.array_equal(F.diffuse_compact(u, 0.1), F.diffuse_steps(u, 0.1, 1))
     ones = np.full(F.N, 0.375)
     assert (F.diffuse_compact(ones, 0.1) == 0.375).all()
+
+
+@pytest.mark.parametrize("name,r,t", [("carpet", 4, 3), ("carpet", 5, 7), ("vicsek", 5, 4), ("triangle", 7, 5)])
+def test_diffusion_light_cone_matches_full_field(oracle_lib, name, r, t):
+    F = frac(oracle_lib, name, r)
+    a, seed = 0.1, 21
+    full = F.diffuse_steps(F.fill_uniform_compact(seed), a, t)
+    rng = np.random.default_rng(3)
+    cs = rng.choice(F.N, size=min(F.N, 2000), replace=False)
+    got = F.diffuse_cone(seed, a, F.lam(cs), t)
+    assert np.allclose(got, full[cs], rtol=0, atol=1e-13)
