@@ -236,6 +236,40 @@ SQZ_API sqz_status sqz_bf16_encode(const sqz_fractal *f, const float *d_u, float
 SQZ_API sqz_status sqz_bf16_decode(const sqz_fractal *f, const uint16_t *d_b, float offset, float *d_u,
                                    void *stream);
 
+/*
+ * Batched Life: `count` independent fractals (handles may repeat and may mix
+ * replica patterns and levels) advanced together, one persistent launch per
+ * step (the batched form of the method's data-parallel step).  The handles
+ * must outlive the batch and live on the current device.  Instance i owns
+ * bytes [offsets[i], offsets[i] + cells_i) of one state buffer of
+ * offsets[count] bytes (sqz_batch_layout); the gaps are padding.  A batch is
+ * not thread-safe: calls on one batch must not overlap.
+ */
+typedef struct sqz_batch sqz_batch;
+
+SQZ_API sqz_status sqz_batch_create(int32_t count, const sqz_fractal *const *fractals, sqz_batch **out);
+
+SQZ_API void sqz_batch_destroy(sqz_batch *b);
+
+/* offsets: count + 1 host entries (may be NULL); total_cells: sum of cells_i (may be NULL). */
+SQZ_API sqz_status sqz_batch_layout(const sqz_batch *b, uint64_t *offsets, uint64_t *total_cells);
+
+/* Instance i gets sqz_fill_bernoulli(fractal_i, seeds[i], p, COMPACT).  seeds: host array of count. */
+SQZ_API sqz_status sqz_batch_fill_bernoulli(const sqz_batch *b, const uint64_t *seeds, double p, uint8_t *d_state,
+                                            void *stream);
+
+/* One step of every instance: one kernel launch.  Buffers 16-byte aligned, non-overlapping. */
+SQZ_API sqz_status sqz_batch_step(const sqz_batch *b, const uint8_t *d_in, uint8_t *d_out, void *stream);
+
+/* `steps` steps ping-ponging from d_a (result in d_a if steps is even, else d_b).  For steps >= 2 the
+ * launches are captured once into a hipGraph (cached for the same buffers and step count) and replayed. */
+SQZ_API sqz_status sqz_batch_run(sqz_batch *b, uint8_t *d_a, uint8_t *d_b, int32_t steps, void *stream);
+
+/* Time candidate grid sizes (workgroups per compute unit) on the given buffers (their contents are
+ * advanced by a few steps) and keep the fastest for this batch and for later batches of the same
+ * composition in this process.  *wg_per_cu (may be NULL) receives the choice. */
+SQZ_API sqz_status sqz_batch_autotune(sqz_batch *b, uint8_t *d_a, uint8_t *d_b, void *stream, int32_t *wg_per_cu);
+
 /* Static text for a status code. */
 SQZ_API const char *sqz_status_string(sqz_status st);
 

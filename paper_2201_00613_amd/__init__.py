@@ -221,3 +221,90 @@ class Fractal:
         with dev:
             check(lib().sqz_bf16_decode(self._h, _ptr(b), offset, _ptr(out), st))
         return out
+
+
+class Batch:
+    """Many fractals advanced together: one persistent launch per step (sqz_batch_*).
+
+    The state is one uint8 tensor of ``total_bytes``; instance i's cells are the
+    slice ``[offsets[i], offsets[i] + fractals[i].cells)`` (see ``instance``).
+    """
+
+    def __init__(self, fractals):
+        torch = _torch()
+        self.fractals = list(fractals)
+        n = len(self.fractals)
+        arr = (ctypes.c_void_p * n)(*[f._h.value for f in self.fractals])
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.fractals[0].device):
+            check(lib().sqz_batch_create(n, arr, ctypes.byref(h)))
+        self._h = h
+        offs = (ctypes.c_uint64 * (n + 1))()
+        total = ctypes.c_uint64()
+        check(lib().sqz_batch_layout(h, offs, ctypes.byref(total)))
+        self.offsets = [int(v) for v in offs]
+        self.total_bytes = self.offsets[-1]
+        self.total_cells = int(total.value)
+        self.device = self.fractals[0].device
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sqz_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _ctx(self):
+        torch = _torch()
+        return torch, torch.cuda.device(self.device), _stream(torch, self.device)
+
+    def _need(self, t, name):
+        torch = _torch()
+        if t.device != self.device or t.dtype != torch.uint8 or not t.is_contiguous() or t.numel() != self.total_bytes:
+            raise ValueError(f"{name}: need a contiguous uint8 tensor of {self.total_bytes} bytes on {self.device}")
+
+    def empty_state(self):
+        torch = _torch()
+        return torch.zeros(self.total_bytes, dtype=torch.uint8, device=self.device)
+
+    def instance(self, state, i: int):
+        return state[self.offsets[i]:self.offsets[i] + self.fractals[i].cells]
+
+    def fill_bernoulli(self, seeds, p: float, out=None):
+        torch, dev, st = self._ctx()
+        out = self.empty_state() if out is None else out
+        self._need(out, "out")
+        arr = (ctypes.c_uint64 * len(self.fractals))(*[int(s) for s in seeds])
+        with dev:
+            check(lib().sqz_batch_fill_bernoulli(self._h, arr, p, _ptr(out), st))
+        return out
+
+    def step(self, src, dst):
+        torch, dev, st = self._ctx()
+        self._need(src, "src")
+        self._need(dst, "dst")
+        with dev:
+            check(lib().sqz_batch_step(self._h, _ptr(src), _ptr(dst), st))
+        return dst
+
+    def run(self, a, b, steps: int):
+        """steps steps ping-ponging a -> b -> ... (hipGraph replay for steps >= 2)."""
+        torch, dev, st = self._ctx()
+        self._need(a, "a")
+        self._need(b, "b")
+        with dev:
+            check(lib().sqz_batch_run(self._h, _ptr(a), _ptr(b), steps, st))
+        return a if steps % 2 == 0 else b
+
+    def autotune(self, a, b) -> int:
+        torch, dev, st = self._ctx()
+        self._need(a, "a")
+        self._need(b, "b")
+        w = ctypes.c_int32()
+        with dev:
+            check(lib().sqz_batch_autotune(self._h, _ptr(a), _ptr(b), st, ctypes.byref(w)))
+        return int(w.value)

@@ -96,3 +96,17 @@ def check(status: int) -> None:
     if status != OK:
         msg = lib().sqz_last_error().decode(errors="replace")
         raise SqueezeError(status, msg)
+
+
+SIGNATURES.update({
+    "sqz_batch_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "sqz_batch_destroy": (None, [ctypes.c_void_p]),
+    "sqz_batch_layout": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
+    "sqz_batch_fill_bernoulli": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
+                                                ctypes.c_void_p]),
+    "sqz_batch_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "sqz_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                     ctypes.c_void_p]),
+    "sqz_batch_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.POINTER(ctypes.c_int32)]),
+})

@@ -18,6 +18,16 @@ struct sqz_fractal {
     size_t device_mem;  // total memory of the device the handle lives on
 };
 
+struct sqz_batch {
+    sqz::BatchHost *h;
+    std::vector<const sqz_fractal *> fractals;
+    size_t device_mem;
+};
+
+namespace sqz {
+const FractalHost &fractal_host_of(const sqz_fractal *f) { return f->h; }
+}  // namespace sqz
+
 namespace sqz {
 
 static thread_local char g_err[512];
@@ -535,6 +545,93 @@ sqz_status sqz_bf16_decode(const sqz_fractal *f, const uint16_t *d_b, float offs
     if (st != SQZ_OK) return st;
     if (!d_u || !d_b) return set_error(SQZ_ERR_INVALID, "NULL buffer");
     return launch_bf16_convert(f->h, 0, d_u, offset, (uint16_t *)d_b, (hipStream_t)stream);
+}
+
+sqz_status sqz_batch_create(int32_t count, const sqz_fractal *const *fractals, sqz_batch **out)
+{
+    if (!out || !fractals) return set_error(SQZ_ERR_INVALID, "NULL argument");
+    if (count < 1) return set_error(SQZ_ERR_INVALID, "count=%d < 1", count);
+    for (int32_t i = 0; i < count; ++i) {
+        sqz_status st = check_handle(fractals[i]);
+        if (st != SQZ_OK) return st;
+    }
+    sqz_batch *b = new (std::nothrow) sqz_batch;
+    if (!b) return set_error(SQZ_ERR_NOMEM, "host allocation failed");
+    b->fractals.assign(fractals, fractals + count);
+    b->device_mem = fractals[0]->device_mem;
+    sqz_status st = batch_create(fractals, count, &b->h);
+    if (st != SQZ_OK) {
+        delete b;
+        return st;
+    }
+    *out = b;
+    return SQZ_OK;
+}
+
+void sqz_batch_destroy(sqz_batch *b)
+{
+    if (!b) return;
+    batch_destroy(b->h);
+    delete b;
+}
+
+sqz_status sqz_batch_layout(const sqz_batch *b, uint64_t *offsets, uint64_t *total_cells)
+{
+    if (!b) return set_error(SQZ_ERR_INVALID, "batch is NULL");
+    const int32_t n = batch_count(b->h);
+    if (offsets)
+        for (int32_t i = 0; i <= n; ++i) offsets[i] = i < n ? batch_offset(b->h, i) : batch_total_bytes(b->h);
+    if (total_cells) *total_cells = batch_total_cells(b->h);
+    return SQZ_OK;
+}
+
+static sqz_status check_batch_buffers(const sqz_batch *b, const void *x, const void *y)
+{
+    if (!b) return set_error(SQZ_ERR_INVALID, "batch is NULL");
+    sqz_status st = check_handle(b->fractals[0]);
+    if (st != SQZ_OK) return st;
+    if (!x || !y) return set_error(SQZ_ERR_INVALID, "NULL buffer");
+    if (((uintptr_t)x | (uintptr_t)y) & 15) return set_error(SQZ_ERR_INVALID, "batch buffers must be 16-byte aligned");
+    if (overlap(x, y, batch_total_bytes(b->h))) return set_error(SQZ_ERR_INVALID, "batch buffers overlap");
+    return SQZ_OK;
+}
+
+sqz_status sqz_batch_fill_bernoulli(const sqz_batch *b, const uint64_t *seeds, double p, uint8_t *d_state, void *stream)
+{
+    if (!b || !seeds || !d_state) return set_error(SQZ_ERR_INVALID, "NULL argument");
+    if (((uintptr_t)d_state) & 15) return set_error(SQZ_ERR_INVALID, "batch buffer must be 16-byte aligned");
+    const int32_t n = batch_count(b->h);
+    for (int32_t i = 0; i < n; ++i) {
+        sqz_status st = sqz_fill_bernoulli(b->fractals[i], seeds[i], p, SQZ_LAYOUT_COMPACT,
+                                           d_state + batch_offset(b->h, i), stream);
+        if (st != SQZ_OK) return st;
+    }
+    return SQZ_OK;
+}
+
+sqz_status sqz_batch_step(const sqz_batch *b, const uint8_t *d_in, uint8_t *d_out, void *stream)
+{
+    sqz_status st = check_batch_buffers(b, d_in, d_out);
+    if (st != SQZ_OK) return st;
+    return batch_step(b->h, d_in, d_out, (hipStream_t)stream);
+}
+
+sqz_status sqz_batch_run(sqz_batch *b, uint8_t *d_a, uint8_t *d_b, int32_t steps, void *stream)
+{
+    sqz_status st = check_batch_buffers(b, d_a, d_b);
+    if (st != SQZ_OK) return st;
+    if (steps < 0) return set_error(SQZ_ERR_INVALID, "steps < 0");
+    return batch_run(b->h, d_a, d_b, steps, (hipStream_t)stream);
+}
+
+sqz_status sqz_batch_autotune(sqz_batch *b, uint8_t *d_a, uint8_t *d_b, void *stream, int32_t *wg_per_cu)
+{
+    sqz_status st = check_batch_buffers(b, d_a, d_b);
+    if (st != SQZ_OK) return st;
+    unsigned best = 0;
+    st = batch_autotune(b->h, d_a, d_b, (hipStream_t)stream, &best);
+    if (st == SQZ_OK && wg_per_cu) *wg_per_cu = (int32_t)best;
+    return st;
 }
 
 const char *sqz_status_string(sqz_status st)

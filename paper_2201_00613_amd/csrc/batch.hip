@@ -1,0 +1,445 @@
+// Batched Life: many independent fractals of mixed replica pattern and level
+// advanced together, one persistent launch per step.
+//
+// Every instance owns a 256-byte aligned range of one state buffer.  Its work
+// is a list of units: level-M tiles for the bit-sliced (triangle, Vicsek) and
+// expanded-tile (any pattern) paths, runs of 4096 cells for the thread-level
+// path (instances too small to tile).  The units of all instances form one
+// sequence; workgroup b takes the units whose first cell falls in the b-th
+// equal share of all cells, so the split is balanced by cells and each
+// workgroup walks adjacent tiles of one or two instances.  The tile bodies are
+// the same device functions the single-fractal kernels use, with LDS carved
+// from one dynamic buffer; the expanded-tile tables are reloaded only when a
+// workgroup moves to an instance with a different tile configuration.
+//
+// Runs of several steps are captured once into a hipGraph (kernel nodes only)
+// and replayed; an autotuner times candidate grid sizes on the caller's
+// buffers and keeps the fastest, cached per batch composition.
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "tile_device.h"
+#include "xtile_device.h"
+
+struct sqz_fractal;  // api.hip
+
+namespace sqz {
+
+enum BatchKind : uint32_t { kBTri = 1, kBTriPaper = 2, kBVicsek = 3, kBX66 = 4, kBX83 = 5, kBXAny = 6, kBCell = 7 };
+
+constexpr uint32_t kCellUnit = 4096;
+
+struct BatchInst {
+    uint32_t kind, xcfg;   // xcfg: expanded-tile configuration id (LDS tables)
+    uint64_t base;         // byte offset of the instance in the state buffer
+    uint64_t units;        // work units
+    uint64_t unit_cells;   // cells per unit
+    uint64_t cell_start;   // first cell of the instance in the batch's cell sequence
+    uint64_t cells;
+    TileArgs tile;
+    XArgs x;
+    MapParams P;
+};
+
+struct BatchArgs {
+    const BatchInst *inst;
+    const uint64_t *cell_start;  // ninst + 1 entries
+    uint32_t ninst;
+    uint64_t total_cells;
+};
+
+namespace {
+
+__device__ __forceinline__ void life_cell_unit(const MapParams &P, const uint8_t *in, uint8_t *out, uint64_t unit)
+{
+    const uint64_t c0 = unit * kCellUnit;
+    for (uint32_t k = threadIdx.x; k < kCellUnit; k += 256) {
+        const uint64_t c = c0 + k;
+        if (c >= P.N) break;
+        uint32_t x, y;
+        if (P.N <= 0x100000000ull)
+            lam_map32(P, (uint32_t)c, x, y);
+        else
+            lam_map64(P, c, x, y);
+        uint32_t cnt = 0;
+#pragma unroll
+        for (int j = 0; j < 9; ++j) {
+            if (j == 4) continue;
+            const uint64_t q = nu_map(P, (int32_t)x + j % 3 - 1, (int32_t)y + j / 3 - 1);
+            if (q != kHole64) cnt += in[q];
+        }
+        const uint32_t self = in[c];
+        out[c] = (uint8_t)(cnt == 3 || (self && cnt == 2));
+    }
+}
+
+template <class Pat>
+__device__ __forceinline__ void bitsliced_unit(const BatchInst &I, const uint8_t *in, uint8_t *out, uint64_t t,
+                                               unsigned char *smem)
+{
+    using LDS = TileLds<Pat>;
+    uint32_t *s_in = reinterpret_cast<uint32_t *>(smem);
+    uint32_t *s_out = s_in + LDS::IN_WORDS;
+    tile_body<Pat>(I.tile, in, out, t, s_in, s_out);
+}
+
+__global__ void __launch_bounds__(256) k_batch_life(BatchArgs B, const uint8_t *__restrict__ in,
+                                                    uint8_t *__restrict__ out)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint64_t lo = B.total_cells * blockIdx.x / gridDim.x;
+    const uint64_t hi = B.total_cells * (blockIdx.x + 1) / gridDim.x;
+    // instance holding cell lo (uniform binary search)
+    uint32_t a = 0, b = B.ninst;
+    while (b - a > 1) {
+        const uint32_t m = (a + b) / 2;
+        if (B.cell_start[m] <= lo)
+            a = m;
+        else
+            b = m;
+    }
+    uint32_t i = a;
+    uint64_t j = 0;
+    {
+        const BatchInst &I = B.inst[i];
+        j = (lo - I.cell_start + I.unit_cells - 1) / I.unit_cells;
+    }
+    int loaded = -1;  // expanded-tile configuration currently in LDS
+    const XOp op{};
+    while (i < B.ninst) {
+        const BatchInst &I = B.inst[i];
+        if (j >= I.units) {
+            ++i;
+            j = 0;
+            continue;
+        }
+        if (I.cell_start + j * I.unit_cells >= hi) break;
+        const uint8_t *ii = in + I.base;
+        uint8_t *oo = out + I.base;
+        __syncthreads();  // the previous unit's LDS reads are done
+        switch (I.kind) {
+        case kBTri:
+            loaded = -1;
+            bitsliced_unit<PatTriangle>(I, ii, oo, j, smem);
+            break;
+        case kBTriPaper:
+            loaded = -1;
+            bitsliced_unit<PatTrianglePaper>(I, ii, oo, j, smem);
+            break;
+        case kBVicsek:
+            loaded = -1;
+            bitsliced_unit<PatVicsek>(I, ii, oo, j, smem);
+            break;
+        case kBX66:
+        case kBX83:
+        case kBXAny: {
+            const XLds<XLife> S(smem, I.x);
+            if (loaded != (int)I.xcfg) {
+                xtile_setup<XLife>(I.x, S);
+                loaded = (int)I.xcfg;
+            }
+            if (I.kind == kBX83)
+                xtile_body<XLife, 83>(I.x, ii, oo, j, op, S);
+            else if (I.kind == kBX66)
+                xtile_body<XLife, 66>(I.x, ii, oo, j, op, S);
+            else
+                xtile_body<XLife, 0>(I.x, ii, oo, j, op, S);
+            break;
+        }
+        default:
+            life_cell_unit(I.P, ii, oo, j);
+            break;
+        }
+        ++j;
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+struct BatchHost {
+    int device;
+    int cus;
+    std::vector<BatchInst> inst;
+    std::vector<uint64_t> offsets;  // byte offset of each instance; back() = total bytes
+    std::vector<uint64_t> cells;
+    uint64_t total_cells, total_bytes;
+    BatchInst *d_inst;
+    uint64_t *d_cell_start;
+    size_t lds;
+    unsigned wg_per_cu, max_wg_per_cu;
+    std::string key;
+    hipStream_t cap;
+    hipGraphExec_t gexec;
+    const void *g_a, *g_b;
+    int32_t g_steps;
+    void *g_stream;
+};
+
+static std::mutex g_tune_mu;
+static std::map<std::string, unsigned> g_tune_cache;
+
+const FractalHost &fractal_host_of(const sqz_fractal *f);  // api.hip
+
+static uint32_t kind_of(const FractalHost &F)
+{
+    if (F.tile_kind == 1) return kBTri;
+    if (F.tile_kind == 2) return kBTriPaper;
+    if (F.tile_kind == 3) return kBVicsek;
+    if (F.xtile) return F.xtile->P == 83 ? kBX83 : (F.xtile->P == 66 ? kBX66 : kBXAny);
+    return kBCell;
+}
+
+static TileArgs tile_args_from(const FractalHost &F)
+{
+    const TileConfig *T = F.tile;
+    TileArgs A;
+    A.ntiles = T->ntiles;
+    A.N = F.N;
+    A.tile = T->tile;
+    A.nblocks = T->nblocks;
+    A.nthalo = T->nthalo;
+    A.hstride = T->hstride;
+    A.halo_word = T->halo_word;
+    A.block_halo = T->d_block_halo;
+    A.tile_halo = T->d_tile_halo;
+    return A;
+}
+
+template <class Pat>
+static size_t tile_lds() { return (size_t)(TileLds<Pat>::IN_WORDS + TileLds<Pat>::WMAX + 1) * 4; }
+
+static size_t tile_lds_of(const FractalHost &F)
+{
+    switch (F.tile_kind) {
+    case 1: return tile_lds<PatTriangle>();
+    case 2: return tile_lds<PatTrianglePaper>();
+    default: return tile_lds<PatVicsek>();
+    }
+}
+
+sqz_status batch_create(const sqz_fractal *const *fr, int32_t count, BatchHost **out)
+{
+    BatchHost *H = new BatchHost();
+    H->inst.resize(count);
+    H->offsets.resize(count + 1);
+    H->cells.resize(count);
+    hipError_t e = hipGetDevice(&H->device);
+    if (e != hipSuccess) {
+        delete H;
+        return hip_error(e, "hipGetDevice");
+    }
+    hipDeviceProp_t prop;
+    H->cus = hipGetDeviceProperties(&prop, H->device) == hipSuccess ? prop.multiProcessorCount : 256;
+    std::map<std::string, uint32_t> xcfg_ids;
+    std::vector<uint64_t> cell_start(count + 1);
+    uint64_t off = 0, cstart = 0;
+    size_t lds = 0;
+    char buf[64];
+    for (int32_t i = 0; i < count; ++i) {
+        const FractalHost &F = fractal_host_of(fr[i]);
+        if (F.device != H->device) {
+            delete H;
+            return set_error(SQZ_ERR_INVALID, "instance %d lives on device %d, not %d", i, F.device, H->device);
+        }
+        BatchInst &I = H->inst[i];
+        memset(&I, 0, sizeof I);
+        I.kind = kind_of(F);
+        I.base = off;
+        I.cells = F.N;
+        I.cell_start = cstart;
+        I.P = F.P;
+        if (I.kind == kBTri || I.kind == kBTriPaper || I.kind == kBVicsek) {
+            I.tile = tile_args_from(F);
+            I.units = I.tile.ntiles;
+            I.unit_cells = I.tile.tile;
+            lds = std::max(lds, tile_lds_of(F));
+        } else if (I.kind != kBCell) {
+            const XTileConfig *X = F.xtile;
+            I.x = X->base;
+            const size_t need = xt_layout(X->P, X->KM, X->R, 1, false, &I.x);
+            I.x.vec = (X->KM % 16 == 0) ? 1u : 0u;
+            lds = std::max(lds, need);
+            std::string key = std::to_string(F.s) + ":" + std::to_string(X->M);
+            for (int j = 0; j < F.k; ++j) key += "," + std::to_string(F.ox[j]) + "/" + std::to_string(F.oy[j]);
+            auto it = xcfg_ids.find(key);
+            if (it == xcfg_ids.end()) it = xcfg_ids.emplace(key, (uint32_t)xcfg_ids.size()).first;
+            I.xcfg = it->second;
+            // tables are identical for one (pattern, M): use the first instance's copy
+            for (int32_t p = 0; p < i; ++p)
+                if ((H->inst[p].kind == I.kind) && H->inst[p].xcfg == I.xcfg && H->inst[p].kind != kBCell &&
+                    H->inst[p].kind >= kBX66) {
+                    I.x.lam = H->inst[p].x.lam;
+                    I.x.mem_in = H->inst[p].x.mem_in;
+                    I.x.rpos = H->inst[p].x.rpos;
+                    I.x.rinfo = H->inst[p].x.rinfo;
+                    break;
+                }
+            I.units = X->ntiles;
+            I.unit_cells = X->KM;
+        } else {
+            I.units = (F.N + kCellUnit - 1) / kCellUnit;
+            I.unit_cells = kCellUnit;
+        }
+        snprintf(buf, sizeof buf, "%d:%d:%d;", (int)I.kind, F.s, F.r);
+        H->key += buf;
+        H->cells[i] = F.N;
+        cell_start[i] = cstart;
+        H->offsets[i] = off;
+        cstart += F.N;
+        off += (F.N + 255) / 256 * 256;
+    }
+    cell_start[count] = cstart;
+    H->offsets[count] = off;
+    H->total_cells = cstart;
+    H->total_bytes = off;
+    H->lds = std::max<size_t>(lds, 16);
+    H->d_inst = nullptr;
+    H->d_cell_start = nullptr;
+    H->cap = nullptr;
+    H->gexec = nullptr;
+    e = hipMalloc(&H->d_inst, sizeof(BatchInst) * count);
+    if (e == hipSuccess) e = hipMemcpy(H->d_inst, H->inst.data(), sizeof(BatchInst) * count, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&H->d_cell_start, sizeof(uint64_t) * (count + 1));
+    if (e == hipSuccess)
+        e = hipMemcpy(H->d_cell_start, cell_start.data(), sizeof(uint64_t) * (count + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&H->cap, hipStreamNonBlocking);
+    int per_cu = 0;
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_life, 256, H->lds);
+    if (e != hipSuccess) {
+        if (H->d_inst) (void)hipFree(H->d_inst);
+        if (H->d_cell_start) (void)hipFree(H->d_cell_start);
+        if (H->cap) (void)hipStreamDestroy(H->cap);
+        delete H;
+        return hip_error(e, "batch setup");
+    }
+    H->max_wg_per_cu = per_cu < 1 ? 1u : (unsigned)per_cu;
+    H->wg_per_cu = H->max_wg_per_cu;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(H->key);
+        if (it != g_tune_cache.end()) H->wg_per_cu = std::min(it->second, H->max_wg_per_cu);
+    }
+    *out = H;
+    return SQZ_OK;
+}
+
+void batch_destroy(BatchHost *H)
+{
+    if (!H) return;
+    if (H->gexec) (void)hipGraphExecDestroy(H->gexec);
+    if (H->cap) (void)hipStreamDestroy(H->cap);
+    (void)hipFree(H->d_inst);
+    (void)hipFree(H->d_cell_start);
+    delete H;
+}
+
+static sqz_status launch_batch(const BatchHost *H, unsigned wg_per_cu, const uint8_t *in, uint8_t *out, hipStream_t st)
+{
+    BatchArgs A;
+    A.inst = H->d_inst;
+    A.cell_start = H->d_cell_start;
+    A.ninst = (uint32_t)H->inst.size();
+    A.total_cells = H->total_cells;
+    uint64_t grid = (uint64_t)H->cus * wg_per_cu;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_batch_life, dim3((unsigned)grid), dim3(256), H->lds, st, A, in, out);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SQZ_OK : hip_error(e, "batch launch");
+}
+
+sqz_status batch_step(const BatchHost *H, const uint8_t *in, uint8_t *out, hipStream_t st)
+{
+    return launch_batch(H, H->wg_per_cu, in, out, st);
+}
+
+sqz_status batch_run(BatchHost *H, uint8_t *a, uint8_t *b, int32_t steps, hipStream_t st)
+{
+    if (steps == 0) return SQZ_OK;
+    if (steps == 1) return batch_step(H, a, b, st);
+    if (!(H->gexec && H->g_a == a && H->g_b == b && H->g_steps == steps)) {
+        if (H->gexec) {
+            (void)hipGraphExecDestroy(H->gexec);
+            H->gexec = nullptr;
+        }
+        hipError_t e = hipStreamBeginCapture(H->cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_error(e, "hipStreamBeginCapture");
+        sqz_status s2 = SQZ_OK;
+        for (int32_t i = 0; i < steps && s2 == SQZ_OK; ++i)
+            s2 = launch_batch(H, H->wg_per_cu, (i & 1) ? b : a, (i & 1) ? a : b, H->cap);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(H->cap, &g);
+        if (s2 != SQZ_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return s2;
+        }
+        if (e != hipSuccess) return hip_error(e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&H->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            H->gexec = nullptr;
+            return hip_error(e, "hipGraphInstantiate");
+        }
+        H->g_a = a;
+        H->g_b = b;
+        H->g_steps = steps;
+    }
+    hipError_t e = hipGraphLaunch(H->gexec, st);
+    return e == hipSuccess ? SQZ_OK : hip_error(e, "hipGraphLaunch");
+}
+
+sqz_status batch_autotune(BatchHost *H, uint8_t *a, uint8_t *b, hipStream_t st, unsigned *best_out)
+{
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return set_error(SQZ_ERR_HIP, "hipEventCreate failed");
+    unsigned best = H->wg_per_cu;
+    float best_ms = 1e30f;
+    sqz_status st2 = SQZ_OK;
+    for (unsigned w = 1; w <= H->max_wg_per_cu && st2 == SQZ_OK; w = (w < 4 ? w + 1 : w * 2)) {
+        st2 = launch_batch(H, w, a, b, st);  // warm-up
+        if (st2 != SQZ_OK) break;
+        (void)hipEventRecord(e0, st);
+        for (int i = 0; i < 4 && st2 == SQZ_OK; ++i) st2 = launch_batch(H, w, (i & 1) ? b : a, (i & 1) ? a : b, st);
+        (void)hipEventRecord(e1, st);
+        if (hipEventSynchronize(e1) != hipSuccess) {
+            st2 = set_error(SQZ_ERR_HIP, "autotune synchronisation failed");
+            break;
+        }
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = w;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st2 != SQZ_OK) return st2;
+    H->wg_per_cu = best;
+    if (H->gexec) {
+        (void)hipGraphExecDestroy(H->gexec);
+        H->gexec = nullptr;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[H->key] = best;
+    }
+    if (best_out) *best_out = best;
+    return SQZ_OK;
+}
+
+uint64_t batch_total_bytes(const BatchHost *H) { return H->total_bytes; }
+uint64_t batch_offset(const BatchHost *H, int32_t i) { return H->offsets[i]; }
+int32_t batch_count(const BatchHost *H) { return (int32_t)H->inst.size(); }
+unsigned batch_wg_per_cu(const BatchHost *H) { return H->wg_per_cu; }
+uint64_t batch_total_cells(const BatchHost *H) { return H->total_cells; }
+
+}  // namespace sqz

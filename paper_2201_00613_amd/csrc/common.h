@@ -213,6 +213,20 @@ sqz_status launch_mass(const FractalHost &F, int dtype, const void *u, double of
 sqz_status launch_bf16_convert(const FractalHost &F, int encode, const float *u, float offset, uint16_t *b,
                                hipStream_t st);
 int mass_grid();
+
+// Batched Life (batch.hip)
+struct BatchHost;
+sqz_status batch_create(const sqz_fractal *const *fr, int32_t count, BatchHost **out);
+void batch_destroy(BatchHost *H);
+sqz_status batch_step(const BatchHost *H, const uint8_t *in, uint8_t *out, hipStream_t st);
+sqz_status batch_run(BatchHost *H, uint8_t *a, uint8_t *b, int32_t steps, hipStream_t st);
+sqz_status batch_autotune(BatchHost *H, uint8_t *a, uint8_t *b, hipStream_t st, unsigned *best_out);
+uint64_t batch_total_bytes(const BatchHost *H);
+uint64_t batch_offset(const BatchHost *H, int32_t i);
+int32_t batch_count(const BatchHost *H);
+unsigned batch_wg_per_cu(const BatchHost *H);
+uint64_t batch_total_cells(const BatchHost *H);
+const FractalHost &fractal_host_of(const sqz_fractal *f);
 sqz_status launch_life_tile(const FractalHost &F, const uint8_t *in, uint8_t *out, hipStream_t st);
 
 }  // namespace sqz

@@ -1,446 +1,24 @@
-// Block-level Squeeze (Section "Moving from Thread-level to Block-level")
-// for Life on compact storage, bit-sliced.
-//
-// Work decomposition
-//   tile  = a level-M subtree: the contiguous compact range [t K^M, (t+1) K^M).
-//           One workgroup per tile.  The coarse maps (lambda/nu at level r-M)
-//           are evaluated once per tile, ahead of time, to find the few cells of
-//           neighbouring tiles that touch it ("tile halo").
-//   block = a level-J subtree of K^J <= 32 cells, held as one 32-bit word
-//           (bit i = state of the block's cell i).  One lane per block.
-// Inside a tile nothing is mapped per cell: the neighbours of a block's cells
-// are either cells of the same block -- a fixed set of (bit shift, bit mask)
-// moves derived from the replica pattern at compile time -- or one of a fixed
-// set of "block halo" cells of the adjacent blocks, found through a table that
-// is the same for every tile (the micro brute force the paper applies inside a
-// block).  Neighbour counts are summed with bit-sliced full adders over up to
-// eight single-bit layers, then B3/S23 is applied to all cells of the block
-// with a few logic operations.
-//
-// Memory path per tile: coalesced 16-byte loads of the tile's bytes, packed to
-// bits in LDS (pack: a 4-byte dot product with byte weights 1,2,4,8 (then
-// 16..128) turns eight 0/1 bytes into one byte of bits); results are OR-ed into
-// an LDS bit array and written back with coalesced 16-byte stores (unpack:
-// (v * 0x204081) & 0x01010101 spreads four bits over four bytes).  Tile
-// boundaries are not 16-byte aligned: the two edge words of a tile are stored
-// byte by byte, one byte per lane, so neighbouring tiles never overwrite each
-// other.
-#include <utility>
+// Bit-sliced block-level Life kernels (device code in tile_device.h) and
+// their host-side preparation: tile halo slots, block-halo tables, per-tile
+// halo indices.
 #include <vector>
 
-#include "common.h"
+#include "tile_device.h"
 
 namespace sqz {
-
-// ---------------------------------------------------------------------------
-// Replica patterns with a tiled kernel.  Replica j is at (OX[j], OY[j]).
-// ---------------------------------------------------------------------------
-// Build-time knobs (defaults are the tuned values).
-#ifndef SQZ_TRI_TILE_LEVEL
-#define SQZ_TRI_TILE_LEVEL 8
-#endif
-#ifndef SQZ_NT_LOAD
-#define SQZ_NT_LOAD 0
-#endif
-#ifndef SQZ_NT_STORE
-#define SQZ_NT_STORE 0
-#endif
-
-struct PatTriangle {  // Sierpinski triangle, member iff x & y == 0
-    static constexpr int S = 2, K = 3, J = 3, MMAX = SQZ_TRI_TILE_LEVEL;
-    static constexpr int OX[3] = {0, 1, 0};
-    static constexpr int OY[3] = {0, 0, 1};
-};
-struct PatTrianglePaper {  // the paper's orientation: top, middle, right
-    static constexpr int S = 2, K = 3, J = 3, MMAX = SQZ_TRI_TILE_LEVEL;
-    static constexpr int OX[3] = {0, 0, 1};
-    static constexpr int OY[3] = {0, 1, 1};
-};
-struct PatVicsek {  // Vicsek cross
-    static constexpr int S = 3, K = 5, J = 2, MMAX = 6;
-    static constexpr int OX[5] = {1, 0, 1, 2, 1};
-    static constexpr int OY[5] = {0, 1, 1, 1, 2};
-};
-
-constexpr int cpow(int b, int e)
-{
-    int p = 1;
-    for (int i = 0; i < e; ++i) p *= b;
-    return p;
-}
-
-constexpr int kMaxHalo = 16;      // halo cells per block
-constexpr int kMaxTileHalo = 32;  // halo cells per tile (one LDS word of bits)
-constexpr int kBlock = 256;
-
-// ---------------------------------------------------------------------------
-// Compile-time plan of one block's neighbourhood.
-// ---------------------------------------------------------------------------
-struct BlockPlan {
-    int nc, box;
-    int lx[32], ly[32];              // local lambda of the block's cells
-    int nlayer;                      // single-bit layers summed per cell
-    int nterm;                       // in-block moves: L[layer] |= shift(x) & mask
-    int t_layer[128], t_shift[128];  // shift > 0: source bit above target (x >> shift)
-    uint32_t t_mask[128];
-    int nhalo;                       // distinct halo cells (block direction, cell)
-    int h_dx[kMaxHalo], h_dy[kMaxHalo], h_idx[kMaxHalo];
-    int nhterm;                      // L[layer] |= halo_bit[slot] << bit
-    int ht_layer[64], ht_slot[64], ht_bit[64];
-    bool ok;
-};
-
-template <class Pat>
-constexpr int local_nu(int x, int y)
-{
-    int c = 0;
-    for (int mu = Pat::J; mu >= 1; --mu) {
-        const int sc = cpow(Pat::S, mu - 1);
-        const int qx = (x / sc) % Pat::S, qy = (y / sc) % Pat::S;
-        int j = -1;
-        for (int i = 0; i < Pat::K; ++i)
-            if (Pat::OX[i] == qx && Pat::OY[i] == qy) j = i;
-        if (j < 0) return -1;
-        c += j * cpow(Pat::K, mu - 1);
-    }
-    return c;
-}
-
-template <class Pat>
-constexpr BlockPlan derive_plan()
-{
-    BlockPlan p{};
-    p.ok = true;
-    p.nc = cpow(Pat::K, Pat::J);
-    p.box = cpow(Pat::S, Pat::J);
-    if (p.nc > 32) {
-        p.ok = false;
-        return p;
-    }
-    for (int i = 0; i < p.nc; ++i) {
-        int v = i, x = 0, y = 0, sp = 1;
-        for (int mu = 1; mu <= Pat::J; ++mu) {
-            const int b = v % Pat::K;
-            v /= Pat::K;
-            x += Pat::OX[b] * sp;
-            y += Pat::OY[b] * sp;
-            sp *= Pat::S;
-        }
-        p.lx[i] = x;
-        p.ly[i] = y;
-    }
-    for (int i = 0; i < p.nc; ++i) {
-        bool used[8] = {};
-        int nused = 0;
-        int halo_slots[8] = {};
-        int nh = 0;
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-                if (!dx && !dy) continue;
-                const int qx = p.lx[i] + dx, qy = p.ly[i] + dy;
-                if (qx >= 0 && qy >= 0 && qx < p.box && qy < p.box) {
-                    const int j = local_nu<Pat>(qx, qy);
-                    if (j < 0) continue;
-                    const int shift = j - i;  // source bit j -> target bit i
-                    int layer = -1;
-                    for (int t = 0; t < p.nterm && layer < 0; ++t)
-                        if (p.t_shift[t] == shift && !used[p.t_layer[t]]) {
-                            layer = p.t_layer[t];
-                            p.t_mask[t] |= 1u << i;
-                        }
-                    if (layer < 0) {
-                        for (int l = 0; l < 8 && layer < 0; ++l)
-                            if (!used[l]) layer = l;
-                        p.t_layer[p.nterm] = layer;
-                        p.t_shift[p.nterm] = shift;
-                        p.t_mask[p.nterm] = 1u << i;
-                        ++p.nterm;
-                    }
-                    used[layer] = true;
-                    ++nused;
-                } else {
-                    const int bdx = qx < 0 ? -1 : (qx >= p.box ? 1 : 0);
-                    const int bdy = qy < 0 ? -1 : (qy >= p.box ? 1 : 0);
-                    const int j = local_nu<Pat>(qx - bdx * p.box, qy - bdy * p.box);
-                    if (j < 0) continue;
-                    int slot = -1;
-                    for (int h = 0; h < p.nhalo; ++h)
-                        if (p.h_dx[h] == bdx && p.h_dy[h] == bdy && p.h_idx[h] == j) slot = h;
-                    if (slot < 0) {
-                        if (p.nhalo == kMaxHalo) {
-                            p.ok = false;
-                            return p;
-                        }
-                        slot = p.nhalo++;
-                        p.h_dx[slot] = bdx;
-                        p.h_dy[slot] = bdy;
-                        p.h_idx[slot] = j;
-                    }
-                    halo_slots[nh++] = slot;
-                }
-            }
-        for (int h = 0; h < nh; ++h) {
-            int layer = -1;
-            for (int l = 0; l < 8 && layer < 0; ++l)
-                if (!used[l]) layer = l;
-            used[layer] = true;
-            ++nused;
-            p.ht_layer[p.nhterm] = layer;
-            p.ht_slot[p.nhterm] = halo_slots[h];
-            p.ht_bit[p.nhterm] = i;
-            ++p.nhterm;
-        }
-        if (nused > p.nlayer) p.nlayer = nused;
-    }
-    return p;
-}
-
-template <class Pat>
-struct PlanOf {
-    static constexpr BlockPlan value = derive_plan<Pat>();
-    static_assert(value.ok, "replica pattern does not fit the bit-sliced block kernel");
-};
-
-// ---------------------------------------------------------------------------
-// Per-tile configuration built on the host.
-// ---------------------------------------------------------------------------
-struct TileConfig {
-    int M;                 // tile level
-    uint32_t tile;         // K^M cells per tile
-    uint32_t nblocks;      // K^(M-J)
-    uint32_t nthalo;       // tile halo slots
-    uint32_t hstride;      // u32 entries per block in the block-halo table (multiple of 4)
-    uint32_t halo_word;    // LDS word index of the tile-halo bits (the next word is all zero)
-    uint64_t ntiles;       // K^(r-M)
-    uint32_t *d_block_halo;  // [32 alignments][nblocks][hstride]
-    uint64_t *d_tile_halo;
-    MapParams Pc;          // maps at the coarse level r-M
-    void *d_coarse_tables;
-};
-
-struct TileArgs {
-    uint64_t ntiles, N;
-    uint32_t tile, nblocks, nthalo, hstride, halo_word;
-    const uint32_t *block_halo;
-    const uint64_t *tile_halo;
-};
-
-template <class Pat>
-struct TileLds {
-    static constexpr int TMAX = cpow(Pat::K, Pat::MMAX);
-    static constexpr int WMAX = (TMAX + 31 + 31) / 32;  // words covering o + tile bits
-    static constexpr int HALO_WORD = WMAX + 1;          // tile-halo bits, then one zero word
-    static constexpr int IN_WORDS = HALO_WORD + 2;
-};
-
-// Bit 0 of eight bytes (two words) -> one byte of bits, via 4-byte dot products.
-__device__ __forceinline__ uint32_t pack8(uint32_t d0, uint32_t d1)
-{
-    return __builtin_amdgcn_udot4(d1, 0x80402010u, __builtin_amdgcn_udot4(d0, 0x08040201u, 0u, false), false);
-}
-__device__ __forceinline__ uint32_t spread4(uint32_t v) { return __umul24(v, 0x204081u) & 0x01010101u; }
-
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ uint4 load16(const uint8_t *p)
-{
-#if SQZ_NT_LOAD
-    const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
-    return make_uint4(v.x, v.y, v.z, v.w);
-#else
-    return *reinterpret_cast<const uint4 *>(p);
-#endif
-}
-__device__ __forceinline__ void store16(uint8_t *p, uint4 v)
-{
-#if SQZ_NT_STORE
-    u32x4 w = {v.x, v.y, v.z, v.w};
-    __builtin_nontemporal_store(w, reinterpret_cast<u32x4 *>(p));
-#else
-    *reinterpret_cast<uint4 *>(p) = v;
-#endif
-}
-
-template <int Layer, int Shift, uint32_t Mask, int NL>
-__device__ __forceinline__ void move_term(uint32_t x, uint32_t (&L)[NL])
-{
-    if constexpr (Shift > 0)
-        L[Layer] |= (x >> Shift) & Mask;
-    else
-        L[Layer] |= (x << (-Shift)) & Mask;
-}
-
-template <class Pat, int NL, size_t... I>
-__device__ __forceinline__ void apply_moves(uint32_t x, uint32_t (&L)[NL], std::index_sequence<I...>)
-{
-    constexpr const BlockPlan &PL = PlanOf<Pat>::value;
-    (move_term<PL.t_layer[I], PL.t_shift[I], PL.t_mask[I], NL>(x, L), ...);
-}
-
-template <int Layer, int Slot, int Bit, int NL, int NH>
-__device__ __forceinline__ void halo_term(const uint32_t (&hb)[NH], uint32_t (&L)[NL])
-{
-    L[Layer] |= hb[Slot] << Bit;
-}
-
-template <class Pat, int NL, int NH, size_t... I>
-__device__ __forceinline__ void apply_halo(const uint32_t (&hb)[NH], uint32_t (&L)[NL], std::index_sequence<I...>)
-{
-    constexpr const BlockPlan &PL = PlanOf<Pat>::value;
-    (halo_term<PL.ht_layer[I], PL.ht_slot[I], PL.ht_bit[I], NL, NH>(hb, L), ...);
-}
-
-// B3/S23 on all cells of a block: alive' = (count == 3) | (alive & count == 2).
-template <int NL>
-__device__ __forceinline__ uint32_t life_rule(uint32_t x, const uint32_t (&L)[NL])
-{
-    if constexpr (NL <= 5) {
-        uint32_t v[5] = {0u, 0u, 0u, 0u, 0u};
-#pragma unroll
-        for (int l = 0; l < NL; ++l) v[l] = L[l];
-        const uint32_t a = v[0], b = v[1], c = v[2], d = v[3], e = v[4];
-        const uint32_t s1 = a ^ b ^ c, c1 = (a & b) | (c & (a ^ b));
-        const uint32_t s2 = s1 ^ d ^ e, c2 = (s1 & d) | (e & (s1 ^ d));
-        // count = s2 + 2 (c1 + c2): 2 or 3 iff exactly one carry
-        return (c1 ^ c2) & (s2 | x);
-    } else {
-        uint32_t b0 = 0, b1 = 0, b2 = 0;  // b2 sticks once the count reaches 4
-#pragma unroll
-        for (int l = 0; l < NL; ++l) {
-            const uint32_t c0 = b0 & L[l];
-            b0 ^= L[l];
-            b2 |= b1 & c0;
-            b1 ^= c0;
-        }
-        return ~b2 & b1 & (b0 | x);
-    }
-}
-
-// XCD-aware order: workgroups are dealt round-robin to the 8 XCDs; give each
-// XCD a contiguous run of tiles so halo reads of adjacent tiles hit its L2.
-__device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t G)
-{
-    const uint32_t q = G / 8, rem = G % 8, xcd = b % 8, pos = b / 8;
-    return xcd < rem ? xcd * (q + 1) + pos : rem * (q + 1) + (xcd - rem) * q + pos;
-}
 
 template <class Pat>
 __global__ void __launch_bounds__(kBlock) k_life_tile(TileArgs A, const uint8_t *__restrict__ in,
                                                       uint8_t *__restrict__ out)
 {
     using LDS = TileLds<Pat>;
-    constexpr const BlockPlan &PL = PlanOf<Pat>::value;
-    constexpr int NC = PL.nc;
-    constexpr uint32_t CELLS = NC == 32 ? 0xFFFFFFFFu : ((1u << NC) - 1u);
-    constexpr int NL = PL.nlayer;
-    constexpr int NH = PL.nhalo;
-
     __shared__ uint32_t s_in[LDS::IN_WORDS];
     __shared__ uint32_t s_out[LDS::WMAX + 1];  // +1: a block's high half may land one word past the tile
-
-    const uint32_t tid = threadIdx.x;
     const uint32_t G = gridDim.x;
     for (uint64_t round = 0; round * G < A.ntiles; ++round) {
         const uint64_t t = round * G + xcd_remap(blockIdx.x, G);
         if (t >= A.ntiles) break;  // uniform across the workgroup
-        const uint64_t S0 = t * A.tile;  // first byte of the tile
-        const uint64_t A0 = S0 & ~31ull;
-        const uint32_t o = (uint32_t)(S0 - A0);
-        const uint32_t W = (o + A.tile + 31) / 32;
-
-        const uint32_t *bh_o = A.block_halo + (size_t)o * A.nblocks * A.hstride;
-
-        // Phase B, first half: the global indices of the tile's halo cells are
-        // requested before the tile's own bytes so the two latencies overlap.
-        uint64_t gi = kHole64;
-        if (tid < A.nthalo) gi = A.tile_halo[t * A.nthalo + tid];
-
-        // Phase A: load and pack the tile (plus the bytes of its first and last
-        // 32-byte words that belong to the neighbouring tiles).
-        for (uint32_t w = tid; w < W; w += kBlock) {
-            const uint64_t g = A0 + 32ull * w;
-            uint32_t bits = 0;
-            if (g + 32 <= A.N) {
-                const uint4 a = load16(in + g);
-                const uint4 b = load16(in + g + 16);
-                bits = pack8(a.x, a.y) | pack8(a.z, a.w) << 8 | pack8(b.x, b.y) << 16 | pack8(b.z, b.w) << 24;
-            } else {
-                for (uint32_t i = 0; i < 32; ++i)
-                    if (g + i < A.N) bits |= (uint32_t)(in[g + i] & 1u) << i;
-            }
-            s_in[w] = bits;
-            s_out[w] = 0;
-        }
-        // Phase B, second half: the halo cells themselves, gathered by ballot.
-        if (tid < 64) {
-            const uint32_t v = gi != kHole64 ? (in[gi] & 1u) : 0u;
-            const uint64_t m = __ballot(v);
-            if (tid == 0) {
-                s_in[A.halo_word] = (uint32_t)m;
-                s_in[A.halo_word + 1] = 0u;
-            }
-        }
-        __syncthreads();
-
-        // Phase C: one lane per level-J block.
-        for (uint32_t b = tid; b < A.nblocks; b += kBlock) {
-            const uint32_t pos = o + b * NC;
-            const uint32_t lo = s_in[pos >> 5], hi = s_in[(pos >> 5) + 1];
-            const uint32_t x = __builtin_amdgcn_alignbit(hi, lo, pos) & CELLS;  // shift = pos mod 32
-            uint32_t hb[NH > 0 ? NH : 1] = {};
-            const uint32_t *he = bh_o + (size_t)b * A.hstride;
-#pragma unroll
-            for (int h0 = 0; h0 < NH; h0 += 4) {
-                const uint4 q = *reinterpret_cast<const uint4 *>(he + h0);
-                const uint32_t qq[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-                for (int h = h0; h < NH && h < h0 + 4; ++h) {
-                    // entry: LDS byte address of the word << 16 | bit within the word
-                    const uint32_t e = qq[h - h0];
-                    const uint32_t word = *reinterpret_cast<const uint32_t *>(
-                        reinterpret_cast<const char *>(s_in) + (e >> 16));
-                    hb[h] = __builtin_amdgcn_ubfe(word, e, 1);
-                }
-            }
-            uint32_t L[NL];
-#pragma unroll
-            for (int l = 0; l < NL; ++l) L[l] = 0;
-            apply_moves<Pat, NL>(x, L, std::make_index_sequence<PL.nterm>{});
-            apply_halo<Pat, NL, (NH > 0 ? NH : 1)>(hb, L, std::make_index_sequence<PL.nhterm>{});
-            const uint32_t res = life_rule<NL>(x, L) & CELLS;
-            const uint64_t sh = (uint64_t)res << (pos & 31);
-            atomicOr(&s_out[pos >> 5], (uint32_t)sh);
-            atomicOr(&s_out[(pos >> 5) + 1], (uint32_t)(sh >> 32));
-        }
-        __syncthreads();
-
-        // Phase D: unpack and store whole words; the (at most two) edge words
-        // of the tile go out byte by byte, one byte per lane of wave 0.
-        const uint32_t last = W - 1;
-        const bool first_partial = o != 0, last_partial = ((o + A.tile) & 31) != 0;
-        for (uint32_t w = tid; w < W; w += kBlock) {
-            const uint32_t v = s_out[w];
-            const uint64_t g = A0 + 32ull * w;
-            if (!((w == 0 && first_partial) || (w == last && last_partial))) {
-                uint4 a, b;
-                a.x = spread4(v & 15);
-                a.y = spread4((v >> 4) & 15);
-                a.z = spread4((v >> 8) & 15);
-                a.w = spread4((v >> 12) & 15);
-                b.x = spread4((v >> 16) & 15);
-                b.y = spread4((v >> 20) & 15);
-                b.z = spread4((v >> 24) & 15);
-                b.w = spread4(v >> 28);
-                store16(out + g, a);
-                store16(out + g + 16, b);
-            }
-        }
-        if (tid < 64) {
-            const uint32_t w = tid < 32 ? 0u : last, i = tid & 31u, lp = 32 * w + i;
-            const bool mine = tid < 32 ? first_partial : (last_partial && (last != 0 || !first_partial));
-            if (mine && lp >= o && lp < o + A.tile) out[A0 + lp] = (uint8_t)((s_out[w] >> i) & 1u);
-        }
-        __syncthreads();  // LDS is reused by the next round
+        tile_body<Pat>(A, in, out, t, s_in, s_out);
     }
 }
 

@@ -1,207 +1,27 @@
-// Expanded-tile kernels: block-level Squeeze (Section "Moving from
-// Thread-level to Block-level") for any NBB pattern, for Life and for the
-// explicit diffusion update.
-//
-// A tile is a level-M subtree: compact range [t K^M, (t+1) K^M).  Its cells
-// are scattered into an on-chip copy of the tile's s^M x s^M expanded box,
-// with a one-cell ring around it (pitch P = s^M + 2), through a tile-invariant
-// table of local lambda positions.  The ring holds the few cells of adjacent
-// tiles that touch the tile; their compact addresses are the adjacent tiles'
-// bases (eight coarse nu at level r-M, evaluated once per tile) plus a
-// tile-invariant cell index.  Every cell then reads its eight neighbours at
-// fixed offsets in LDS (holes hold 0 and are never written) and writes its
-// result in compact order, so global reads and writes are coalesced.
-//
-// The grid is persistent: each workgroup keeps the tables in LDS and walks a
-// contiguous run of tiles, so the neighbouring tiles whose ring cells it reads
-// were just loaded into (or are about to be loaded into) its XCD's L2.
-//
-// Diffusion (the PDE application named in the Introduction): u' = u + a (S -
-// deg u), S the sum of the member neighbours' values, deg their count (no flux
-// through holes or the box edge), evaluated in binary32 in a fixed order.
-// bfloat16 storage keeps delta = u - offset with a caller-chosen offset (the
-// mean, which the update conserves); the update is linear, so it runs on delta
-// directly, accumulates in binary32 and rounds to bfloat16 either to nearest
-// even or stochastically with 16 counter-hash bits per (seed, step, cell).
+// Expanded-tile kernels (device code in xtile_device.h) and their host side:
+// tile level choice, tile-invariant tables, launches; thread-level
+// diffusion, binary64 mass and bfloat16 conversion kernels.
 #include <string.h>
 
 #include <vector>
 
-#include "common.h"
+#include "xtile_device.h"
 
 namespace sqz {
 
 namespace {
 
-constexpr int kXBlock = 256;
-constexpr size_t kXLdsBudget = 48 * 1024;
-
-struct XArgs {
-    uint64_t ntiles;
-    uint32_t KM, P, R;
-    uint32_t off_mem, off_lam, off_rpos, off_rinfo, off_nbase;
-    uint32_t vec;  // 1 when a tile is a whole number of 16-byte vectors
-    const uint16_t *lam;
-    const uint8_t *mem_in;
-    const uint16_t *rpos;
-    const uint32_t *rinfo;
-    MapParams Pc;
-};
-
-struct XOp {
-    float coef;
-    uint32_t rounding;  // sqz_rounding
-    uint64_t seed, step;
-};
-
-struct XLife {
-    using G = uint8_t;
-    using L = uint8_t;
-    static constexpr bool kMem = false;
-    static constexpr int kVec = 16;
-};
-struct XDiffF32 {
-    using G = float;
-    using L = float;
-    static constexpr bool kMem = true;
-    static constexpr int kVec = 4;
-};
-struct XDiffBF16 {
-    using G = uint16_t;  // bfloat16 bits of delta
-    using L = float;
-    static constexpr bool kMem = true;
-    static constexpr int kVec = 8;
-};
-
-__device__ __forceinline__ uint8_t to_lds(uint8_t v) { return v; }
-__device__ __forceinline__ float to_lds(float v) { return v; }
-__device__ __forceinline__ float to_lds(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
-
-// 16 pseudo-random bits per (seed, step, cell): SplitMix64's finaliser on a
-// Weyl combination of the three counters.
-__device__ __forceinline__ uint32_t rand16(uint64_t seed, uint64_t step, uint64_t cell)
-{
-    uint64_t z = seed + (step + 1) * 0x9E3779B97F4A7C15ull + (cell + 1) * 0xD1B54A32D192ED03ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return (uint32_t)((z ^ (z >> 31)) >> 48);
-}
-
-// binary32 -> bfloat16 bits: nearest-even, or stochastic (add 16 random bits
-// below the kept mantissa, truncate).
-__device__ __forceinline__ uint16_t to_bf16(float u, uint32_t rounding, uint32_t r16)
-{
-    uint32_t b = __float_as_uint(u);
-    b += rounding == SQZ_ROUND_STOCHASTIC ? r16 : 0x7FFFu + ((b >> 16) & 1u);
-    return (uint16_t)(b >> 16);
-}
-
-template <class Op>
-__device__ __forceinline__ typename Op::G cell_update(const typename Op::L *s_val, const uint8_t *s_mem, uint32_t p,
-                                                      uint32_t P, const XOp &op, uint64_t gcell)
-{
-    using L = typename Op::L;
-    const L *b = s_val + (p - P - 1);
-    const L n0 = b[0], n1 = b[1], n2 = b[2], n3 = b[P], c = b[P + 1], n4 = b[P + 2];
-    const L n5 = b[2 * P], n6 = b[2 * P + 1], n7 = b[2 * P + 2];
-    if constexpr (!Op::kMem) {
-        const uint32_t cnt = (uint32_t)n0 + n1 + n2 + n3 + n4 + n5 + n6 + n7;
-        return (typename Op::G)(cnt == 3 || (c && cnt == 2));
-    } else {
-        const uint8_t *m = s_mem + (p - P - 1);
-        const uint32_t deg = (uint32_t)m[0] + m[1] + m[2] + m[P] + m[P + 2] + m[2 * P] + m[2 * P + 1] + m[2 * P + 2];
-        const float S = ((((((n0 + n1) + n2) + n3) + n4) + n5) + n6) + n7;
-        const float u = fmaf(op.coef, fmaf(-(float)deg, c, S), c);
-        if constexpr (sizeof(typename Op::G) == 4)
-            return u;
-        else
-            return to_bf16(u, op.rounding, op.rounding == SQZ_ROUND_STOCHASTIC ? rand16(op.seed, op.step, gcell) : 0u);
-    }
-}
-
 template <class Op, int PT>
 __global__ void __launch_bounds__(kXBlock) k_xtile(XArgs A, const typename Op::G *__restrict__ in,
                                                    typename Op::G *__restrict__ out, XOp op)
 {
-    using G = typename Op::G;
-    using L = typename Op::L;
-    constexpr int VEC = Op::kVec;
     extern __shared__ __align__(16) unsigned char smem[];
-    const uint32_t P = PT ? (uint32_t)PT : A.P;
-    const uint32_t PP = P * P, KM = A.KM, R = A.R;
-    L *s_val = reinterpret_cast<L *>(smem);
-    uint8_t *s_mem = smem + A.off_mem;
-    uint16_t *s_lam = reinterpret_cast<uint16_t *>(smem + A.off_lam);
-    uint16_t *s_rpos = reinterpret_cast<uint16_t *>(smem + A.off_rpos);
-    uint32_t *s_rinfo = reinterpret_cast<uint32_t *>(smem + A.off_rinfo);
-    uint64_t *s_nbase = reinterpret_cast<uint64_t *>(smem + A.off_nbase);
-    const uint32_t tid = threadIdx.x;
-
-    for (uint32_t i = tid; i < PP; i += kXBlock) {
-        s_val[i] = (L)0;
-        if constexpr (Op::kMem) s_mem[i] = A.mem_in[i];
-    }
-    for (uint32_t i = tid; i < KM; i += kXBlock) s_lam[i] = A.lam[i];
-    for (uint32_t i = tid; i < R; i += kXBlock) {
-        s_rpos[i] = A.rpos[i];
-        s_rinfo[i] = A.rinfo[i];
-    }
-
+    const XLds<Op> S(smem, A);
+    xtile_setup<Op>(A, S);
     const uint64_t chunk = (A.ntiles + gridDim.x - 1) / gridDim.x;
     const uint64_t t0 = (uint64_t)blockIdx.x * chunk;
     const uint64_t t1 = t0 + chunk < A.ntiles ? t0 + chunk : A.ntiles;
-    for (uint64_t t = t0; t < t1; ++t) {
-        __syncthreads();  // tables ready / previous tile's reads of LDS done
-        // adjacent tiles' first cells (eight coarse nu of this tile's coarse cell)
-        if (tid < 8) {
-            const int d = tid < 4 ? (int)tid : (int)tid + 1;
-            uint32_t X, Y;
-            if (A.Pc.N <= 0x100000000ull)
-                lam_map32(A.Pc, (uint32_t)t, X, Y);
-            else
-                lam_map64(A.Pc, t, X, Y);
-            const uint64_t nt = nu_map(A.Pc, (int32_t)X + d % 3 - 1, (int32_t)Y + d / 3 - 1);
-            s_nbase[tid] = nt == kHole64 ? kHole64 : nt * KM;
-        }
-        // scatter the tile's cells into the expanded box
-        const G *src = in + t * KM;
-        if (A.vec) {
-            for (uint32_t v = tid; v < KM / VEC; v += kXBlock) {
-                const uint4 q = *reinterpret_cast<const uint4 *>(src + (size_t)v * VEC);
-                const G *e = reinterpret_cast<const G *>(&q);
-#pragma unroll
-                for (int i = 0; i < VEC; ++i) s_val[s_lam[v * VEC + i]] = to_lds(e[i]);
-            }
-        } else {
-            for (uint32_t l = tid; l < KM; l += kXBlock) s_val[s_lam[l]] = to_lds(src[l]);
-        }
-        __syncthreads();
-        // the ring: cells of adjacent tiles that touch this one
-        for (uint32_t j = tid; j < R; j += kXBlock) {
-            const uint32_t info = s_rinfo[j];
-            const uint64_t nb = s_nbase[info >> 16];
-            L v = (L)0;
-            if (nb != kHole64) v = to_lds(in[nb + (info & 0xFFFFu)]);
-            s_val[s_rpos[j]] = v;
-            if constexpr (Op::kMem) s_mem[s_rpos[j]] = nb != kHole64;
-        }
-        __syncthreads();
-        // update every cell, results in compact order
-        G *dst = out + t * KM;
-        const uint64_t gbase = t * KM;
-        if (A.vec) {
-            for (uint32_t v = tid; v < KM / VEC; v += kXBlock) {
-                uint4 q;
-                G *e = reinterpret_cast<G *>(&q);
-#pragma unroll
-                for (int i = 0; i < VEC; ++i)
-                    e[i] = cell_update<Op>(s_val, s_mem, s_lam[v * VEC + i], P, op, gbase + v * VEC + i);
-                *reinterpret_cast<uint4 *>(dst + (size_t)v * VEC) = q;
-            }
-        } else {
-            for (uint32_t l = tid; l < KM; l += kXBlock) dst[l] = cell_update<Op>(s_val, s_mem, s_lam[l], P, op, gbase + l);
-        }
-    }
+    for (uint64_t t = t0; t < t1; ++t) xtile_body<Op, PT>(A, in, out, t, op, S);
 }
 
 // ---------------------------------------------------------------------------
@@ -300,43 +120,6 @@ unsigned grid_for(uint64_t count)
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
-struct XTileConfig {
-    int M;
-    uint32_t KM, B, P, R;
-    uint64_t ntiles;
-    void *d_tab;
-    XArgs base;  // tables and offsets (LDS offsets for the diffusion layout)
-    size_t lds_life, lds_diff;
-    unsigned grid_life, grid_diff;
-    void *d_coarse;
-};
-
-static size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
-
-// LDS layout: values, membership bytes (diffusion), lambda table, ring tables, 8 bases.
-static size_t xt_layout(uint32_t P, uint32_t KM, uint32_t R, size_t val_bytes, bool mem, XArgs *A)
-{
-    size_t off = align16((size_t)P * P * val_bytes);
-    const size_t off_mem = off;
-    if (mem) off = align16(off + (size_t)P * P);
-    const size_t off_lam = off;
-    off = align16(off + (size_t)KM * 2);
-    const size_t off_rpos = off;
-    off = align16(off + (size_t)R * 2);
-    const size_t off_rinfo = off;
-    off = align16(off + (size_t)R * 4);
-    const size_t off_nbase = off;
-    off += 8 * 8;
-    if (A) {
-        A->off_mem = (uint32_t)off_mem;
-        A->off_lam = (uint32_t)off_lam;
-        A->off_rpos = (uint32_t)off_rpos;
-        A->off_rinfo = (uint32_t)off_rinfo;
-        A->off_nbase = (uint32_t)off_nbase;
-    }
-    return off;
-}
-
 struct RingSlot {
     uint16_t pos;
     uint32_t info;
@@ -427,8 +210,8 @@ sqz_status xtile_prepare(FractalHost &F)
         lam[c] = (uint16_t)((y + 1) * P + (x + 1));
         mem[lam[c]] = 1;
     }
-    const size_t o_lam = 0, o_mem = align16(o_lam + KM * 2), o_rpos = align16(o_mem + (size_t)P * P),
-                 o_rinfo = align16(o_rpos + (size_t)R * 2), total = align16(o_rinfo + (size_t)R * 4 + 4);
+    const size_t o_lam = 0, o_mem = xt_align16(o_lam + KM * 2), o_rpos = xt_align16(o_mem + (size_t)P * P),
+                 o_rinfo = xt_align16(o_rpos + (size_t)R * 2), total = xt_align16(o_rinfo + (size_t)R * 4 + 4);
     std::vector<uint8_t> blob(total, 0);
     memcpy(blob.data() + o_lam, lam.data(), KM * 2);
     memcpy(blob.data() + o_mem, mem.data(), (size_t)P * P);
