@@ -80,7 +80,7 @@ def profiled_traffic(workload: str):
 
     src = os.path.join(ROOT, "paper_2201_00613_amd", "csrc")
     h = hashlib.sha256()
-    for f in ("life_tile.hip", "common.h"):
+    for f in ("life_tile.hip", "tile_device.h", "common.h"):
         h.update(open(os.path.join(src, f), "rb").read())
     path = os.path.join(ROOT, "profiles", "k_life_tile_triangle_r16.md")
     if not os.path.exists(path):
@@ -110,6 +110,82 @@ def cpu_baseline(r: int, seed: int, p: float, min_sec: float, max_steps: int) ->
             "sample": f"{steps} full B3/S23 step(s) of the level-{r} triangle ({O.N} cells each), {sec:.1f} s"}
 
 
+def batch_leg(torch, sqz, steps: int) -> dict:
+    """512 instances drawn from seed over triangle, carpet and Vicsek (1e4..1e7 cells
+    each), Bernoulli(0.5), `steps` steps as one graph replay after autotuning."""
+    from paper_2201_00613_amd import workloads as W
+
+    inst = W.batch_instances(512, 2201)
+    cache, fr = {}, []
+    for name, s, offs, r, seed in inst:
+        if (name, r) not in cache:
+            cache[(name, r)] = sqz.Fractal(s, offs, r)
+        fr.append(cache[(name, r)])
+    B = sqz.Batch(fr)
+    seeds = [x[4] for x in inst]
+    a = B.fill_bernoulli(seeds, 0.5)
+    b = B.empty_state()
+    wg = B.autotune(a, b)
+    a = B.fill_bernoulli(seeds, 0.5, out=a)
+    B.run(a, b, steps)  # capture + warm-up
+    a = B.fill_bernoulli(seeds, 0.5, out=a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    B.run(a, b, steps)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3
+    res = {"instances": len(inst), "cells": B.total_cells, "steps": steps, "ms_per_step": sec * 1e3 / steps,
+           "cell_updates_per_s": B.total_cells * steps / sec,
+           "algorithmic_gbs": 2 * B.total_cells * steps / sec / 1e9, "wg_per_cu": wg, "graph": True,
+           "mix": {k: sum(1 for x in inst if x[0] == k) for k in ("triangle", "carpet", "vicsek")}}
+    del a, b, B, fr, cache
+    torch.cuda.empty_cache()
+    return res
+
+
+def diffusion_leg(torch, sqz, steps: int) -> dict:
+    """Carpet r=9 (134,217,728 cells), coef 0.1, U(0,1) start: binary32 and bfloat16
+    (offset storage, stochastic rounding) for `steps` steps; binary64 mass drift."""
+    from paper_2201_00613_amd import workloads as W
+
+    F = sqz.Fractal(*W.CARPET, 9)
+    res = {"fractal": "sierpinski carpet s=3 k=8", "level": 9, "cells": F.cells, "coef": 0.1, "steps": steps,
+           "tile_level": F.xtile_level}
+    u = F.fill_uniform(2201)
+    m0 = float(F.mass_f64(u))
+    mean = m0 / F.cells
+    for dtype, nbytes in (("f32", 8), ("bf16", 4)):
+        if dtype == "f32":
+            a, b = u.clone(), torch.empty_like(u)
+            kw = {}
+            offset = 0.0
+        else:
+            a = F.bf16_encode(u, mean)
+            b = torch.empty_like(a)
+            kw = {"rounding": "stochastic", "seed": 17}
+            offset = mean
+        F.diffuse_run(a, b, 2, 0.1, dtype=dtype, **kw)  # warm-up (result discarded)
+        a = u.clone() if dtype == "f32" else F.bf16_encode(u, mean)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        r = F.diffuse_run(a, b, steps, 0.1, dtype=dtype, **kw)
+        e1.record()
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) / 1e3
+        m1 = float(F.mass_f64(r, dtype=dtype, offset=offset))
+        res[dtype] = {"ms_per_step": sec * 1e3 / steps, "cell_updates_per_s": F.cells * steps / sec,
+                      "algorithmic_gbs": nbytes * F.cells * steps / sec / 1e9,
+                      "hbm_frac": nbytes * F.cells * steps / sec / 1e9 / HBM_PEAK_GBS,
+                      "mass_rel_drift": (m1 - m0) / m0}
+        del a, b, r
+    del u, F
+    torch.cuda.empty_cache()
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,6 +198,10 @@ def main() -> int:
     ap.add_argument("--no-bb", action="store_true")
     ap.add_argument("--no-r20", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-diffusion", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=50)
+    ap.add_argument("--diffusion-steps", type=int, default=1000)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--cpu-max-steps", type=int, default=8)
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -191,6 +271,15 @@ def main() -> int:
         log(f"[bench] r=20: {ms20:.3f} ms/step, {gbs20:.1f} GB/s ({100 * gbs20 / HBM_PEAK_GBS:.1f}% of HBM peak)")
         del F20
         torch.cuda.empty_cache()
+    if not args.no_batch:
+        out["batch"] = batch_leg(torch, sqz, args.batch_steps)
+        log(f"[bench] batch: {out['batch']['instances']} instances, {out['batch']['cells']} cells, "
+            f"{out['batch']['ms_per_step']:.3f} ms/step, {out['batch']['cell_updates_per_s']:.3e} cell-updates/s")
+    if not args.no_diffusion:
+        out["diffusion"] = diffusion_leg(torch, sqz, args.diffusion_steps)
+        d = out["diffusion"]
+        log(f"[bench] diffusion carpet r=9: f32 {d['f32']['ms_per_step']:.4f} ms/step ({d['f32']['algorithmic_gbs']:.0f} GB/s), "
+            f"bf16 {d['bf16']['ms_per_step']:.4f} ms/step ({d['bf16']['algorithmic_gbs']:.0f} GB/s)")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(r, seed, p, args.cpu_seconds, args.cpu_max_steps)
         log(f"[bench] cpu oracle: {out['cpu_baseline']['value']:.3e} cell-updates/s "

@@ -30,7 +30,7 @@ struct sqz_fractal;  // api.hip
 
 namespace sqz {
 
-enum BatchKind : uint32_t { kBTri = 1, kBTriPaper = 2, kBVicsek = 3, kBX66 = 4, kBX83 = 5, kBXAny = 6, kBCell = 7 };
+enum BatchKind : uint32_t { kBTri = 1, kBTriPaper = 2, kBVicsek = 3, kBX68 = 4, kBX84 = 5, kBXAny = 6, kBCell = 7 };
 
 constexpr uint32_t kCellUnit = 4096;
 
@@ -40,6 +40,8 @@ struct BatchInst {
     uint64_t units;        // work units
     uint64_t unit_cells;   // cells per unit
     uint64_t cell_start;   // first cell of the instance in the batch's cell sequence
+    uint64_t cost_start;   // first cost unit of the instance (cells weighted by path)
+    uint64_t unit_cost;    // cost of one work unit
     uint64_t cells;
     TileArgs tile;
     XArgs x;
@@ -48,9 +50,9 @@ struct BatchInst {
 
 struct BatchArgs {
     const BatchInst *inst;
-    const uint64_t *cell_start;  // ninst + 1 entries
+    const uint64_t *cost_start;  // ninst + 1 entries
     uint32_t ninst;
-    uint64_t total_cells;
+    uint64_t total_cost;
 };
 
 namespace {
@@ -92,13 +94,13 @@ __global__ void __launch_bounds__(256) k_batch_life(BatchArgs B, const uint8_t *
                                                     uint8_t *__restrict__ out)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const uint64_t lo = B.total_cells * blockIdx.x / gridDim.x;
-    const uint64_t hi = B.total_cells * (blockIdx.x + 1) / gridDim.x;
-    // instance holding cell lo (uniform binary search)
+    const uint64_t lo = B.total_cost * blockIdx.x / gridDim.x;
+    const uint64_t hi = B.total_cost * (blockIdx.x + 1) / gridDim.x;
+    // instance holding cost unit lo (uniform binary search)
     uint32_t a = 0, b = B.ninst;
     while (b - a > 1) {
         const uint32_t m = (a + b) / 2;
-        if (B.cell_start[m] <= lo)
+        if (B.cost_start[m] <= lo)
             a = m;
         else
             b = m;
@@ -107,7 +109,7 @@ __global__ void __launch_bounds__(256) k_batch_life(BatchArgs B, const uint8_t *
     uint64_t j = 0;
     {
         const BatchInst &I = B.inst[i];
-        j = (lo - I.cell_start + I.unit_cells - 1) / I.unit_cells;
+        j = (lo - I.cost_start + I.unit_cost - 1) / I.unit_cost;
     }
     int loaded = -1;  // expanded-tile configuration currently in LDS
     const XOp op{};
@@ -118,7 +120,7 @@ __global__ void __launch_bounds__(256) k_batch_life(BatchArgs B, const uint8_t *
             j = 0;
             continue;
         }
-        if (I.cell_start + j * I.unit_cells >= hi) break;
+        if (I.cost_start + j * I.unit_cost >= hi) break;
         const uint8_t *ii = in + I.base;
         uint8_t *oo = out + I.base;
         __syncthreads();  // the previous unit's LDS reads are done
@@ -126,36 +128,49 @@ __global__ void __launch_bounds__(256) k_batch_life(BatchArgs B, const uint8_t *
         case kBTri:
             loaded = -1;
             bitsliced_unit<PatTriangle>(I, ii, oo, j, smem);
+            ++j;
             break;
         case kBTriPaper:
             loaded = -1;
             bitsliced_unit<PatTrianglePaper>(I, ii, oo, j, smem);
+            ++j;
             break;
         case kBVicsek:
             loaded = -1;
             bitsliced_unit<PatVicsek>(I, ii, oo, j, smem);
+            ++j;
             break;
-        case kBX66:
-        case kBX83:
+        case kBX68:
+        case kBX84:
         case kBXAny: {
             const XLds<XLife> S(smem, I.x);
             if (loaded != (int)I.xcfg) {
                 xtile_setup<XLife>(I.x, S);
                 loaded = (int)I.xcfg;
             }
-            if (I.kind == kBX83)
-                xtile_body<XLife, 83>(I.x, ii, oo, j, op, S);
-            else if (I.kind == kBX66)
-                xtile_body<XLife, 66>(I.x, ii, oo, j, op, S);
-            else
-                xtile_body<XLife, 0>(I.x, ii, oo, j, op, S);
+            // this workgroup's run of consecutive tiles of the instance
+            uint64_t je = (hi - I.cost_start + I.unit_cost - 1) / I.unit_cost;
+            if (je > I.units) je = I.units;
+            if (I.kind == kBX84 && I.x.KM == 16 * 256 && I.x.R <= 2 * 256) {
+                xtile_run<XLife, 84, 16, 2, true>(I.x, ii, oo, j, je, op, S);
+            } else if (I.x.KM <= 16 * 256 && I.x.R <= 2 * 256) {
+                if (I.kind == kBX84)
+                    xtile_run<XLife, 84, 16, 2>(I.x, ii, oo, j, je, op, S);
+                else if (I.kind == kBX68)
+                    xtile_run<XLife, 68, 16, 2>(I.x, ii, oo, j, je, op, S);
+                else
+                    xtile_run<XLife, 0, 16, 2>(I.x, ii, oo, j, je, op, S);
+            } else {
+                for (uint64_t t = j; t < je; ++t) xtile_body<XLife, 0>(I.x, ii, oo, t, op, S);
+            }
+            j = je;
             break;
         }
         default:
             life_cell_unit(I.P, ii, oo, j);
+            ++j;
             break;
         }
-        ++j;
     }
 }
 
@@ -172,7 +187,9 @@ struct BatchHost {
     std::vector<uint64_t> cells;
     uint64_t total_cells, total_bytes;
     BatchInst *d_inst;
-    uint64_t *d_cell_start;
+    uint64_t *d_cost_start;
+    uint64_t total_cost;
+    unsigned xt_weight;  // cost per cell of the expanded-tile path (bit-sliced = 2, thread-level = 32)
     size_t lds;
     unsigned wg_per_cu, max_wg_per_cu;
     std::string key;
@@ -184,7 +201,7 @@ struct BatchHost {
 };
 
 static std::mutex g_tune_mu;
-static std::map<std::string, unsigned> g_tune_cache;
+static std::map<std::string, std::pair<unsigned, unsigned>> g_tune_cache;  // key -> (wg per CU, xt weight)
 
 const FractalHost &fractal_host_of(const sqz_fractal *f);  // api.hip
 
@@ -193,7 +210,7 @@ static uint32_t kind_of(const FractalHost &F)
     if (F.tile_kind == 1) return kBTri;
     if (F.tile_kind == 2) return kBTriPaper;
     if (F.tile_kind == 3) return kBVicsek;
-    if (F.xtile) return F.xtile->P == 83 ? kBX83 : (F.xtile->P == 66 ? kBX66 : kBXAny);
+    if (F.xtile) return F.xtile->P == 84 ? kBX84 : (F.xtile->P == 68 ? kBX68 : kBXAny);
     return kBCell;
 }
 
@@ -223,6 +240,29 @@ static size_t tile_lds_of(const FractalHost &F)
     case 2: return tile_lds<PatTrianglePaper>();
     default: return tile_lds<PatVicsek>();
     }
+}
+
+// Cost of a cell per path (for the static split): bit-sliced 2, expanded tile
+// xt_weight (tuned), thread-level 32.  Uploads the instances and prefix sums.
+static hipError_t upload_costs(BatchHost *H)
+{
+    const size_t n = H->inst.size();
+    std::vector<uint64_t> cs(n + 1);
+    uint64_t c = 0;
+    for (size_t i = 0; i < n; ++i) {
+        BatchInst &I = H->inst[i];
+        const uint32_t k = I.kind;
+        const uint64_t w = (k == kBTri || k == kBTriPaper || k == kBVicsek) ? 2 : (k == kBCell ? 32 : H->xt_weight);
+        I.cost_start = c;
+        I.unit_cost = I.unit_cells * w;
+        cs[i] = c;
+        c += I.units * I.unit_cost;
+    }
+    cs[n] = c;
+    H->total_cost = c;
+    hipError_t e = hipMemcpy(H->d_inst, H->inst.data(), sizeof(BatchInst) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(H->d_cost_start, cs.data(), sizeof(uint64_t) * (n + 1), hipMemcpyHostToDevice);
+    return e;
 }
 
 sqz_status batch_create(const sqz_fractal *const *fr, int32_t count, BatchHost **out)
@@ -264,7 +304,7 @@ sqz_status batch_create(const sqz_fractal *const *fr, int32_t count, BatchHost *
         } else if (I.kind != kBCell) {
             const XTileConfig *X = F.xtile;
             I.x = X->base;
-            const size_t need = xt_layout(X->P, X->KM, X->R, 1, false, &I.x);
+            const size_t need = xt_layout(X->P, X->KM, X->R, 1, false, true, &I.x);
             I.x.vec = (X->KM % 16 == 0) ? 1u : 0u;
             lds = std::max(lds, need);
             std::string key = std::to_string(F.s) + ":" + std::to_string(X->M);
@@ -275,7 +315,7 @@ sqz_status batch_create(const sqz_fractal *const *fr, int32_t count, BatchHost *
             // tables are identical for one (pattern, M): use the first instance's copy
             for (int32_t p = 0; p < i; ++p)
                 if ((H->inst[p].kind == I.kind) && H->inst[p].xcfg == I.xcfg && H->inst[p].kind != kBCell &&
-                    H->inst[p].kind >= kBX66) {
+                    H->inst[p].kind >= kBX68) {
                     I.x.lam = H->inst[p].x.lam;
                     I.x.mem_in = H->inst[p].x.mem_in;
                     I.x.rpos = H->inst[p].x.rpos;
@@ -302,20 +342,24 @@ sqz_status batch_create(const sqz_fractal *const *fr, int32_t count, BatchHost *
     H->total_bytes = off;
     H->lds = std::max<size_t>(lds, 16);
     H->d_inst = nullptr;
-    H->d_cell_start = nullptr;
+    H->d_cost_start = nullptr;
     H->cap = nullptr;
     H->gexec = nullptr;
     e = hipMalloc(&H->d_inst, sizeof(BatchInst) * count);
-    if (e == hipSuccess) e = hipMemcpy(H->d_inst, H->inst.data(), sizeof(BatchInst) * count, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMalloc(&H->d_cell_start, sizeof(uint64_t) * (count + 1));
-    if (e == hipSuccess)
-        e = hipMemcpy(H->d_cell_start, cell_start.data(), sizeof(uint64_t) * (count + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&H->d_cost_start, sizeof(uint64_t) * (count + 1));
+    H->xt_weight = 4;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(H->key);
+        if (it != g_tune_cache.end()) H->xt_weight = it->second.second;
+    }
+    if (e == hipSuccess) e = upload_costs(H);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&H->cap, hipStreamNonBlocking);
     int per_cu = 0;
     if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_life, 256, H->lds);
     if (e != hipSuccess) {
         if (H->d_inst) (void)hipFree(H->d_inst);
-        if (H->d_cell_start) (void)hipFree(H->d_cell_start);
+        if (H->d_cost_start) (void)hipFree(H->d_cost_start);
         if (H->cap) (void)hipStreamDestroy(H->cap);
         delete H;
         return hip_error(e, "batch setup");
@@ -325,7 +369,7 @@ sqz_status batch_create(const sqz_fractal *const *fr, int32_t count, BatchHost *
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(H->key);
-        if (it != g_tune_cache.end()) H->wg_per_cu = std::min(it->second, H->max_wg_per_cu);
+        if (it != g_tune_cache.end()) H->wg_per_cu = std::min(it->second.first, H->max_wg_per_cu);
     }
     *out = H;
     return SQZ_OK;
@@ -337,7 +381,7 @@ void batch_destroy(BatchHost *H)
     if (H->gexec) (void)hipGraphExecDestroy(H->gexec);
     if (H->cap) (void)hipStreamDestroy(H->cap);
     (void)hipFree(H->d_inst);
-    (void)hipFree(H->d_cell_start);
+    (void)hipFree(H->d_cost_start);
     delete H;
 }
 
@@ -345,9 +389,9 @@ static sqz_status launch_batch(const BatchHost *H, unsigned wg_per_cu, const uin
 {
     BatchArgs A;
     A.inst = H->d_inst;
-    A.cell_start = H->d_cell_start;
+    A.cost_start = H->d_cost_start;
     A.ninst = (uint32_t)H->inst.size();
-    A.total_cells = H->total_cells;
+    A.total_cost = H->total_cost;
     uint64_t grid = (uint64_t)H->cus * wg_per_cu;
     if (grid < 1) grid = 1;
     hipLaunchKernelGGL(k_batch_life, dim3((unsigned)grid), dim3(256), H->lds, st, A, in, out);
@@ -400,28 +444,45 @@ sqz_status batch_autotune(BatchHost *H, uint8_t *a, uint8_t *b, hipStream_t st, 
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return set_error(SQZ_ERR_HIP, "hipEventCreate failed");
-    unsigned best = H->wg_per_cu;
+    bool has_xt = false;
+    for (const BatchInst &I : H->inst) has_xt |= I.kind >= kBX68 && I.kind <= kBXAny;
+    const unsigned weights[] = {2, 3, 4, 6, 8};
+    unsigned best = H->wg_per_cu, best_w = H->xt_weight;
     float best_ms = 1e30f;
     sqz_status st2 = SQZ_OK;
-    for (unsigned w = 1; w <= H->max_wg_per_cu && st2 == SQZ_OK; w = (w < 4 ? w + 1 : w * 2)) {
-        st2 = launch_batch(H, w, a, b, st);  // warm-up
-        if (st2 != SQZ_OK) break;
-        (void)hipEventRecord(e0, st);
-        for (int i = 0; i < 4 && st2 == SQZ_OK; ++i) st2 = launch_batch(H, w, (i & 1) ? b : a, (i & 1) ? a : b, st);
-        (void)hipEventRecord(e1, st);
-        if (hipEventSynchronize(e1) != hipSuccess) {
-            st2 = set_error(SQZ_ERR_HIP, "autotune synchronisation failed");
-            break;
+    for (unsigned wi = 0; wi < (has_xt ? 5u : 1u) && st2 == SQZ_OK; ++wi) {
+        if (has_xt) {
+            H->xt_weight = weights[wi];
+            hipError_t e = upload_costs(H);
+            if (e != hipSuccess) {
+                st2 = hip_error(e, "batch cost upload");
+                break;
+            }
         }
-        float ms = 0.0f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        if (ms < best_ms) {
-            best_ms = ms;
-            best = w;
+        for (unsigned w = 1; w <= H->max_wg_per_cu && st2 == SQZ_OK; w = (w < 4 ? w + 1 : w * 2)) {
+            st2 = launch_batch(H, w, a, b, st);  // warm-up
+            if (st2 != SQZ_OK) break;
+            (void)hipEventRecord(e0, st);
+            for (int i = 0; i < 4 && st2 == SQZ_OK; ++i) st2 = launch_batch(H, w, (i & 1) ? b : a, (i & 1) ? a : b, st);
+            (void)hipEventRecord(e1, st);
+            if (hipEventSynchronize(e1) != hipSuccess) {
+                st2 = set_error(SQZ_ERR_HIP, "autotune synchronisation failed");
+                break;
+            }
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = w;
+                best_w = H->xt_weight;
+            }
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    H->xt_weight = best_w;
+    hipError_t e = upload_costs(H);
+    if (st2 == SQZ_OK && e != hipSuccess) st2 = hip_error(e, "batch cost upload");
     if (st2 != SQZ_OK) return st2;
     H->wg_per_cu = best;
     if (H->gexec) {
@@ -430,7 +491,7 @@ sqz_status batch_autotune(BatchHost *H, uint8_t *a, uint8_t *b, hipStream_t st, 
     }
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune_cache[H->key] = best;
+        g_tune_cache[H->key] = std::make_pair(best, best_w);
     }
     if (best_out) *best_out = best;
     return SQZ_OK;

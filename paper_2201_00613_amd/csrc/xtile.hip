@@ -21,7 +21,12 @@ __global__ void __launch_bounds__(kXBlock) k_xtile(XArgs A, const typename Op::G
     const uint64_t chunk = (A.ntiles + gridDim.x - 1) / gridDim.x;
     const uint64_t t0 = (uint64_t)blockIdx.x * chunk;
     const uint64_t t1 = t0 + chunk < A.ntiles ? t0 + chunk : A.ntiles;
-    for (uint64_t t = t0; t < t1; ++t) xtile_body<Op, PT>(A, in, out, t, op, S);
+    if (A.KM == 16 * 256 && A.R <= 2 * 256)
+        xtile_run<Op, PT, 16, 2, true>(A, in, out, t0, t1, op, S);
+    else if (A.KM <= 16 * 256 && A.R <= 2 * 256)
+        xtile_run<Op, PT, 16, 2>(A, in, out, t0, t1, op, S);
+    else
+        for (uint64_t t = t0; t < t1; ++t) xtile_body<Op, PT>(A, in, out, t, op, S);
 }
 
 // ---------------------------------------------------------------------------
@@ -182,11 +187,11 @@ sqz_status xtile_prepare(FractalHost &F)
             B *= F.s;
             KM *= F.k;
         }
-        const uint64_t P = B + 2;
+        const uint64_t P = (B + 2 + 3) / 4 * 4;  // ring on both sides, pitch a multiple of 4
         if (P * P > 65535 || KM > 65535) continue;
-        if (xt_layout((uint32_t)P, (uint32_t)KM, 0, 4, true, nullptr) > kXLdsBudget) continue;
+        if (xt_layout((uint32_t)P, (uint32_t)KM, 0, 4, true, false, nullptr) > kXLdsBudget) continue;
         ring_slots(F, M, (uint32_t)P, ring);
-        if (xt_layout((uint32_t)P, (uint32_t)KM, (uint32_t)ring.size(), 4, true, nullptr) <= kXLdsBudget) break;
+        if (xt_layout((uint32_t)P, (uint32_t)KM, (uint32_t)ring.size(), 4, true, false, nullptr) <= kXLdsBudget) break;
     }
     if (M < 1) return SQZ_OK;  // no expanded tile for this pattern
     XTileConfig *X = new XTileConfig();
@@ -197,7 +202,7 @@ sqz_status xtile_prepare(FractalHost &F)
         X->B *= F.s;
         X->KM *= F.k;
     }
-    X->P = X->B + 2;
+    X->P = (X->B + 2 + 3) / 4 * 4;
     X->R = (uint32_t)ring.size();
     const uint32_t P = X->P, KM = X->KM, R = X->R;
 
@@ -236,13 +241,14 @@ sqz_status xtile_prepare(FractalHost &F)
     X->base.ntiles = X->ntiles;
     X->base.KM = KM;
     X->base.P = P;
+    X->base.B = X->B;
     X->base.R = R;
     X->base.lam = (const uint16_t *)(b + o_lam);
     X->base.mem_in = b + o_mem;
     X->base.rpos = (const uint16_t *)(b + o_rpos);
     X->base.rinfo = (const uint32_t *)(b + o_rinfo);
-    X->lds_life = xt_layout(P, KM, R, 1, false, nullptr);
-    X->lds_diff = xt_layout(P, KM, R, 4, true, nullptr);
+    X->lds_life = xt_layout(P, KM, R, 1, false, true, nullptr);
+    X->lds_diff = xt_layout(P, KM, R, 4, true, false, nullptr);
     X->grid_life = occupancy_grid<XLife, 0>(X->lds_life, X->ntiles, F.device);
     X->grid_diff = occupancy_grid<XDiffF32, 0>(X->lds_diff, X->ntiles, F.device);
     F.xtile = X;
@@ -266,15 +272,15 @@ static sqz_status launch_x(const FractalHost &F, const void *in, void *out, cons
     const XTileConfig *X = F.xtile;
     XArgs A = X->base;
     const bool life = !Op::kMem;
-    const size_t lds = xt_layout(X->P, X->KM, X->R, sizeof(typename Op::L), Op::kMem, &A);
+    const size_t lds = xt_layout(X->P, X->KM, X->R, sizeof(typename Op::L), Op::kMem, Op::kSwar, &A);
     A.vec = ((X->KM * sizeof(typename Op::G)) % 16 == 0 && !(((uintptr_t)in | (uintptr_t)out) & 15)) ? 1u : 0u;
     const unsigned grid = life ? X->grid_life : X->grid_diff;
     using G = typename Op::G;
     const G *i = (const G *)in;
     G *o = (G *)out;
     switch (X->P) {
-    case 66: hipLaunchKernelGGL((k_xtile<Op, 66>), dim3(grid), dim3(kXBlock), lds, st, A, i, o, op); break;
-    case 83: hipLaunchKernelGGL((k_xtile<Op, 83>), dim3(grid), dim3(kXBlock), lds, st, A, i, o, op); break;
+    case 68: hipLaunchKernelGGL((k_xtile<Op, 68>), dim3(grid), dim3(kXBlock), lds, st, A, i, o, op); break;
+    case 84: hipLaunchKernelGGL((k_xtile<Op, 84>), dim3(grid), dim3(kXBlock), lds, st, A, i, o, op); break;
     default: hipLaunchKernelGGL((k_xtile<Op, 0>), dim3(grid), dim3(kXBlock), lds, st, A, i, o, op); break;
     }
     hipError_t e = hipGetLastError();

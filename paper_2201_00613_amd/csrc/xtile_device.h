@@ -34,8 +34,8 @@ constexpr size_t kXLdsBudget = 48 * 1024;
 
 struct XArgs {
     uint64_t ntiles;
-    uint32_t KM, P, R;
-    uint32_t off_mem, off_lam, off_rpos, off_rinfo, off_nbase;
+    uint32_t KM, P, R, B;  // cells per tile, row pitch (multiple of 4), ring slots, box side
+    uint32_t off_val, off_res, off_mem, off_lam, off_rpos, off_rinfo, off_nbase;
     uint32_t vec;  // 1 when a tile is a whole number of 16-byte vectors
     const uint16_t *lam;
     const uint8_t *mem_in;
@@ -54,18 +54,21 @@ struct XLife {
     using G = uint8_t;
     using L = uint8_t;
     static constexpr bool kMem = false;
+    static constexpr bool kSwar = true;  // row-wise SIMD-within-a-register update
     static constexpr int kVec = 16;
 };
 struct XDiffF32 {
     using G = float;
     using L = float;
     static constexpr bool kMem = true;
+    static constexpr bool kSwar = false;
     static constexpr int kVec = 4;
 };
 struct XDiffBF16 {
     using G = uint16_t;  // bfloat16 bits of delta
     using L = float;
     static constexpr bool kMem = true;
+    static constexpr bool kSwar = false;
     static constexpr int kVec = 8;
 };
 
@@ -73,14 +76,19 @@ __device__ __forceinline__ uint8_t to_lds(uint8_t v) { return v; }
 __device__ __forceinline__ float to_lds(float v) { return v; }
 __device__ __forceinline__ float to_lds(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
-// 16 pseudo-random bits per (seed, step, cell): SplitMix64's finaliser on a
-// Weyl combination of the three counters.
+// 16 pseudo-random bits per (seed, step, cell): the "lowbias32" integer
+// finaliser (C. Wellons, hash-prospector, 2018) of a Weyl combination of the
+// counters.  32-bit arithmetic keeps the per-cell cost and register use low.
 __device__ __forceinline__ uint32_t rand16(uint64_t seed, uint64_t step, uint64_t cell)
 {
-    uint64_t z = seed + (step + 1) * 0x9E3779B97F4A7C15ull + (cell + 1) * 0xD1B54A32D192ED03ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return (uint32_t)((z ^ (z >> 31)) >> 48);
+    uint32_t x = (uint32_t)cell ^ ((uint32_t)(cell >> 32) * 0x85EBCA6Bu);
+    x += (uint32_t)seed * 0x9E3779B9u + (uint32_t)(seed >> 32) + (uint32_t)step * 0x7FEB352Du;
+    x ^= x >> 16;
+    x *= 0x7FEB352Du;
+    x ^= x >> 15;
+    x *= 0x846CA68Bu;
+    x ^= x >> 16;
+    return x >> 16;
 }
 
 // binary32 -> bfloat16 bits: nearest-even, or stochastic (add 16 random bits
@@ -119,12 +127,13 @@ __device__ __forceinline__ typename Op::G cell_update(const typename Op::L *s_va
 template <class Op>
 struct XLds {
     typename Op::L *val;
+    uint8_t *res;  // row-update results (Life)
     uint8_t *mem;
     uint16_t *lam, *rpos;
     uint32_t *rinfo;
     uint64_t *nbase;
     __device__ XLds(unsigned char *smem, const XArgs &A)
-        : val(reinterpret_cast<typename Op::L *>(smem)), mem(smem + A.off_mem),
+        : val(reinterpret_cast<typename Op::L *>(smem + A.off_val)), res(smem + A.off_res), mem(smem + A.off_mem),
           lam(reinterpret_cast<uint16_t *>(smem + A.off_lam)), rpos(reinterpret_cast<uint16_t *>(smem + A.off_rpos)),
           rinfo(reinterpret_cast<uint32_t *>(smem + A.off_rinfo)), nbase(reinterpret_cast<uint64_t *>(smem + A.off_nbase))
     {
@@ -139,6 +148,12 @@ __device__ __forceinline__ void xtile_setup(const XArgs &A, const XLds<Op> &S)
     for (uint32_t i = tid; i < PP; i += kXBlock) {
         S.val[i] = (typename Op::L)0;
         if constexpr (Op::kMem) S.mem[i] = A.mem_in[i];
+    }
+    if constexpr (Op::kSwar) {  // the 16 bytes on either side of the box: row updates read them
+        uint32_t *before = reinterpret_cast<uint32_t *>(S.val) - 4;
+        uint32_t *after = reinterpret_cast<uint32_t *>(S.val + PP);
+        if (tid < 4) before[tid] = 0;
+        else if (tid < 8) after[tid - 4] = 0;
     }
     for (uint32_t i = tid; i < A.KM; i += kXBlock) S.lam[i] = A.lam[i];
     for (uint32_t i = tid; i < A.R; i += kXBlock) {
@@ -211,6 +226,148 @@ __device__ __forceinline__ void xtile_body(const XArgs &A, const typename Op::G 
     }
 }
 
+// Bases of the eight tiles adjacent to tile t (eight coarse nu at level r-M),
+// written by lanes 0..7 to dst[0..7]; kHole64 where there is no tile.
+__device__ __forceinline__ void xtile_bases(const XArgs &A, uint64_t t, uint64_t *dst)
+{
+    const uint32_t tid = threadIdx.x;
+    if (tid < 8) {
+        const int d = tid < 4 ? (int)tid : (int)tid + 1;
+        uint32_t X, Y;
+        if (A.Pc.N <= 0x100000000ull)
+            lam_map32(A.Pc, (uint32_t)t, X, Y);
+        else
+            lam_map64(A.Pc, t, X, Y);
+        const uint64_t nt = nu_map(A.Pc, (int32_t)X + d % 3 - 1, (int32_t)Y + d / 3 - 1);
+        dst[tid] = nt == kHole64 ? kHole64 : nt * A.KM;
+    }
+}
+
+// Tiles [t0, t1) with software pipelining: while tile t is updated from LDS,
+// the cells and ring cells of tile t+1 are already in flight into registers.
+// Cell l of a tile is handled by lane l mod 256 (cells k*256 + lane), so the
+// lanes of one wave touch one compact level-2 block: nearby expanded positions,
+// few LDS bank conflicts, and coalesced global accesses.  KPL >= KM/256 and
+// RPL >= R/256 bound the per-lane registers; FULL means KM == KPL * 256 (no
+// per-cell bounds test).  Called by every lane.
+template <class Op, int PT, int KPL, int RPL, bool FULL = false>
+__device__ __forceinline__ void xtile_run(const XArgs &A, const typename Op::G *__restrict__ in,
+                                          typename Op::G *__restrict__ out, uint64_t t0, uint64_t t1, const XOp &op,
+                                          const XLds<Op> &S)
+{
+    using G = typename Op::G;
+    using L = typename Op::L;
+    const uint32_t P = PT ? (uint32_t)PT : A.P;
+    const uint32_t KM = A.KM, R = A.R, tid = threadIdx.x;
+    if (t0 >= t1) return;
+    G cur[KPL];
+    L rv[RPL];
+    bool rm[RPL];
+    __syncthreads();  // tables and the previous work's LDS reads are done
+    xtile_bases(A, t0, S.nbase + 8 * (t0 & 1));
+    __syncthreads();
+    // prologue: tile t0's cells and ring into registers
+    {
+        const G *src = in + t0 * KM;
+        const uint64_t *nb = S.nbase + 8 * (t0 & 1);
+#pragma unroll
+        for (int k = 0; k < KPL; ++k) {
+            const uint32_t l = (uint32_t)k * 256 + tid;
+            if (FULL || l < KM) cur[k] = src[l];
+        }
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) {
+            const uint32_t j = (uint32_t)k * 256 + tid;
+            rv[k] = (L)0;
+            rm[k] = false;
+            if (j < R) {
+                const uint32_t info = S.rinfo[j];
+                const uint64_t b = nb[info >> 16];
+                if (b != kHole64) {
+                    rv[k] = to_lds(in[b + (info & 0xFFFFu)]);
+                    rm[k] = true;
+                }
+            }
+        }
+    }
+    for (uint64_t t = t0; t < t1; ++t) {
+        __syncthreads();  // previous tile's update no longer reads LDS
+#pragma unroll
+        for (int k = 0; k < KPL; ++k) {
+            const uint32_t l = (uint32_t)k * 256 + tid;
+            if (FULL || l < KM) S.val[S.lam[l]] = to_lds(cur[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) {
+            const uint32_t j = (uint32_t)k * 256 + tid;
+            if (j < R) {
+                S.val[S.rpos[j]] = rv[k];
+                if constexpr (Op::kMem) S.mem[S.rpos[j]] = rm[k];
+            }
+        }
+        const bool more = t + 1 < t1;
+        if (more) xtile_bases(A, t + 1, S.nbase + 8 * ((t + 1) & 1));
+        __syncthreads();
+        if (more) {  // issue tile t+1's loads before updating tile t
+            const G *src = in + (t + 1) * KM;
+            const uint64_t *nb = S.nbase + 8 * ((t + 1) & 1);
+#pragma unroll
+            for (int k = 0; k < KPL; ++k) {
+                const uint32_t l = (uint32_t)k * 256 + tid;
+                if (FULL || l < KM) cur[k] = src[l];
+            }
+#pragma unroll
+            for (int k = 0; k < RPL; ++k) {
+                const uint32_t j = (uint32_t)k * 256 + tid;
+                rv[k] = (L)0;
+                rm[k] = false;
+                if (j < R) {
+                    const uint32_t info = S.rinfo[j];
+                    const uint64_t b = nb[info >> 16];
+                    if (b != kHole64) {
+                        rv[k] = to_lds(in[b + (info & 0xFFFFu)]);
+                        rm[k] = true;
+                    }
+                }
+            }
+        }
+        G *dst = out + t * KM;
+        const uint64_t gbase = t * KM;
+        if constexpr (Op::kSwar) {
+            // Life on whole box rows, four positions per 32-bit word: byte-wise
+            // neighbour sums of the three rows shifted by one byte either way,
+            // then (count | self) == 3 per byte.  Ring and holes hold 0.
+            const uint32_t W4 = P / 4, nrow = A.B;
+            const uint32_t *v32 = reinterpret_cast<const uint32_t *>(S.val);
+            uint32_t *r32 = reinterpret_cast<uint32_t *>(S.res);
+            for (uint32_t idx = tid; idx < nrow * W4; idx += kXBlock) {
+                const uint32_t y = 1 + idx / W4, w = idx - (y - 1) * W4;
+                const uint32_t *q = v32 + (y - 1) * W4 + w;  // q[-1] and the word after the box are padding
+                const uint32_t a0 = q[-1], b0 = q[0], c0 = q[1];
+                const uint32_t a1 = q[W4 - 1], b1 = q[W4], c1 = q[W4 + 1];
+                const uint32_t a2 = q[2 * W4 - 1], b2 = q[2 * W4], c2 = q[2 * W4 + 1];
+                const uint32_t cnt = b0 + __builtin_amdgcn_alignbyte(b0, a0, 3) + __builtin_amdgcn_alignbyte(c0, b0, 1) +
+                                     b2 + __builtin_amdgcn_alignbyte(b2, a2, 3) + __builtin_amdgcn_alignbyte(c2, b2, 1) +
+                                     __builtin_amdgcn_alignbyte(b1, a1, 3) + __builtin_amdgcn_alignbyte(c1, b1, 1);
+                const uint32_t z = (cnt | b1) ^ 0x03030303u;
+                r32[y * W4 + w] = (~(((z & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | z) >> 7) & 0x01010101u;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < KPL; ++k) {
+                const uint32_t l = (uint32_t)k * 256 + tid;
+                if (FULL || l < KM) dst[l] = S.res[S.lam[l]];
+            }
+        } else {
+#pragma unroll 4
+            for (int k = 0; k < KPL; ++k) {
+                const uint32_t l = (uint32_t)k * 256 + tid;
+                if (FULL || l < KM) dst[l] = cell_update<Op>(S.val, S.mem, S.lam[l], P, op, gbase + l);
+            }
+        }
+    }
+}
+
 // Host-side configuration of the expanded tiles of one fractal.
 struct XTileConfig {
     int M;
@@ -225,9 +382,13 @@ struct XTileConfig {
 
 // LDS layout: values, membership bytes (diffusion), lambda table, ring tables, 8 bases.
 inline size_t xt_align16(size_t v) { return (v + 15) & ~(size_t)15; }
-inline size_t xt_layout(uint32_t P, uint32_t KM, uint32_t R, size_t val_bytes, bool mem, XArgs *A)
+inline size_t xt_layout(uint32_t P, uint32_t KM, uint32_t R, size_t val_bytes, bool mem, bool swar, XArgs *A)
 {
-    size_t off = xt_align16((size_t)P * P * val_bytes);
+    const size_t box = (size_t)P * P * val_bytes;
+    const size_t off_val = 16;  // padding on both sides: row updates read one word past each end
+    size_t off = xt_align16(off_val + box + 16);
+    const size_t off_res = off;
+    if (swar) off = xt_align16(off + (size_t)P * P);
     const size_t off_mem = off;
     if (mem) off = xt_align16(off + (size_t)P * P);
     const size_t off_lam = off;
@@ -237,8 +398,10 @@ inline size_t xt_layout(uint32_t P, uint32_t KM, uint32_t R, size_t val_bytes, b
     const size_t off_rinfo = off;
     off = xt_align16(off + (size_t)R * 4);
     const size_t off_nbase = off;
-    off += 8 * 8;
+    off += 16 * 8;  // two sets of eight adjacent-tile bases (double-buffered)
     if (A) {
+        A->off_val = (uint32_t)off_val;
+        A->off_res = (uint32_t)off_res;
         A->off_mem = (uint32_t)off_mem;
         A->off_lam = (uint32_t)off_lam;
         A->off_rpos = (uint32_t)off_rpos;
