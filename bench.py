@@ -110,6 +110,29 @@ def cpu_baseline(r: int, seed: int, p: float, min_sec: float, max_steps: int) ->
             "sample": f"{steps} full B3/S23 step(s) of the level-{r} triangle ({O.N} cells each), {sec:.1f} s"}
 
 
+def maps_leg(torch, F, seed, p, steps: int) -> dict:
+    """Scalar look-up-table maps vs matrix-core (int8 MFMA) maps at the benchmark level:
+    lambda over every compact index, nu over every fractal point, and the thread-level
+    Life step with each (one lambda and eight nu per cell)."""
+    idx = torch.arange(F.cells, dtype=torch.int64, device="cuda")
+    xy = torch.empty((F.cells, 2), dtype=torch.int32, device="cuda")
+    back = torch.empty(F.cells, dtype=torch.int64, device="cuda")
+    res = {"cells": F.cells, "steps": steps}
+    for impl in ("scalar", "mfma"):
+        sl = time_steps(torch, lambda i: F.lambda_map(idx, impl=impl, out=xy), steps, 2)
+        sn = time_steps(torch, lambda i: F.nu_map(xy, impl=impl, out=back), steps, 2)
+        life = "cell" if impl == "scalar" else "cell_mfma"
+        sc = compact_run(torch, F, seed, p, steps, 2, impl=life)
+        res[impl] = {"lambda_ms": sl * 1e3 / steps, "lambda_maps_per_s": F.cells * steps / sl,
+                     "nu_ms": sn * 1e3 / steps, "nu_maps_per_s": F.cells * steps / sn,
+                     "life_impl": life, "life_ms_per_step": sc * 1e3 / steps,
+                     "life_cell_updates_per_s": F.cells * steps / sc}
+    res["mfma_speedup"] = {k: res["scalar"][k] / res["mfma"][k] for k in ("lambda_ms", "nu_ms", "life_ms_per_step")}
+    del idx, xy, back
+    torch.cuda.empty_cache()
+    return res
+
+
 def batch_leg(torch, sqz, steps: int) -> dict:
     """512 instances drawn from seed over triangle, carpet and Vicsek (1e4..1e7 cells
     each), Bernoulli(0.5), `steps` steps as one graph replay after autotuning."""
@@ -200,6 +223,8 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-diffusion", action="store_true")
+    ap.add_argument("--no-maps", action="store_true")
+    ap.add_argument("--maps-steps", type=int, default=10)
     ap.add_argument("--batch-steps", type=int, default=50)
     ap.add_argument("--diffusion-steps", type=int, default=1000)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -258,6 +283,11 @@ def main() -> int:
                      "expanded_cells_per_s": F.n * F.n * args.bb_steps / bsec,
                      "algorithmic_gbs": 2 * F.n * F.n / (bsec / args.bb_steps) / 1e9, "steps": args.bb_steps}
         out["speedup_vs_bb"] = ups / bb_ups
+    if not args.no_maps:
+        out["map_variants"] = m = maps_leg(torch, F, seed, p, args.maps_steps)
+        log(f"[bench] maps scalar vs mfma: lambda {m['scalar']['lambda_ms']:.3f} / {m['mfma']['lambda_ms']:.3f} ms, "
+            f"nu {m['scalar']['nu_ms']:.3f} / {m['mfma']['nu_ms']:.3f} ms, "
+            f"cell Life {m['scalar']['life_ms_per_step']:.3f} / {m['mfma']['life_ms_per_step']:.3f} ms/step")
     del F
     torch.cuda.empty_cache()
     if not args.no_r20:

@@ -69,8 +69,28 @@ typedef enum sqz_layout { SQZ_LAYOUT_COMPACT = 0, SQZ_LAYOUT_EXPANDED = 1 } sqz_
  *                  subtree staged on chip.  SQZ_ERR_UNSUPPORTED if the pattern
  *                  has no tiled kernel. */
 /*   SQZ_IMPL_XTILE: block-level Squeeze with the level-M subtree expanded on chip
- *                  (any replica pattern; SQZ_ERR_UNSUPPORTED when no level fits). */
-typedef enum sqz_impl { SQZ_IMPL_AUTO = 0, SQZ_IMPL_CELL = 1, SQZ_IMPL_TILE = 2, SQZ_IMPL_XTILE = 3 } sqz_impl;
+ *                  (any replica pattern; SQZ_ERR_UNSUPPORTED when no level fits).
+ *   SQZ_IMPL_CELL_MFMA: CELL with both maps evaluated on the matrix cores
+ *                  (SQZ_MAP_MFMA below).  A comparison variant, never chosen by AUTO. */
+typedef enum sqz_impl {
+    SQZ_IMPL_AUTO = 0,
+    SQZ_IMPL_CELL = 1,
+    SQZ_IMPL_TILE = 2,
+    SQZ_IMPL_XTILE = 3,
+    SQZ_IMPL_CELL_MFMA = 4
+} sqz_impl;
+
+/* Evaluation of lambda and nu.
+ *   SQZ_MAP_SCALAR: integer arithmetic with chunked look-up tables (several
+ *                   levels per table entry).
+ *   SQZ_MAP_MFMA: the weighted digit sums as int8 matrix products (the
+ *                 encoding of Section "Accelerating Squeeze with Tensor Core
+ *                 Units", laid out for v_mfma_i32_32x32x16_i8: 7-bit limbs of
+ *                 the level weights times one digit per level, int32
+ *                 accumulation).  Exact: a column sum is at most
+ *                 r * 127 * (k - 1) < 2^19.  Requires k <= 127
+ *                 (SQZ_ERR_UNSUPPORTED otherwise).  Results equal SCALAR's. */
+typedef enum sqz_map_impl { SQZ_MAP_SCALAR = 0, SQZ_MAP_MFMA = 1 } sqz_map_impl;
 
 /* Storage type of the diffusion field. */
 typedef enum sqz_dtype { SQZ_F32 = 0, SQZ_BF16 = 1 } sqz_dtype;
@@ -156,6 +176,13 @@ SQZ_API sqz_status sqz_lambda_map(const sqz_fractal *f, const uint64_t *d_idx, i
  */
 SQZ_API sqz_status sqz_nu_map(const sqz_fractal *f, const int32_t *d_xy, int64_t count, uint64_t *d_idx,
                       void *stream);
+
+/* sqz_lambda_map / sqz_nu_map with an explicit evaluation (sqz_map_impl);
+ * SQZ_ERR_INVALID for an unknown value. */
+SQZ_API sqz_status sqz_lambda_map_impl(const sqz_fractal *f, sqz_map_impl impl, const uint64_t *d_idx,
+                                       int64_t count, int32_t *d_xy, void *stream);
+SQZ_API sqz_status sqz_nu_map_impl(const sqz_fractal *f, sqz_map_impl impl, const int32_t *d_xy, int64_t count,
+                                   uint64_t *d_idx, void *stream);
 
 /*
  * Seeded Bernoulli(p) start, keyed by the expanded coordinate: the cell at

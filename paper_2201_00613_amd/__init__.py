@@ -9,12 +9,13 @@ from __future__ import annotations
 
 import ctypes
 
-from ._lib import (BF16, F32, HOLE, IMPL_AUTO, IMPL_CELL, IMPL_TILE, IMPL_XTILE, LAYOUT_COMPACT, LAYOUT_EXPANDED,
+from ._lib import (BF16, F32, HOLE, IMPL_AUTO, IMPL_CELL, IMPL_CELL_MFMA, IMPL_TILE, IMPL_XTILE, MAP_MFMA, MAP_SCALAR, LAYOUT_COMPACT, LAYOUT_EXPANDED,
                    MASS_WORK_DOUBLES, ROUND_NEAREST_EVEN, ROUND_STOCHASTIC, Diffusion, Info, SqueezeError, check, lib)
 
 __all__ = ["Fractal", "SqueezeError", "HOLE", "descriptor_check", "IMPLS"]
 
-IMPLS = {"auto": IMPL_AUTO, "cell": IMPL_CELL, "tile": IMPL_TILE, "xtile": IMPL_XTILE}
+IMPLS = {"auto": IMPL_AUTO, "cell": IMPL_CELL, "tile": IMPL_TILE, "xtile": IMPL_XTILE, "cell_mfma": IMPL_CELL_MFMA}
+MAP_IMPLS = {"scalar": MAP_SCALAR, "mfma": MAP_MFMA}
 DTYPES = {"f32": F32, "bf16": BF16}
 ROUNDINGS = {"nearest": ROUND_NEAREST_EVEN, "stochastic": ROUND_STOCHASTIC}
 
@@ -100,25 +101,31 @@ class Fractal:
         return torch.empty(numel, dtype=torch.uint8, device=self.device)
 
     # -- maps -----------------------------------------------------------------
-    def lambda_map(self, idx):
-        """idx: int64 tensor (read as uint64) -> (count, 2) int32 (x, y); (-1,-1) past the end."""
+    def lambda_map(self, idx, impl: str = "scalar", out=None):
+        """idx: int64 tensor (read as uint64) -> (count, 2) int32 (x, y); (-1,-1) past the end.
+        impl: "scalar" (look-up tables) or "mfma" (matrix-core digit sums)."""
         torch, dev, st = self._ctx()
         idx = idx.contiguous()
-        out = torch.empty((idx.numel(), 2), dtype=torch.int32, device=self.device)
         self._need(idx, torch.int64, idx.numel(), "idx")
+        if out is None:
+            out = torch.empty((idx.numel(), 2), dtype=torch.int32, device=self.device)
+        self._need(out, torch.int32, 2 * idx.numel(), "out")
         with dev:
-            check(lib().sqz_lambda_map(self._h, _ptr(idx), idx.numel(), _ptr(out), st))
+            check(lib().sqz_lambda_map_impl(self._h, MAP_IMPLS[impl], _ptr(idx), idx.numel(), _ptr(out), st))
         return out
 
-    def nu_map(self, xy):
-        """xy: (count, 2) int32 -> int64 tensor of compact indices, -1 (= SQZ_HOLE) for holes."""
+    def nu_map(self, xy, impl: str = "scalar", out=None):
+        """xy: (count, 2) int32 -> int64 tensor of compact indices, -1 (= SQZ_HOLE) for holes.
+        impl: "scalar" (look-up tables) or "mfma" (matrix-core digit sums)."""
         torch, dev, st = self._ctx()
         xy = xy.contiguous()
         count = xy.numel() // 2
         self._need(xy, torch.int32, 2 * count, "xy")
-        out = torch.empty(count, dtype=torch.int64, device=self.device)
+        if out is None:
+            out = torch.empty(count, dtype=torch.int64, device=self.device)
+        self._need(out, torch.int64, count, "out")
         with dev:
-            check(lib().sqz_nu_map(self._h, _ptr(xy), count, _ptr(out), st))
+            check(lib().sqz_nu_map_impl(self._h, MAP_IMPLS[impl], _ptr(xy), count, _ptr(out), st))
         return out
 
     # -- starts ---------------------------------------------------------------

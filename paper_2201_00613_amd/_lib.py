@@ -11,7 +11,8 @@ LIB_PATH = os.path.join(_HERE, "libsqueeze.so")
 OK, ERR_INVALID, ERR_RANGE, ERR_NOMEM, ERR_HIP, ERR_UNSUPPORTED = range(6)
 HOLE = (1 << 64) - 1
 LAYOUT_COMPACT, LAYOUT_EXPANDED = 0, 1
-IMPL_AUTO, IMPL_CELL, IMPL_TILE, IMPL_XTILE = 0, 1, 2, 3
+IMPL_AUTO, IMPL_CELL, IMPL_TILE, IMPL_XTILE, IMPL_CELL_MFMA = 0, 1, 2, 3, 4
+MAP_SCALAR, MAP_MFMA = 0, 1
 F32, BF16 = 0, 1
 ROUND_NEAREST_EVEN, ROUND_STOCHASTIC = 0, 1
 MASS_WORK_DOUBLES = 1025
@@ -51,6 +52,10 @@ SIGNATURES = {
                                       ctypes.c_void_p]),
     "sqz_nu_map": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                   ctypes.c_void_p]),
+    "sqz_lambda_map_impl": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int64,
+                                           ctypes.c_void_p, ctypes.c_void_p]),
+    "sqz_nu_map_impl": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int64,
+                                       ctypes.c_void_p, ctypes.c_void_p]),
     "sqz_fill_bernoulli": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_double, ctypes.c_int,
                                           ctypes.c_void_p, ctypes.c_void_p]),
     "sqz_fill_uniform": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]),

@@ -320,10 +320,12 @@ sqz_status sqz_fractal_create(int32_t s, int32_t k, const int32_t *offsets_xy, i
     f->h.tile_kind = tile_kind_for(f->h);
     f->h.tile = nullptr;
     f->h.xtile = nullptr;
+    f->h.mfma = mfma_prepare(f->h);  // null when the pattern does not fit int8 digits
     if (f->h.tile_kind) st = tile_prepare(f->h);
     if (st == SQZ_OK) st = xtile_prepare(f->h);
     if (st != SQZ_OK) {
         tile_release(f->h);
+        mfma_release(f->h);
         (void)hipFree(f->h.d_tables);
         delete f;
         return st;
@@ -337,6 +339,7 @@ void sqz_fractal_destroy(sqz_fractal *f)
     if (!f) return;
     tile_release(f->h);
     xtile_release(f->h);
+    mfma_release(f->h);
     if (f->h.d_tables) (void)hipFree(f->h.d_tables);
     delete f;
 }
@@ -362,24 +365,48 @@ static sqz_status check_handle(const sqz_fractal *f)
     return SQZ_OK;
 }
 
-sqz_status sqz_lambda_map(const sqz_fractal *f, const uint64_t *d_idx, int64_t count, int32_t *d_xy, void *stream)
+static sqz_status check_map_impl(const sqz_fractal *f, sqz_map_impl impl)
+{
+    if (impl != SQZ_MAP_SCALAR && impl != SQZ_MAP_MFMA) return set_error(SQZ_ERR_INVALID, "unknown map evaluation %d", (int)impl);
+    if (impl == SQZ_MAP_MFMA && !f->h.mfma)
+        return set_error(SQZ_ERR_UNSUPPORTED, "matrix-core maps need k <= 127 (k = %d)", f->h.k);
+    return SQZ_OK;
+}
+
+sqz_status sqz_lambda_map_impl(const sqz_fractal *f, sqz_map_impl impl, const uint64_t *d_idx, int64_t count,
+                               int32_t *d_xy, void *stream)
 {
     sqz_status st = check_handle(f);
     if (st != SQZ_OK) return st;
+    if ((st = check_map_impl(f, impl)) != SQZ_OK) return st;
     if (count < 0) return set_error(SQZ_ERR_INVALID, "count < 0");
     if (count == 0) return SQZ_OK;
     if (!d_idx || !d_xy) return set_error(SQZ_ERR_INVALID, "NULL buffer");
+    if (impl == SQZ_MAP_MFMA) return launch_lambda_mfma(f->h, d_idx, count, d_xy, (hipStream_t)stream);
     return launch_lambda(f->h.P, d_idx, count, d_xy, (hipStream_t)stream);
+}
+
+sqz_status sqz_nu_map_impl(const sqz_fractal *f, sqz_map_impl impl, const int32_t *d_xy, int64_t count,
+                           uint64_t *d_idx, void *stream)
+{
+    sqz_status st = check_handle(f);
+    if (st != SQZ_OK) return st;
+    if ((st = check_map_impl(f, impl)) != SQZ_OK) return st;
+    if (count < 0) return set_error(SQZ_ERR_INVALID, "count < 0");
+    if (count == 0) return SQZ_OK;
+    if (!d_idx || !d_xy) return set_error(SQZ_ERR_INVALID, "NULL buffer");
+    if (impl == SQZ_MAP_MFMA) return launch_nu_mfma(f->h, d_xy, count, d_idx, (hipStream_t)stream);
+    return launch_nu(f->h.P, d_xy, count, d_idx, (hipStream_t)stream);
+}
+
+sqz_status sqz_lambda_map(const sqz_fractal *f, const uint64_t *d_idx, int64_t count, int32_t *d_xy, void *stream)
+{
+    return sqz_lambda_map_impl(f, SQZ_MAP_SCALAR, d_idx, count, d_xy, stream);
 }
 
 sqz_status sqz_nu_map(const sqz_fractal *f, const int32_t *d_xy, int64_t count, uint64_t *d_idx, void *stream)
 {
-    sqz_status st = check_handle(f);
-    if (st != SQZ_OK) return st;
-    if (count < 0) return set_error(SQZ_ERR_INVALID, "count < 0");
-    if (count == 0) return SQZ_OK;
-    if (!d_idx || !d_xy) return set_error(SQZ_ERR_INVALID, "NULL buffer");
-    return launch_nu(f->h.P, d_xy, count, d_idx, (hipStream_t)stream);
+    return sqz_nu_map_impl(f, SQZ_MAP_SCALAR, d_xy, count, d_idx, stream);
 }
 
 sqz_status sqz_fill_bernoulli(const sqz_fractal *f, uint64_t seed, double p, sqz_layout layout, uint8_t *d_state,
@@ -437,6 +464,9 @@ sqz_status sqz_compact_step_impl(const sqz_fractal *f, sqz_impl impl, const uint
     case SQZ_IMPL_XTILE:
         if (!f->h.xtile) return set_error(SQZ_ERR_UNSUPPORTED, "no expanded tile fits this fractal");
         return launch_life_xtile(f->h, d_in, d_out, s);
+    case SQZ_IMPL_CELL_MFMA:
+        if (!f->h.mfma) return set_error(SQZ_ERR_UNSUPPORTED, "matrix-core maps need k <= 127 (k = %d)", f->h.k);
+        return launch_life_cell_mfma(f->h, d_in, d_out, s);
     }
     return set_error(SQZ_ERR_INVALID, "unknown implementation %d", (int)impl);
 }

@@ -160,6 +160,7 @@ __device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t i)
 // ---------------------------------------------------------------------------
 struct TileConfig;   // defined in life_tile.hip
 struct XTileConfig;  // defined in xtile.hip
+struct MfmaParams;   // defined in mfma_maps.hip
 
 struct FractalHost {
     int32_t s, k, r;
@@ -174,6 +175,7 @@ struct FractalHost {
     int tile_kind;                // 0 = none
     TileConfig *tile;
     XTileConfig *xtile;           // expanded-tile kernels (any pattern), null if none
+    MfmaParams *mfma;             // matrix-core map variants, null if unsupported (k > 127)
 };
 
 // Host helpers (api.cpp)
@@ -192,6 +194,13 @@ sqz_status launch_fill_bernoulli(const MapParams &P, uint64_t seed, uint32_t thr
                                  uint8_t *out, hipStream_t st);
 sqz_status launch_fill_uniform(const MapParams &P, uint64_t seed, float *out, hipStream_t st);
 sqz_status launch_life_cell(const MapParams &P, const uint8_t *in, uint8_t *out, hipStream_t st);
+
+// Matrix-core map variants (mfma_maps.hip)
+MfmaParams *mfma_prepare(const FractalHost &F);
+void mfma_release(FractalHost &F);
+sqz_status launch_lambda_mfma(const FractalHost &F, const uint64_t *idx, int64_t count, int32_t *xy, hipStream_t st);
+sqz_status launch_nu_mfma(const FractalHost &F, const int32_t *xy, int64_t count, uint64_t *idx, hipStream_t st);
+sqz_status launch_life_cell_mfma(const FractalHost &F, const uint8_t *in, uint8_t *out, hipStream_t st);
 
 // Expanded bounding-box baseline (bb.hip)
 sqz_status launch_life_bb(const FractalHost &F, const uint8_t *in, uint8_t *out, hipStream_t st);
