@@ -45,15 +45,41 @@ def time_steps(torch, step, steps: int, warmup: int):
     return start.elapsed_time(end) / 1e3
 
 
+def run_launches(F, steps: int) -> int:
+    """Launches sqz_compact_run makes for `steps` steps: two steps per launch when the
+    two-step tiled kernel exists, with the launch count's parity equal to that of
+    `steps` (two one-step launches replace one two-step launch when needed)."""
+    if F.run_steps_per_launch != 2:
+        return steps
+    n2, n1 = steps // 2, steps % 2
+    if (n2 + n1) % 2 != steps % 2:
+        n2, n1 = n2 - 1, n1 + 2
+    return n2 + n1
+
+
 def compact_run(torch, F, seed, p, steps, warmup, impl="auto"):
+    """Seconds for `steps` Life steps after `warmup` untimed ones.  impl "auto" runs
+    them as one sqz_compact_run call (the library's step loop); other impls launch
+    one step at a time."""
     a = F.fill_bernoulli(seed, p)
     b = torch.empty_like(a)
-    bufs = (a, b)
+    if impl == "auto":
+        x = F.compact_run(a, b, warmup)
+        y = b if x is a else a
+        torch.cuda.synchronize()
+        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record()
+        F.compact_run(x, y, steps)
+        end.record()
+        torch.cuda.synchronize()
+        sec = start.elapsed_time(end) / 1e3
+    else:
+        bufs = (a, b)
 
-    def step(i):
-        F.compact_step(bufs[i & 1], bufs[(i + 1) & 1], impl=impl)
+        def step(i):
+            F.compact_step(bufs[i & 1], bufs[(i + 1) & 1], impl=impl)
 
-    sec = time_steps(torch, step, steps, warmup)
+        sec = time_steps(torch, step, steps, warmup)
     del a, b
     return sec
 
@@ -129,6 +155,37 @@ def maps_leg(torch, F, seed, p, steps: int) -> dict:
                      "life_cell_updates_per_s": F.cells * steps / sc}
     res["mfma_speedup"] = {k: res["scalar"][k] / res["mfma"][k] for k in ("lambda_ms", "nu_ms", "life_ms_per_step")}
     del idx, xy, back
+    torch.cuda.empty_cache()
+    return res
+
+
+def blocks_leg(torch, F, seed, p, steps: int) -> dict:
+    """The block-size / memory trade-off at the benchmark level: for blocks of side
+    rho = 2^m, Life steps on micro-block storage (k^(r-m) blocks of rho x rho bytes)
+    and with the lambda(omega) approach (expanded n x n array, workgroups over the
+    compact grid of blocks).  Memory is the two state buffers."""
+    res = {"cells": F.cells, "steps": steps, "expanded_bytes_x2": 2 * F.n * F.n, "micro_blocks": [],
+           "lambda_omega": []}
+    a = F.fill_bernoulli(seed, p)
+    for m in range(0, 7):
+        nbytes = F.microblock_bytes(m)
+        x = F.microblock_pack(a, m)
+        y = torch.empty_like(x)
+        bufs = (x, y)
+        sec = time_steps(torch, lambda i: F.microblock_step(bufs[i & 1], bufs[(i + 1) & 1], m), steps, 2)
+        res["micro_blocks"].append({"rho": 2 ** m, "bytes_x2": 2 * nbytes, "mrf": F.n * F.n / nbytes,
+                                    "ms_per_step": sec * 1e3 / steps, "cell_updates_per_s": F.cells * steps / sec})
+        del x, y, bufs
+    del a
+    torch.cuda.empty_cache()
+    e = F.fill_bernoulli(seed, p, layout="expanded")
+    f = e.clone()
+    bufs = (e, f)
+    for m in range(0, 7):
+        sec = time_steps(torch, lambda i: F.lambda_omega_step(bufs[i & 1], bufs[(i + 1) & 1], m), steps, 2)
+        res["lambda_omega"].append({"rho": 2 ** m, "ms_per_step": sec * 1e3 / steps,
+                                    "cell_updates_per_s": F.cells * steps / sec})
+    del e, f, bufs
     torch.cuda.empty_cache()
     return res
 
@@ -224,6 +281,8 @@ def main() -> int:
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-diffusion", action="store_true")
     ap.add_argument("--no-maps", action="store_true")
+    ap.add_argument("--no-blocks", action="store_true")
+    ap.add_argument("--blocks-steps", type=int, default=5)
     ap.add_argument("--maps-steps", type=int, default=10)
     ap.add_argument("--batch-steps", type=int, default=50)
     ap.add_argument("--diffusion-steps", type=int, default=1000)
@@ -256,8 +315,11 @@ def main() -> int:
     sec = compact_run(torch, F, seed, p, args.steps, args.warmup, args.impl)
     ups = F.cells * args.steps / sec
     ms = sec * 1e3 / args.steps
-    gbs = BYTES_PER_UPDATE * F.cells / (sec / args.steps) / 1e9
-    log(f"[bench] compact: {ms:.4f} ms/step, {ups:.4e} cell-updates/s, {gbs:.1f} GB/s algorithmic")
+    launches = run_launches(F, args.steps) if args.impl == "auto" else args.steps
+    # algorithmic bytes per launch: each launch reads and writes every cell once
+    gbs = BYTES_PER_UPDATE * F.cells * launches / sec / 1e9
+    log(f"[bench] compact: {ms:.4f} ms/step ({launches} launches), {ups:.4e} cell-updates/s, "
+        f"{gbs:.1f} GB/s algorithmic per launch")
 
     out = {
         "metric": METRIC, "value": ups, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
@@ -265,13 +327,20 @@ def main() -> int:
         "vs_baseline": None, "dtype": "u8", "data": "synthetic",
         "config": {"workload": f"sierpinski-triangle-r{r}-life-b3s23", "fractal": "sierpinski triangle s=2 k=3",
                    "level": r, "cells": F.cells, "bernoulli_p": p, "seed": seed, "impl": args.impl,
-                   "tile_level": F.tile_level, "note": "2 x 43 MB working set is Infinity-Cache resident"},
+                   "tile_level": F.tile_level, "steps_per_launch": args.steps / launches,
+                   "note": "2 x 43 MB working set is Infinity-Cache resident"},
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs / HBM_PEAK_GBS, "traffic": None},
     }
+    if args.impl == "auto" and F.run_steps_per_launch == 2:
+        s1 = compact_run(torch, F, seed, p, args.steps, args.warmup, "tile")
+        out["one_step_per_launch"] = {"ms_per_step": s1 * 1e3 / args.steps,
+                                      "cell_updates_per_s": F.cells * args.steps / s1,
+                                      "algorithmic_gbs": BYTES_PER_UPDATE * F.cells * args.steps / s1 / 1e9}
+        log(f"[bench] one step per launch: {s1 * 1e3 / args.steps:.4f} ms/step")
     rec = profiled_traffic(out["config"]["workload"]) if args.impl == "auto" else None
     if rec:
-        out["roofline"]["traffic"] = rec["traffic_bytes_per_launch"] / (sec / args.steps) / 1e9
+        out["roofline"]["traffic"] = rec["traffic_bytes_per_launch"] / (sec / launches) / 1e9
         out["roofline"]["traffic_bytes_per_launch"] = rec["traffic_bytes_per_launch"]
         out["roofline"]["traffic_vs_algorithmic"] = rec["traffic_bytes_per_launch"] / (BYTES_PER_UPDATE * F.cells)
     if not args.no_bb:
@@ -283,6 +352,10 @@ def main() -> int:
                      "expanded_cells_per_s": F.n * F.n * args.bb_steps / bsec,
                      "algorithmic_gbs": 2 * F.n * F.n / (bsec / args.bb_steps) / 1e9, "steps": args.bb_steps}
         out["speedup_vs_bb"] = ups / bb_ups
+    if not args.no_blocks:
+        out["block_layouts"] = bl = blocks_leg(torch, F, seed, p, args.blocks_steps)
+        log("[bench] micro-blocks rho/ms: " + ", ".join(f"{d['rho']}:{d['ms_per_step']:.3f}" for d in bl["micro_blocks"]))
+        log("[bench] lambda(omega) rho/ms: " + ", ".join(f"{d['rho']}:{d['ms_per_step']:.3f}" for d in bl["lambda_omega"]))
     if not args.no_maps:
         out["map_variants"] = m = maps_leg(torch, F, seed, p, args.maps_steps)
         log(f"[bench] maps scalar vs mfma: lambda {m['scalar']['lambda_ms']:.3f} / {m['mfma']['lambda_ms']:.3f} ms, "
@@ -294,11 +367,15 @@ def main() -> int:
         F20 = sqz.Fractal(*TRIANGLE, 20)
         s20 = compact_run(torch, F20, seed, 0.3, args.r20_steps, 2)
         ms20 = s20 * 1e3 / args.r20_steps
-        gbs20 = BYTES_PER_UPDATE * F20.cells / (s20 / args.r20_steps) / 1e9
-        out["r20"] = {"cells": F20.cells, "steps": args.r20_steps, "ms_per_step": ms20,
-                      "cell_updates_per_s": F20.cells * args.r20_steps / s20, "algorithmic_gbs": gbs20,
-                      "hbm_frac": gbs20 / HBM_PEAK_GBS, "bernoulli_p": 0.3}
-        log(f"[bench] r=20: {ms20:.3f} ms/step, {gbs20:.1f} GB/s ({100 * gbs20 / HBM_PEAK_GBS:.1f}% of HBM peak)")
+        l20 = run_launches(F20, args.r20_steps)
+        gbs20 = BYTES_PER_UPDATE * F20.cells * l20 / s20 / 1e9
+        out["r20"] = {"cells": F20.cells, "steps": args.r20_steps, "launches": l20, "ms_per_step": ms20,
+                      "ms_per_launch": s20 * 1e3 / l20, "cell_updates_per_s": F20.cells * args.r20_steps / s20,
+                      "algorithmic_gbs_per_launch": gbs20, "hbm_frac": gbs20 / HBM_PEAK_GBS,
+                      "step_equivalent_gbs": BYTES_PER_UPDATE * F20.cells * args.r20_steps / s20 / 1e9,
+                      "bernoulli_p": 0.3}
+        log(f"[bench] r=20: {ms20:.3f} ms/step, {l20} launches, {gbs20:.1f} GB/s per launch "
+            f"({100 * gbs20 / HBM_PEAK_GBS:.1f}% of HBM peak)")
         del F20
         torch.cuda.empty_cache()
     if not args.no_batch:

@@ -129,6 +129,9 @@ typedef struct sqz_info {
     uint64_t compact_h;  /* height, k^floor(r/2) (Section "Compacting NBB Fractals") */
     int32_t has_tile;    /* 1 if SQZ_IMPL_TILE is available for this pattern */
     int32_t xtile_level; /* level of the expanded tiles of SQZ_IMPL_XTILE (0 if none) */
+    int32_t run_steps_per_launch; /* Life steps per launch in sqz_compact_run with 16-byte aligned
+                                     buffers: 2 with the two-step tiled kernel, else 1 */
+    int32_t reserved;
 } sqz_info;
 
 /*
@@ -232,6 +235,40 @@ SQZ_API sqz_status sqz_compact_run(const sqz_fractal *f, uint8_t *d_a, uint8_t *
  */
 SQZ_API sqz_status sqz_expanded_step(const sqz_fractal *f, const uint8_t *d_in, uint8_t *d_out,
                              void *stream);
+
+/*
+ * Block-level layouts (Section "Moving from Thread-level to Block-level";
+ * the approaches compared in Section "Experimental Setup and Results").
+ * block_level m: blocks are the level-m subtrees, side s^m (rho in the
+ * paper), k^(r-m) of them.  0 <= m <= r and s^m <= 64, else
+ * SQZ_ERR_RANGE (m outside [0, r]) or SQZ_ERR_UNSUPPORTED (side > 64).
+ * Buffers of the steps must be 4-byte aligned and must not overlap
+ * (SQZ_ERR_INVALID).  All steps compute the same Life rule as
+ * sqz_compact_step.
+ *
+ * lambda(omega) approach: states in the expanded n x n array (row-major,
+ * as sqz_expanded_step), workgroups launched over the compact grid of
+ * blocks, so only the k^(r-m) member blocks are read and written.  Cells
+ * outside member blocks are never written: d_out must hold 0 there (a
+ * buffer from sqz_fill_bernoulli(..., SQZ_LAYOUT_EXPANDED) or zeroed).
+ */
+SQZ_API sqz_status sqz_lambda_omega_step(const sqz_fractal *f, int32_t block_level, const uint8_t *d_in,
+                                         uint8_t *d_out, void *stream);
+
+/*
+ * Micro-block storage (block-level Squeeze memory): block t (compact order)
+ * at byte offset t * s^(2m), holding its s^m x s^m box row-major with holes
+ * stored as 0; *bytes = k^(r-m) s^(2m).  pack: compact (N bytes) -> blocks,
+ * every block byte written.  unpack: blocks -> compact.  step: one Life step
+ * from blocks to blocks.
+ */
+SQZ_API sqz_status sqz_microblock_bytes(const sqz_fractal *f, int32_t block_level, uint64_t *bytes);
+SQZ_API sqz_status sqz_microblock_pack(const sqz_fractal *f, int32_t block_level, const uint8_t *d_compact,
+                                       uint8_t *d_blocks, void *stream);
+SQZ_API sqz_status sqz_microblock_unpack(const sqz_fractal *f, int32_t block_level, const uint8_t *d_blocks,
+                                         uint8_t *d_compact, void *stream);
+SQZ_API sqz_status sqz_microblock_step(const sqz_fractal *f, int32_t block_level, const uint8_t *d_in,
+                                       uint8_t *d_out, void *stream);
 
 /*
  * One diffusion step (see sqz_diffusion).  d_in, d_out: N values of the

@@ -9,8 +9,8 @@ from __future__ import annotations
 
 import ctypes
 
-from ._lib import (BF16, F32, HOLE, IMPL_AUTO, IMPL_CELL, IMPL_CELL_MFMA, IMPL_TILE, IMPL_XTILE, MAP_MFMA, MAP_SCALAR, LAYOUT_COMPACT, LAYOUT_EXPANDED,
-                   MASS_WORK_DOUBLES, ROUND_NEAREST_EVEN, ROUND_STOCHASTIC, Diffusion, Info, SqueezeError, check, lib)
+from ._lib import (BF16, F32, HOLE, IMPL_AUTO, IMPL_CELL, IMPL_CELL_MFMA, IMPL_TILE, IMPL_XTILE, LAYOUT_COMPACT,
+                   LAYOUT_EXPANDED, MAP_MFMA, MAP_SCALAR, MASS_WORK_DOUBLES, ROUND_NEAREST_EVEN, ROUND_STOCHASTIC, Diffusion, Info, SqueezeError, check, lib)
 
 __all__ = ["Fractal", "SqueezeError", "HOLE", "descriptor_check", "IMPLS"]
 
@@ -73,6 +73,7 @@ class Fractal:
         self.has_tile = bool(info.has_tile)
         self.tile_level = info.tile_level
         self.xtile_level = info.xtile_level
+        self.run_steps_per_launch = info.run_steps_per_launch
         self.offsets = [tuple(map(int, xy)) for xy in offsets]
 
     def close(self):
@@ -171,6 +172,52 @@ class Fractal:
         self._need(dst.view(-1), torch.uint8, self.n * self.n, "dst")
         with dev:
             check(lib().sqz_expanded_step(self._h, _ptr(src), _ptr(dst), st))
+        return dst
+
+    # -- block-level layouts ---------------------------------------------------
+    def lambda_omega_step(self, src, dst, block_level: int):
+        """Life on the expanded n x n array with workgroups over the compact grid of
+        level-`block_level` blocks; cells outside member blocks of dst must be 0."""
+        torch, dev, st = self._ctx()
+        self._need(src.view(-1), torch.uint8, self.n * self.n, "src")
+        self._need(dst.view(-1), torch.uint8, self.n * self.n, "dst")
+        with dev:
+            check(lib().sqz_lambda_omega_step(self._h, block_level, _ptr(src), _ptr(dst), st))
+        return dst
+
+    def microblock_bytes(self, block_level: int) -> int:
+        v = ctypes.c_uint64()
+        check(lib().sqz_microblock_bytes(self._h, block_level, ctypes.byref(v)))
+        return v.value
+
+    def microblock_pack(self, compact, block_level: int, out=None):
+        torch, dev, st = self._ctx()
+        self._need(compact, torch.uint8, self.cells, "compact")
+        nbytes = self.microblock_bytes(block_level)
+        if out is None:
+            out = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._need(out, torch.uint8, nbytes, "out")
+        with dev:
+            check(lib().sqz_microblock_pack(self._h, block_level, _ptr(compact), _ptr(out), st))
+        return out
+
+    def microblock_unpack(self, blocks, block_level: int, out=None):
+        torch, dev, st = self._ctx()
+        self._need(blocks, torch.uint8, self.microblock_bytes(block_level), "blocks")
+        if out is None:
+            out = torch.empty(self.cells, dtype=torch.uint8, device=self.device)
+        self._need(out, torch.uint8, self.cells, "out")
+        with dev:
+            check(lib().sqz_microblock_unpack(self._h, block_level, _ptr(blocks), _ptr(out), st))
+        return out
+
+    def microblock_step(self, src, dst, block_level: int):
+        torch, dev, st = self._ctx()
+        nbytes = self.microblock_bytes(block_level)
+        self._need(src, torch.uint8, nbytes, "src")
+        self._need(dst, torch.uint8, nbytes, "dst")
+        with dev:
+            check(lib().sqz_microblock_step(self._h, block_level, _ptr(src), _ptr(dst), st))
         return dst
 
     # -- diffusion ------------------------------------------------------------

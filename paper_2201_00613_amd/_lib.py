@@ -30,6 +30,7 @@ class Info(ctypes.Structure):
         ("tile_level", ctypes.c_int32), ("n", ctypes.c_int64), ("cells", ctypes.c_uint64),
         ("compact_w", ctypes.c_uint64), ("compact_h", ctypes.c_uint64),
         ("has_tile", ctypes.c_int32), ("xtile_level", ctypes.c_int32),
+        ("run_steps_per_launch", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 
@@ -52,6 +53,15 @@ SIGNATURES = {
                                       ctypes.c_void_p]),
     "sqz_nu_map": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                   ctypes.c_void_p]),
+    "sqz_lambda_omega_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_void_p]),
+    "sqz_microblock_bytes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]),
+    "sqz_microblock_pack": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p]),
+    "sqz_microblock_unpack": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_void_p]),
+    "sqz_microblock_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p]),
     "sqz_lambda_map_impl": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int64,
                                            ctypes.c_void_p, ctypes.c_void_p]),
     "sqz_nu_map_impl": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int64,

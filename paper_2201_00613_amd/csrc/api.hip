@@ -351,6 +351,7 @@ sqz_status sqz_fractal_info(const sqz_fractal *f, sqz_info *out)
     out->has_tile = f->h.tile_kind != 0;
     out->tile_level = tile_level_of(f->h);
     out->xtile_level = xtile_level_of(f->h);
+    out->run_steps_per_launch = tile_two_step_ok(f->h) ? 2 : 1;
     return SQZ_OK;
 }
 
@@ -483,6 +484,30 @@ sqz_status sqz_compact_run(const sqz_fractal *f, uint8_t *d_a, uint8_t *d_b, int
     if (steps < 0) return set_error(SQZ_ERR_INVALID, "steps < 0");
     if (!d_a || !d_b) return set_error(SQZ_ERR_INVALID, "NULL buffer");
     if (overlap(d_a, d_b, f->h.N)) return set_error(SQZ_ERR_INVALID, "d_a and d_b overlap");
+    const bool aligned = !(((uintptr_t)d_a | (uintptr_t)d_b) & 15);
+    if (f->h.tile_kind && aligned && tile_two_step_ok(f->h)) {
+        // Two steps per launch (temporal blocking).  Every launch swaps the
+        // buffers, so the launch count must have the parity of `steps` for the
+        // result to land where one-step launches would leave it: n2 two-step
+        // launches bracketed by n1 / 2 one-step launches at each end.
+        int32_t n2 = steps / 2, n1 = steps - 2 * n2;
+        if (((n2 + n1) & 1) != (steps & 1)) {
+            n2 -= 1;
+            n1 += 2;
+        }
+        const hipStream_t s = (hipStream_t)stream;
+        int32_t launch = 0;
+        auto one = [&](bool two) {
+            const uint8_t *in = (launch & 1) ? d_b : d_a;
+            uint8_t *out = (launch & 1) ? d_a : d_b;
+            ++launch;
+            return two ? launch_life_tile2(f->h, in, out, s) : launch_life_tile(f->h, in, out, s);
+        };
+        for (int32_t i = 0; i < n1 / 2 && st == SQZ_OK; ++i) st = one(false);
+        for (int32_t i = 0; i < n2 && st == SQZ_OK; ++i) st = one(true);
+        for (int32_t i = n1 / 2; i < n1 && st == SQZ_OK; ++i) st = one(false);
+        return st;
+    }
     for (int32_t i = 0; i < steps; ++i) {
         const uint8_t *in = (i & 1) ? d_b : d_a;
         uint8_t *out = (i & 1) ? d_a : d_b;
@@ -490,6 +515,69 @@ sqz_status sqz_compact_run(const sqz_fractal *f, uint8_t *d_a, uint8_t *d_b, int
         if (st != SQZ_OK) return st;
     }
     return SQZ_OK;
+}
+
+static sqz_status check_block_buffers(const void *a, const void *b, uint64_t bytes)
+{
+    if (!a || !b) return set_error(SQZ_ERR_INVALID, "NULL buffer");
+    if (((uintptr_t)a | (uintptr_t)b) & 3) return set_error(SQZ_ERR_INVALID, "buffers must be 4-byte aligned");
+    if (overlap(a, b, bytes)) return set_error(SQZ_ERR_INVALID, "buffers overlap");
+    return SQZ_OK;
+}
+
+sqz_status sqz_lambda_omega_step(const sqz_fractal *f, int32_t block_level, const uint8_t *d_in, uint8_t *d_out,
+                                 void *stream)
+{
+    sqz_status st = check_handle(f);
+    if (st != SQZ_OK) return st;
+    if ((st = blocks_check(f->h, block_level, nullptr)) != SQZ_OK) return st;
+    const uint64_t n = (uint64_t)f->h.n;
+    if ((st = check_block_buffers(d_in, d_out, n * n)) != SQZ_OK) return st;
+    return launch_life_blocks(f->h, block_level, true, d_in, d_out, (hipStream_t)stream);
+}
+
+sqz_status sqz_microblock_bytes(const sqz_fractal *f, int32_t block_level, uint64_t *bytes)
+{
+    sqz_status st = check_handle(f);
+    if (st != SQZ_OK) return st;
+    if (!bytes) return set_error(SQZ_ERR_INVALID, "bytes is NULL");
+    if ((st = blocks_check(f->h, block_level, nullptr)) != SQZ_OK) return st;
+    *bytes = blocks_bytes(f->h, block_level);
+    return SQZ_OK;
+}
+
+sqz_status sqz_microblock_pack(const sqz_fractal *f, int32_t block_level, const uint8_t *d_compact, uint8_t *d_blocks,
+                               void *stream)
+{
+    sqz_status st = check_handle(f);
+    if (st != SQZ_OK) return st;
+    if ((st = blocks_check(f->h, block_level, nullptr)) != SQZ_OK) return st;
+    if (!d_compact || !d_blocks) return set_error(SQZ_ERR_INVALID, "NULL buffer");
+    if (ranges_overlap(d_compact, f->h.N, d_blocks, blocks_bytes(f->h, block_level)))
+        return set_error(SQZ_ERR_INVALID, "buffers overlap");
+    return launch_blocks_convert(f->h, block_level, true, d_compact, d_blocks, (hipStream_t)stream);
+}
+
+sqz_status sqz_microblock_unpack(const sqz_fractal *f, int32_t block_level, const uint8_t *d_blocks,
+                                 uint8_t *d_compact, void *stream)
+{
+    sqz_status st = check_handle(f);
+    if (st != SQZ_OK) return st;
+    if ((st = blocks_check(f->h, block_level, nullptr)) != SQZ_OK) return st;
+    if (!d_compact || !d_blocks) return set_error(SQZ_ERR_INVALID, "NULL buffer");
+    if (ranges_overlap(d_compact, f->h.N, d_blocks, blocks_bytes(f->h, block_level)))
+        return set_error(SQZ_ERR_INVALID, "buffers overlap");
+    return launch_blocks_convert(f->h, block_level, false, d_blocks, d_compact, (hipStream_t)stream);
+}
+
+sqz_status sqz_microblock_step(const sqz_fractal *f, int32_t block_level, const uint8_t *d_in, uint8_t *d_out,
+                               void *stream)
+{
+    sqz_status st = check_handle(f);
+    if (st != SQZ_OK) return st;
+    if ((st = blocks_check(f->h, block_level, nullptr)) != SQZ_OK) return st;
+    if ((st = check_block_buffers(d_in, d_out, blocks_bytes(f->h, block_level))) != SQZ_OK) return st;
+    return launch_life_blocks(f->h, block_level, false, d_in, d_out, (hipStream_t)stream);
 }
 
 sqz_status sqz_expanded_step(const sqz_fractal *f, const uint8_t *d_in, uint8_t *d_out, void *stream)

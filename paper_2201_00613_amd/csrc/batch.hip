@@ -214,22 +214,6 @@ static uint32_t kind_of(const FractalHost &F)
     return kBCell;
 }
 
-static TileArgs tile_args_from(const FractalHost &F)
-{
-    const TileConfig *T = F.tile;
-    TileArgs A;
-    A.ntiles = T->ntiles;
-    A.N = F.N;
-    A.tile = T->tile;
-    A.nblocks = T->nblocks;
-    A.nthalo = T->nthalo;
-    A.hstride = T->hstride;
-    A.halo_word = T->halo_word;
-    A.block_halo = T->d_block_halo;
-    A.tile_halo = T->d_tile_halo;
-    return A;
-}
-
 template <class Pat>
 static size_t tile_lds() { return (size_t)(TileLds<Pat>::IN_WORDS + TileLds<Pat>::WMAX + 1) * 4; }
 
@@ -297,7 +281,7 @@ sqz_status batch_create(const sqz_fractal *const *fr, int32_t count, BatchHost *
         I.cell_start = cstart;
         I.P = F.P;
         if (I.kind == kBTri || I.kind == kBTriPaper || I.kind == kBVicsek) {
-            I.tile = tile_args_from(F);
+            I.tile = tile_args(F);
             I.units = I.tile.ntiles;
             I.unit_cells = I.tile.tile;
             lds = std::max(lds, tile_lds_of(F));

@@ -202,6 +202,14 @@ sqz_status launch_lambda_mfma(const FractalHost &F, const uint64_t *idx, int64_t
 sqz_status launch_nu_mfma(const FractalHost &F, const int32_t *xy, int64_t count, uint64_t *idx, hipStream_t st);
 sqz_status launch_life_cell_mfma(const FractalHost &F, const uint8_t *in, uint8_t *out, hipStream_t st);
 
+// Block-level layouts: lambda(omega) on the expanded array, micro-block storage (blocks.hip)
+sqz_status blocks_check(const FractalHost &F, int m, int64_t *side);
+uint64_t blocks_bytes(const FractalHost &F, int m);
+sqz_status launch_life_blocks(const FractalHost &F, int m, bool expanded, const uint8_t *in, uint8_t *out,
+                              hipStream_t st);
+sqz_status launch_blocks_convert(const FractalHost &F, int m, bool pack, const uint8_t *src, uint8_t *dst,
+                                 hipStream_t st);
+
 // Expanded bounding-box baseline (bb.hip)
 sqz_status launch_life_bb(const FractalHost &F, const uint8_t *in, uint8_t *out, hipStream_t st);
 
@@ -237,5 +245,7 @@ unsigned batch_wg_per_cu(const BatchHost *H);
 uint64_t batch_total_cells(const BatchHost *H);
 const FractalHost &fractal_host_of(const sqz_fractal *f);
 sqz_status launch_life_tile(const FractalHost &F, const uint8_t *in, uint8_t *out, hipStream_t st);
+bool tile_two_step_ok(const FractalHost &F);  // two Life steps per launch available
+sqz_status launch_life_tile2(const FractalHost &F, const uint8_t *in, uint8_t *out, hipStream_t st);
 
 }  // namespace sqz

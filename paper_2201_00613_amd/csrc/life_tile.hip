@@ -22,6 +22,22 @@ __global__ void __launch_bounds__(kBlock) k_life_tile(TileArgs A, const uint8_t 
     }
 }
 
+template <class Pat>
+__global__ void __launch_bounds__(kBlock) k_life_tile2(TileArgs A, const uint8_t *__restrict__ in,
+                                                       uint8_t *__restrict__ out)
+{
+    using LDS = TileLds<Pat>;
+    __shared__ uint32_t s_a[LDS::IN_WORDS];
+    __shared__ uint32_t s_b[LDS::IN_WORDS];
+    __shared__ uint32_t s_c[LDS::WMAX + 1];
+    const uint32_t G = gridDim.x;
+    for (uint64_t round = 0; round * G < A.ntiles; ++round) {
+        const uint64_t t = round * G + xcd_remap(blockIdx.x, G);
+        if (t >= A.ntiles) break;  // uniform across the workgroup
+        tile_body2<Pat>(A, in, out, t, s_a, s_b, s_c);
+    }
+}
+
 // Tile-halo cells of every tile: global compact index of each slot's cell.
 __global__ void __launch_bounds__(kBlock) k_tile_halo(MapParams Pc, uint64_t ntiles, uint32_t nthalo,
                                                       uint64_t tile_cells, const int4 *__restrict__ slots,
@@ -96,12 +112,51 @@ sqz_status prepare(FractalHost &F)
         return set_error(SQZ_ERR_UNSUPPORTED, "tile halo of %zu cells exceeds %d", slots.size(), kMaxTileHalo);
     }
     T->nthalo = (uint32_t)slots.size();
+    // table entry codes: a bit position relative to the tile's first bit (< 2^20), or
+    const uint32_t kSlot = 1u << 20, kZero = 1u << 21, kRing2 = 1u << 22;  // slot, zero, second-ring slot
+
+    // second ring (two steps per launch): for each tile-halo cell and each of
+    // its eight neighbours, where the neighbour's state lives in LDS -- a tile
+    // bit (local compact index, shifted by the alignment o below), another
+    // tile-halo bit, a second-ring bit, or the zero word.
+    std::vector<Slot> ring2;
+    std::vector<uint32_t> h1((size_t)T->nthalo * 8, kZero);
+    for (uint32_t h = 0; h < T->nthalo; ++h) {
+        int d = 0;
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                if (!dx && !dy) continue;
+                const int64_t qx = slots[h].px + dx, qy = slots[h].py + dy;
+                uint32_t e = kZero;
+                if (qx >= 0 && qy >= 0 && qx < side && qy < side) {
+                    const int64_t j = host_nu(F, M, qx, qy);
+                    if (j >= 0) e = (uint32_t)j;
+                } else {
+                    const int tdx = qx < 0 ? -1 : (qx >= side ? 1 : 0), tdy = qy < 0 ? -1 : (qy >= side ? 1 : 0);
+                    const int64_t j = host_nu(F, M, qx - tdx * side, qy - tdy * side);
+                    if (j >= 0) {
+                        for (size_t s2 = 0; s2 < slots.size(); ++s2)
+                            if (slots[s2].px == qx && slots[s2].py == qy) e = kSlot + (uint32_t)s2;
+                        if (e == kZero) {
+                            size_t s2 = 0;
+                            while (s2 < ring2.size() && !(ring2[s2].px == qx && ring2[s2].py == qy)) ++s2;
+                            if (s2 == ring2.size()) ring2.push_back(Slot{tdx, tdy, j, qx, qy});
+                            e = kRing2 + (uint32_t)s2;
+                        }
+                    }
+                }
+                h1[(size_t)h * 8 + d++] = e;
+            }
+    }
+    T->nh2 = ring2.size() <= 32 && T->nthalo > 0 ? (uint32_t)ring2.size() : 0u;
+    const bool two_step = T->nh2 > 0;
+    if (!two_step) ring2.clear();
+    T->tstride = T->nthalo + T->nh2;
 
     // block halo table: for block b and halo slot h, the source cell's bit
     // position relative to the tile's first bit (< 2^20), a tile-halo slot, or
     // nothing.  Expanded below into LDS (word address << 16 | bit) entries for
     // each of the 32 possible alignments o of a tile's first bit.
-    const uint32_t kSlot = 1u << 20, kZero = 1u << 21;
     std::vector<uint32_t> bh((size_t)T->nblocks * T->hstride, kZero);
     const int64_t bside = cpow(Pat::S, M - J);
     for (uint32_t b = 0; b < T->nblocks; ++b) {
@@ -121,23 +176,31 @@ sqz_status prepare(FractalHost &F)
             bh[(size_t)b * T->hstride + h] = e;
         }
     }
+    // (LDS byte address of the word << 16 | bit) for alignment o
+    auto lds_entry = [&](uint32_t e, uint32_t o) {
+        uint32_t word, bit;
+        if (e & kZero) {
+            word = T->halo_word + 1;
+            bit = 0;
+        } else if (e & kRing2) {
+            word = T->halo_word + 2;
+            bit = e - kRing2;
+        } else if (e & kSlot) {
+            word = T->halo_word;
+            bit = e - kSlot;
+        } else {
+            word = (e + o) >> 5;
+            bit = (e + o) & 31;
+        }
+        return ((4 * word) << 16) | bit;
+    };
     std::vector<uint32_t> bho((size_t)32 * bh.size());
     for (uint32_t o = 0; o < 32; ++o)
-        for (size_t i = 0; i < bh.size(); ++i) {
-            const uint32_t e = bh[i];
-            uint32_t word, bit;
-            if (e & kZero) {
-                word = T->halo_word + 1;
-                bit = 0;
-            } else if (e & kSlot) {
-                word = T->halo_word;
-                bit = e - kSlot;
-            } else {
-                word = (e + o) >> 5;
-                bit = (e + o) & 31;
-            }
-            bho[o * bh.size() + i] = ((4 * word) << 16) | bit;
-        }
+        for (size_t i = 0; i < bh.size(); ++i) bho[o * bh.size() + i] = lds_entry(bh[i], o);
+    std::vector<uint32_t> h1o(two_step ? (size_t)32 * h1.size() : 1, 0);
+    if (two_step)
+        for (uint32_t o = 0; o < 32; ++o)
+            for (size_t i = 0; i < h1.size(); ++i) h1o[o * h1.size() + i] = lds_entry(h1[i], o);
 
     // coarse maps and per-tile halo indices
     sqz_status st = build_map_params(F, F.r - M, T->Pc, &T->d_coarse_tables);
@@ -148,18 +211,24 @@ sqz_status prepare(FractalHost &F)
     T->ntiles = T->Pc.N;
     T->d_block_halo = nullptr;
     T->d_tile_halo = nullptr;
+    T->d_h1src = nullptr;
     int4 *d_slots = nullptr;
-    std::vector<int4> hs(slots.size() ? slots.size() : 1);
+    std::vector<int4> hs(T->tstride ? T->tstride : 1);
     for (size_t s = 0; s < slots.size(); ++s) hs[s] = make_int4(slots[s].dx, slots[s].dy, (int)slots[s].idx, 0);
+    for (size_t s = 0; s < ring2.size(); ++s)
+        hs[slots.size() + s] = make_int4(ring2[s].dx, ring2[s].dy, (int)ring2[s].idx, 0);
     hipError_t e = hipMalloc(&T->d_block_halo, bho.size() * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMemcpy(T->d_block_halo, bho.data(), bho.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMalloc(&T->d_tile_halo, (size_t)T->ntiles * (T->nthalo ? T->nthalo : 1) * sizeof(uint64_t));
+    if (e == hipSuccess) e = hipMalloc(&T->d_h1src, h1o.size() * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMemcpy(T->d_h1src, h1o.data(), h1o.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMalloc(&T->d_tile_halo, (size_t)T->ntiles * (T->tstride ? T->tstride : 1) * sizeof(uint64_t));
     if (e == hipSuccess) e = hipMalloc(&d_slots, hs.size() * sizeof(int4));
     if (e == hipSuccess) e = hipMemcpy(d_slots, hs.data(), hs.size() * sizeof(int4), hipMemcpyHostToDevice);
-    if (e == hipSuccess && T->nthalo) {
+    if (e == hipSuccess && T->tstride) {
         uint64_t g = (T->ntiles + kBlock - 1) / kBlock;
         if (g > 16384) g = 16384;
-        hipLaunchKernelGGL(k_tile_halo, dim3((unsigned)g), dim3(kBlock), 0, 0, T->Pc, T->ntiles, T->nthalo,
+        hipLaunchKernelGGL(k_tile_halo, dim3((unsigned)g), dim3(kBlock), 0, 0, T->Pc, T->ntiles, T->tstride,
                            (uint64_t)T->tile, d_slots, T->d_tile_halo);
         e = hipGetLastError();
         if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -168,6 +237,7 @@ sqz_status prepare(FractalHost &F)
     if (e != hipSuccess) {
         if (T->d_block_halo) (void)hipFree(T->d_block_halo);
         if (T->d_tile_halo) (void)hipFree(T->d_tile_halo);
+        if (T->d_h1src) (void)hipFree(T->d_h1src);
         (void)hipFree(T->d_coarse_tables);
         delete T;
         return hip_error(e, "tile table setup");
@@ -177,25 +247,20 @@ sqz_status prepare(FractalHost &F)
 }
 
 template <class Pat>
-sqz_status launch(const FractalHost &F, const uint8_t *in, uint8_t *out, hipStream_t st)
+sqz_status launch(const FractalHost &F, const uint8_t *in, uint8_t *out, bool two, hipStream_t st)
 {
     const TileConfig *T = F.tile;
     if (((uintptr_t)in & 15) || ((uintptr_t)out & 15))
         return set_error(SQZ_ERR_INVALID, "tiled kernel needs 16-byte aligned buffers");
-    TileArgs A;
-    A.ntiles = T->ntiles;
-    A.N = F.N;
-    A.tile = T->tile;
-    A.nblocks = T->nblocks;
-    A.nthalo = T->nthalo;
-    A.hstride = T->hstride;
-    A.halo_word = T->halo_word;
-    A.block_halo = T->d_block_halo;
-    A.tile_halo = T->d_tile_halo;
+    if (two && !T->nh2) return set_error(SQZ_ERR_UNSUPPORTED, "no two-step tiled kernel for this fractal");
+    const TileArgs A = tile_args(F);
     const uint64_t grid = T->ntiles < (1ull << 20) ? T->ntiles : (1ull << 20);
-    hipLaunchKernelGGL(k_life_tile<Pat>, dim3((unsigned)grid), dim3(kBlock), 0, st, A, in, out);
+    if (two)
+        hipLaunchKernelGGL(k_life_tile2<Pat>, dim3((unsigned)grid), dim3(kBlock), 0, st, A, in, out);
+    else
+        hipLaunchKernelGGL(k_life_tile<Pat>, dim3((unsigned)grid), dim3(kBlock), 0, st, A, in, out);
     hipError_t e = hipGetLastError();
-    return e == hipSuccess ? SQZ_OK : hip_error(e, "compact_step (tile) launch");
+    return e == hipSuccess ? SQZ_OK : hip_error(e, two ? "compact_run (two-step tile) launch" : "compact_step (tile) launch");
 }
 
 enum { kNone = 0, kTriangle = 1, kTrianglePaper = 2, kVicsek = 3 };
@@ -225,6 +290,7 @@ void tile_release(FractalHost &F)
     if (!F.tile) return;
     (void)hipFree(F.tile->d_block_halo);
     (void)hipFree(F.tile->d_tile_halo);
+    (void)hipFree(F.tile->d_h1src);
     (void)hipFree(F.tile->d_coarse_tables);
     delete F.tile;
     F.tile = nullptr;
@@ -235,9 +301,21 @@ int32_t tile_level_of(const FractalHost &F) { return F.tile ? F.tile->M : 0; }
 sqz_status launch_life_tile(const FractalHost &F, const uint8_t *in, uint8_t *out, hipStream_t st)
 {
     switch (F.tile_kind) {
-    case kTriangle: return launch<PatTriangle>(F, in, out, st);
-    case kTrianglePaper: return launch<PatTrianglePaper>(F, in, out, st);
-    case kVicsek: return launch<PatVicsek>(F, in, out, st);
+    case kTriangle: return launch<PatTriangle>(F, in, out, false, st);
+    case kTrianglePaper: return launch<PatTrianglePaper>(F, in, out, false, st);
+    case kVicsek: return launch<PatVicsek>(F, in, out, false, st);
+    }
+    return set_error(SQZ_ERR_UNSUPPORTED, "no tiled kernel");
+}
+
+bool tile_two_step_ok(const FractalHost &F) { return F.tile && F.tile->nh2 > 0; }
+
+sqz_status launch_life_tile2(const FractalHost &F, const uint8_t *in, uint8_t *out, hipStream_t st)
+{
+    switch (F.tile_kind) {
+    case kTriangle: return launch<PatTriangle>(F, in, out, true, st);
+    case kTrianglePaper: return launch<PatTrianglePaper>(F, in, out, true, st);
+    case kVicsek: return launch<PatVicsek>(F, in, out, true, st);
     }
     return set_error(SQZ_ERR_UNSUPPORTED, "no tiled kernel");
 }

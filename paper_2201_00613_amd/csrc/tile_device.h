@@ -209,29 +209,55 @@ struct TileConfig {
     int M;                 // tile level
     uint32_t tile;         // K^M cells per tile
     uint32_t nblocks;      // K^(M-J)
-    uint32_t nthalo;       // tile halo slots
+    uint32_t nthalo;       // tile halo slots (cells of other tiles adjacent to the tile)
+    uint32_t nh2;          // second-ring slots (adjacent to a tile-halo cell only); 0: no two-step kernel
+    uint32_t tstride;      // per-tile entries of d_tile_halo: nthalo + nh2
     uint32_t hstride;      // u32 entries per block in the block-halo table (multiple of 4)
     uint32_t halo_word;    // LDS word index of the tile-halo bits (the next word is all zero)
     uint64_t ntiles;       // K^(r-M)
     uint32_t *d_block_halo;  // [32 alignments][nblocks][hstride]
-    uint64_t *d_tile_halo;
+    uint64_t *d_tile_halo;   // [ntiles][tstride] global indices of the halo and second-ring cells
+    uint32_t *d_h1src;       // [32 alignments][nthalo][8] LDS sources of each tile-halo cell's neighbours
     MapParams Pc;          // maps at the coarse level r-M
     void *d_coarse_tables;
 };
 
 struct TileArgs {
     uint64_t ntiles, N;
-    uint32_t tile, nblocks, nthalo, hstride, halo_word;
+    uint32_t tile, nblocks, nthalo, nh2, tstride, hstride, halo_word;
     const uint32_t *block_halo;
     const uint64_t *tile_halo;
+    const uint32_t *h1src;
 };
 
+inline TileArgs tile_args(const FractalHost &F)
+{
+    const TileConfig *T = F.tile;
+    TileArgs A;
+    A.ntiles = T->ntiles;
+    A.N = F.N;
+    A.tile = T->tile;
+    A.nblocks = T->nblocks;
+    A.nthalo = T->nthalo;
+    A.nh2 = T->nh2;
+    A.tstride = T->tstride;
+    A.hstride = T->hstride;
+    A.halo_word = T->halo_word;
+    A.block_halo = T->d_block_halo;
+    A.tile_halo = T->d_tile_halo;
+    A.h1src = T->d_h1src;
+    return A;
+}
+
+// LDS words of one tile's bits: o + tile bits, then (from HALO_WORD) the
+// tile-halo bits, a zero word, the second-ring bits and the tile-halo
+// membership bits (absent adjacent tiles).
 template <class Pat>
 struct TileLds {
     static constexpr int TMAX = cpow(Pat::K, Pat::MMAX);
     static constexpr int WMAX = (TMAX + 31 + 31) / 32;  // words covering o + tile bits
-    static constexpr int HALO_WORD = WMAX + 1;          // tile-halo bits, then one zero word
-    static constexpr int IN_WORDS = HALO_WORD + 2;
+    static constexpr int HALO_WORD = WMAX + 1;
+    static constexpr int IN_WORDS = HALO_WORD + 4;
 };
 
 // Bit 0 of eight bytes (two words) -> one byte of bits, via 4-byte dot products.
@@ -325,61 +351,20 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t G)
     return xcd < rem ? xcd * (q + 1) + pos : rem * (q + 1) + (xcd - rem) * q + pos;
 }
 
-// One tile (phases A to D).  s_in / s_out: TileLds<Pat>::IN_WORDS and WMAX + 1
-// words of LDS.  Called by every lane of the workgroup.
+// Phase C: one lane per level-J block.  Reads the tile's bits and halo words
+// from `src`, ORs the new states into `dst` (zeroed beforehand).
 template <class Pat>
-__device__ __forceinline__ void tile_body(const TileArgs &A, const uint8_t *__restrict__ in, uint8_t *__restrict__ out,
-                                          uint64_t t, uint32_t *s_in, uint32_t *s_out)
+__device__ __forceinline__ void tile_blocks(const TileArgs &A, uint32_t o, const uint32_t *bh_o, const uint32_t *src,
+                                            uint32_t *dst)
 {
     constexpr const BlockPlan &PL = PlanOf<Pat>::value;
     constexpr int NC = PL.nc;
     constexpr uint32_t CELLS = NC == 32 ? 0xFFFFFFFFu : ((1u << NC) - 1u);
     constexpr int NL = PL.nlayer;
     constexpr int NH = PL.nhalo;
-    const uint32_t tid = threadIdx.x;
-    const uint64_t S0 = t * A.tile;  // first byte of the tile
-    const uint64_t A0 = S0 & ~31ull;
-    const uint32_t o = (uint32_t)(S0 - A0);
-    const uint32_t W = (o + A.tile + 31) / 32;
-
-    const uint32_t *bh_o = A.block_halo + (size_t)o * A.nblocks * A.hstride;
-
-    // Phase B, first half: the global indices of the tile's halo cells are
-    // requested before the tile's own bytes so the two latencies overlap.
-    uint64_t gi = kHole64;
-    if (tid < A.nthalo) gi = A.tile_halo[t * A.nthalo + tid];
-
-    // Phase A: load and pack the tile (plus the bytes of its first and last
-    // 32-byte words that belong to the neighbouring tiles).
-    for (uint32_t w = tid; w < W; w += kBlock) {
-        const uint64_t g = A0 + 32ull * w;
-        uint32_t bits = 0;
-        if (g + 32 <= A.N) {
-            const uint4 a = load16(in + g);
-            const uint4 b = load16(in + g + 16);
-            bits = pack8(a.x, a.y) | pack8(a.z, a.w) << 8 | pack8(b.x, b.y) << 16 | pack8(b.z, b.w) << 24;
-        } else {
-            for (uint32_t i = 0; i < 32; ++i)
-                if (g + i < A.N) bits |= (uint32_t)(in[g + i] & 1u) << i;
-        }
-        s_in[w] = bits;
-        s_out[w] = 0;
-    }
-    // Phase B, second half: the halo cells themselves, gathered by ballot.
-    if (tid < 64) {
-        const uint32_t v = gi != kHole64 ? (in[gi] & 1u) : 0u;
-        const uint64_t m = __ballot(v);
-        if (tid == 0) {
-            s_in[A.halo_word] = (uint32_t)m;
-            s_in[A.halo_word + 1] = 0u;
-        }
-    }
-    __syncthreads();
-
-    // Phase C: one lane per level-J block.
-    for (uint32_t b = tid; b < A.nblocks; b += kBlock) {
+    for (uint32_t b = threadIdx.x; b < A.nblocks; b += kBlock) {
         const uint32_t pos = o + b * NC;
-        const uint32_t lo = s_in[pos >> 5], hi = s_in[(pos >> 5) + 1];
+        const uint32_t lo = src[pos >> 5], hi = src[(pos >> 5) + 1];
         const uint32_t x = __builtin_amdgcn_alignbit(hi, lo, pos) & CELLS;  // shift = pos mod 32
         uint32_t hb[NH > 0 ? NH : 1] = {};
         const uint32_t *he = bh_o + (size_t)b * A.hstride;
@@ -391,8 +376,7 @@ __device__ __forceinline__ void tile_body(const TileArgs &A, const uint8_t *__re
             for (int h = h0; h < NH && h < h0 + 4; ++h) {
                 // entry: LDS byte address of the word << 16 | bit within the word
                 const uint32_t e = qq[h - h0];
-                const uint32_t word = *reinterpret_cast<const uint32_t *>(
-                    reinterpret_cast<const char *>(s_in) + (e >> 16));
+                const uint32_t word = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(src) + (e >> 16));
                 hb[h] = __builtin_amdgcn_ubfe(word, e, 1);
             }
         }
@@ -403,17 +387,20 @@ __device__ __forceinline__ void tile_body(const TileArgs &A, const uint8_t *__re
         apply_halo<Pat, NL, (NH > 0 ? NH : 1)>(hb, L, std::make_index_sequence<PL.nhterm>{});
         const uint32_t res = life_rule<NL>(x, L) & CELLS;
         const uint64_t sh = (uint64_t)res << (pos & 31);
-        atomicOr(&s_out[pos >> 5], (uint32_t)sh);
-        atomicOr(&s_out[(pos >> 5) + 1], (uint32_t)(sh >> 32));
+        atomicOr(&dst[pos >> 5], (uint32_t)sh);
+        atomicOr(&dst[(pos >> 5) + 1], (uint32_t)(sh >> 32));
     }
-    __syncthreads();
+}
 
-    // Phase D: unpack and store whole words; the (at most two) edge words
-    // of the tile go out byte by byte, one byte per lane of wave 0.
-    const uint32_t last = W - 1;
+// Phase D: unpack the bits in `src` and store whole words; the (at most two)
+// edge words of the tile go out byte by byte, one byte per lane of wave 0.
+__device__ __forceinline__ void tile_store(const TileArgs &A, uint8_t *__restrict__ out, uint64_t A0, uint32_t o,
+                                           uint32_t W, const uint32_t *src)
+{
+    const uint32_t tid = threadIdx.x, last = W - 1;
     const bool first_partial = o != 0, last_partial = ((o + A.tile) & 31) != 0;
     for (uint32_t w = tid; w < W; w += kBlock) {
-        const uint32_t v = s_out[w];
+        const uint32_t v = src[w];
         const uint64_t g = A0 + 32ull * w;
         if (!((w == 0 && first_partial) || (w == last && last_partial))) {
             uint4 a, b;
@@ -432,9 +419,129 @@ __device__ __forceinline__ void tile_body(const TileArgs &A, const uint8_t *__re
     if (tid < 64) {
         const uint32_t w = tid < 32 ? 0u : last, i = tid & 31u, lp = 32 * w + i;
         const bool mine = tid < 32 ? first_partial : (last_partial && (last != 0 || !first_partial));
-        if (mine && lp >= o && lp < o + A.tile) out[A0 + lp] = (uint8_t)((s_out[w] >> i) & 1u);
+        if (mine && lp >= o && lp < o + A.tile) out[A0 + lp] = (uint8_t)((src[w] >> i) & 1u);
     }
+}
+
+// Phase A: load and pack the tile (plus the bytes of its first and last
+// 32-byte words that belong to the neighbouring tiles) into s_in.
+__device__ __forceinline__ void tile_pack(const TileArgs &A, const uint8_t *__restrict__ in, uint64_t A0, uint32_t W,
+                                          uint32_t *s_in)
+{
+    for (uint32_t w = threadIdx.x; w < W; w += kBlock) {
+        const uint64_t g = A0 + 32ull * w;
+        uint32_t bits = 0;
+        if (g + 32 <= A.N) {
+            const uint4 a = load16(in + g);
+            const uint4 b = load16(in + g + 16);
+            bits = pack8(a.x, a.y) | pack8(a.z, a.w) << 8 | pack8(b.x, b.y) << 16 | pack8(b.z, b.w) << 24;
+        } else {
+            for (uint32_t i = 0; i < 32; ++i)
+                if (g + i < A.N) bits |= (uint32_t)(in[g + i] & 1u) << i;
+        }
+        s_in[w] = bits;
+    }
+}
+
+// One tile, one step (phases A to D).  s_in / s_out: TileLds<Pat>::IN_WORDS
+// and WMAX + 1 words of LDS.  Called by every lane of the workgroup.
+template <class Pat>
+__device__ __forceinline__ void tile_body(const TileArgs &A, const uint8_t *__restrict__ in, uint8_t *__restrict__ out,
+                                          uint64_t t, uint32_t *s_in, uint32_t *s_out)
+{
+    const uint32_t tid = threadIdx.x;
+    const uint64_t S0 = t * A.tile;  // first byte of the tile
+    const uint64_t A0 = S0 & ~31ull;
+    const uint32_t o = (uint32_t)(S0 - A0);
+    const uint32_t W = (o + A.tile + 31) / 32;
+    const uint32_t *bh_o = A.block_halo + (size_t)o * A.nblocks * A.hstride;
+
+    // Phase B, first half: the global indices of the tile's halo cells are
+    // requested before the tile's own bytes so the two latencies overlap.
+    uint64_t gi = kHole64;
+    if (tid < A.nthalo) gi = A.tile_halo[t * A.tstride + tid];
+    tile_pack(A, in, A0, W, s_in);
+    for (uint32_t w = tid; w <= W; w += kBlock) s_out[w] = 0;
+    // Phase B, second half: the halo cells themselves, gathered by ballot.
+    if (tid < 64) {
+        const uint32_t v = gi != kHole64 ? (in[gi] & 1u) : 0u;
+        const uint64_t m = __ballot(v);
+        if (tid == 0) {
+            s_in[A.halo_word] = (uint32_t)m;
+            s_in[A.halo_word + 1] = 0u;
+        }
+    }
+    __syncthreads();
+    tile_blocks<Pat>(A, o, bh_o, s_in, s_out);
+    __syncthreads();
+    tile_store(A, out, A0, o, W, s_out);
     __syncthreads();  // LDS is reused by the next tile
+}
+
+// One tile, two steps (temporal blocking).  The tile-halo cells' states at
+// t+1 come from their own neighbours at t: tile cells, other tile-halo cells
+// and the second ring (cells adjacent to a tile-halo cell only), whose LDS
+// sources are the tile-invariant table h1src.  s_a, s_b: IN_WORDS words,
+// s_c: WMAX + 1 words.
+template <class Pat>
+__device__ __forceinline__ void tile_body2(const TileArgs &A, const uint8_t *__restrict__ in,
+                                           uint8_t *__restrict__ out, uint64_t t, uint32_t *s_a, uint32_t *s_b,
+                                           uint32_t *s_c)
+{
+    const uint32_t tid = threadIdx.x, HW = A.halo_word;
+    const uint64_t S0 = t * A.tile;
+    const uint64_t A0 = S0 & ~31ull;
+    const uint32_t o = (uint32_t)(S0 - A0);
+    const uint32_t W = (o + A.tile + 31) / 32;
+    const uint32_t *bh_o = A.block_halo + (size_t)o * A.nblocks * A.hstride;
+
+    // lanes 0..31: tile-halo slots, lanes 32..63: second-ring slots
+    uint64_t gi = kHole64;
+    if (tid < A.nthalo)
+        gi = A.tile_halo[t * A.tstride + tid];
+    else if (tid >= 32 && tid < 32 + A.nh2)
+        gi = A.tile_halo[t * A.tstride + A.nthalo + (tid - 32)];
+    tile_pack(A, in, A0, W, s_a);
+    for (uint32_t w = tid; w <= W; w += kBlock) {
+        s_b[w] = 0;
+        s_c[w] = 0;
+    }
+    if (tid < 64) {
+        const uint32_t v = gi != kHole64 ? (in[gi] & 1u) : 0u;
+        const uint64_t m = __ballot(v), ex = __ballot(gi != kHole64);
+        if (tid == 0) {
+            s_a[HW] = (uint32_t)m;
+            s_a[HW + 1] = 0u;
+            s_a[HW + 2] = (uint32_t)(m >> 32);
+            s_a[HW + 3] = (uint32_t)ex;
+            s_b[HW] = 0u;
+            s_b[HW + 1] = 0u;
+        }
+    }
+    __syncthreads();
+    tile_blocks<Pat>(A, o, bh_o, s_a, s_b);
+    {
+        // tile-halo cell h = tid / 8 at t+1; eight lanes read its eight neighbours
+        const uint32_t h = tid >> 3;
+        uint32_t bit = 0;
+        if (h < A.nthalo) {
+            const uint32_t e = A.h1src[((size_t)o * A.nthalo + h) * 8 + (tid & 7)];
+            bit = __builtin_amdgcn_ubfe(*reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(s_a) + (e >> 16)),
+                                        e, 1);
+        }
+        const uint64_t m = __ballot(bit);
+        if (h < A.nthalo && (tid & 7) == 0) {
+            const uint32_t cnt = __builtin_popcountll((m >> (tid & 56)) & 0xFFull);
+            const uint32_t self = (s_a[HW] >> h) & 1u, present = (s_a[HW + 3] >> h) & 1u;
+            const uint32_t nv = present & ((cnt == 3) | (self & (cnt == 2)));
+            if (nv) atomicOr(&s_b[HW], 1u << h);
+        }
+    }
+    __syncthreads();
+    tile_blocks<Pat>(A, o, bh_o, s_b, s_c);
+    __syncthreads();
+    tile_store(A, out, A0, o, W, s_c);
+    __syncthreads();
 }
 
 }  // namespace sqz

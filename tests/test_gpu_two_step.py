@@ -1,0 +1,57 @@
+"""GPU parity of the two-step tiled kernel (two Life steps per launch, used by
+sqz_compact_run): every step count, every tiled pattern, bit-exact against
+one-step launches and the oracle, with the result in the documented buffer."""
+import numpy as np
+import pytest
+
+from gpu_common import gpu_fractal, mismatch, oracle_fractal, to_np, torch_or_skip
+
+pytestmark = pytest.mark.gpu
+
+CASES = [("triangle", 3), ("triangle", 5), ("triangle", 8), ("triangle", 9), ("triangle", 11),
+         ("triangle_paper", 4), ("triangle_paper", 9), ("vicsek", 2), ("vicsek", 3), ("vicsek", 6),
+         ("vicsek", 8)]
+
+
+@pytest.mark.parametrize("name,r", CASES)
+def test_run_equals_single_steps_and_oracle(name, r):
+    torch = torch_or_skip()
+    F, O = gpu_fractal(name, r), oracle_fractal(name, r)
+    assert F.has_tile
+    assert F.run_steps_per_launch == 2  # tile-halo slots exist even for a single tile (all absent)
+    start = O.fill_compact(2201, 0.5)
+    nb = O.neighbour_table() if F.cells <= 3 ** 11 else None
+    for steps in range(0, 8):
+        a = F.fill_bernoulli(2201, 0.5)
+        b = torch.zeros_like(a)
+        res = F.compact_run(a, b, steps)
+        assert res is (a if steps % 2 == 0 else b)
+        x, y = F.fill_bernoulli(2201, 0.5), torch.empty_like(a)
+        for _ in range(steps):
+            F.compact_step(x, y, impl="tile")
+            x, y = y, x
+        assert torch.equal(res, x), (name, r, steps)
+        if nb is not None and steps in (2, 3, 6):
+            mismatch(to_np(res), O.life_steps(start, steps, nb), f"{name} r={r} {steps} steps")
+
+
+def test_all_alive_two_steps():
+    """All cells alive at t = 0: tile-halo cells change state in the first step, so the
+    second step depends on their recomputed states."""
+    torch = torch_or_skip()
+    F, O = gpu_fractal("triangle", 10), oracle_fractal("triangle", 10)
+    a = torch.ones(F.cells, dtype=torch.uint8, device="cuda")
+    res = F.compact_run(a, torch.empty_like(a), 2)
+    mismatch(to_np(res), O.life_steps(np.ones(F.cells, np.uint8), 2), "all alive, 2 steps")
+
+
+def test_r16_run_equals_single_steps():
+    torch = torch_or_skip()
+    F = gpu_fractal("triangle", 16)
+    a = F.fill_bernoulli(9, 0.5)
+    r1 = F.compact_run(a.clone(), torch.empty_like(a), 14)
+    x, y = a.clone(), torch.empty_like(a)
+    for _ in range(14):
+        F.compact_step(x, y, impl="tile")
+        x, y = y, x
+    assert torch.equal(r1, x)
