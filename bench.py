@@ -108,7 +108,7 @@ def profiled_traffic(workload: str):
     h = hashlib.sha256()
     for f in ("life_tile.hip", "tile_device.h", "common.h"):
         h.update(open(os.path.join(src, f), "rb").read())
-    path = os.path.join(ROOT, "profiles", "k_life_tile_triangle_r16.md")
+    path = os.path.join(ROOT, "profiles", "k_life_tile2_triangle_r16.md")
     if not os.path.exists(path):
         return None
     m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)

@@ -77,7 +77,8 @@ sqz_status prepare(FractalHost &F)
     constexpr const BlockPlan &PL = PlanOf<Pat>::value;
     constexpr int J = Pat::J;
     TileConfig *T = new TileConfig();
-    T->M = F.r < Pat::MMAX ? F.r : Pat::MMAX;
+    const int mtop = F.r >= Pat::MBIG ? Pat::MMAX : (Pat::MSMALL < Pat::MMAX ? Pat::MSMALL : Pat::MMAX);
+    T->M = F.r < mtop ? F.r : mtop;
     const int M = T->M;
     T->tile = (uint32_t)cpow(Pat::K, M);
     T->nblocks = (uint32_t)cpow(Pat::K, M - J);

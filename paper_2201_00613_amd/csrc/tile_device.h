@@ -37,8 +37,8 @@ namespace sqz {
 // Replica patterns with a tiled kernel.  Replica j is at (OX[j], OY[j]).
 // ---------------------------------------------------------------------------
 // Build-time knobs (defaults are the tuned values).
-#ifndef SQZ_TRI_TILE_LEVEL
-#define SQZ_TRI_TILE_LEVEL 8
+#ifndef SQZ_TRI_TILE_LEVEL  // triangle tile level for large fractals
+#define SQZ_TRI_TILE_LEVEL 9
 #endif
 #ifndef SQZ_NT_LOAD
 #define SQZ_NT_LOAD 0
@@ -47,18 +47,21 @@ namespace sqz {
 #define SQZ_NT_STORE 0
 #endif
 
+// Tile level M: MMAX for fractals of level >= MBIG, else MSMALL (more,
+// smaller tiles keep a smaller fractal's launch balanced; at level 20 the
+// larger triangle tile is faster).
 struct PatTriangle {  // Sierpinski triangle, member iff x & y == 0
-    static constexpr int S = 2, K = 3, J = 3, MMAX = SQZ_TRI_TILE_LEVEL;
+    static constexpr int S = 2, K = 3, J = 3, MMAX = SQZ_TRI_TILE_LEVEL, MSMALL = 8, MBIG = 20;
     static constexpr int OX[3] = {0, 1, 0};
     static constexpr int OY[3] = {0, 0, 1};
 };
 struct PatTrianglePaper {  // the paper's orientation: top, middle, right
-    static constexpr int S = 2, K = 3, J = 3, MMAX = SQZ_TRI_TILE_LEVEL;
+    static constexpr int S = 2, K = 3, J = 3, MMAX = SQZ_TRI_TILE_LEVEL, MSMALL = 8, MBIG = 20;
     static constexpr int OX[3] = {0, 0, 1};
     static constexpr int OY[3] = {0, 1, 1};
 };
 struct PatVicsek {  // Vicsek cross
-    static constexpr int S = 3, K = 5, J = 2, MMAX = 6;
+    static constexpr int S = 3, K = 5, J = 2, MMAX = 6, MSMALL = 6, MBIG = 0;
     static constexpr int OX[5] = {1, 0, 1, 2, 1};
     static constexpr int OY[5] = {0, 1, 1, 1, 2};
 };
