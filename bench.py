@@ -46,15 +46,14 @@ def time_steps(torch, step, steps: int, warmup: int):
 
 
 def run_launches(F, steps: int) -> int:
-    """Launches sqz_compact_run makes for `steps` steps: two steps per launch when the
-    two-step tiled kernel exists, with the launch count's parity equal to that of
-    `steps` (two one-step launches replace one two-step launch when needed)."""
-    if F.run_steps_per_launch != 2:
+    """Launches sqz_compact_run makes for `steps` steps: K = F.run_steps_per_launch
+    steps per launch plus one launch of the remainder, and one more launch when the
+    count's parity differs from that of `steps` (a launch is split in two)."""
+    K = F.run_steps_per_launch
+    if K < 2:
         return steps
-    n2, n1 = steps // 2, steps % 2
-    if (n2 + n1) % 2 != steps % 2:
-        n2, n1 = n2 - 1, n1 + 2
-    return n2 + n1
+    n = steps // K + (1 if steps % K else 0)
+    return n + (1 if n % 2 != steps % 2 else 0)
 
 
 def compact_run(torch, F, seed, p, steps, warmup, impl="auto"):

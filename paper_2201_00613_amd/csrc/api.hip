@@ -351,7 +351,7 @@ sqz_status sqz_fractal_info(const sqz_fractal *f, sqz_info *out)
     out->has_tile = f->h.tile_kind != 0;
     out->tile_level = tile_level_of(f->h);
     out->xtile_level = xtile_level_of(f->h);
-    out->run_steps_per_launch = tile_two_step_ok(f->h) ? 2 : 1;
+    out->run_steps_per_launch = tile_steps_per_launch(f->h) > 1 ? tile_steps_per_launch(f->h) : 1;
     return SQZ_OK;
 }
 
@@ -485,27 +485,25 @@ sqz_status sqz_compact_run(const sqz_fractal *f, uint8_t *d_a, uint8_t *d_b, int
     if (!d_a || !d_b) return set_error(SQZ_ERR_INVALID, "NULL buffer");
     if (overlap(d_a, d_b, f->h.N)) return set_error(SQZ_ERR_INVALID, "d_a and d_b overlap");
     const bool aligned = !(((uintptr_t)d_a | (uintptr_t)d_b) & 15);
-    if (f->h.tile_kind && aligned && tile_two_step_ok(f->h)) {
-        // Two steps per launch (temporal blocking).  Every launch swaps the
-        // buffers, so the launch count must have the parity of `steps` for the
-        // result to land where one-step launches would leave it: n2 two-step
-        // launches bracketed by n1 / 2 one-step launches at each end.
-        int32_t n2 = steps / 2, n1 = steps - 2 * n2;
-        if (((n2 + n1) & 1) != (steps & 1)) {
-            n2 -= 1;
-            n1 += 2;
-        }
+    const int K = f->h.tile_kind && aligned ? tile_steps_per_launch(f->h) : 0;
+    if (K >= 2) {
+        // Several steps per launch (temporal blocking): launches of K steps and
+        // one of the remainder.  Every launch swaps the buffers, so the launch
+        // count must have the parity of `steps` for the result to land where
+        // one-step launches would leave it; if it does not, the last launch of
+        // two or more steps is split into (n - 1) + 1.
+        std::vector<int> plan((size_t)(steps / K), K);
+        if (steps % K) plan.push_back(steps % K);
+        if ((plan.size() & 1) != (size_t)(steps & 1))
+            for (size_t i = plan.size(); i-- > 0;)
+                if (plan[i] >= 2) {
+                    plan[i] -= 1;
+                    plan.push_back(1);
+                    break;
+                }
         const hipStream_t s = (hipStream_t)stream;
-        int32_t launch = 0;
-        auto one = [&](bool two) {
-            const uint8_t *in = (launch & 1) ? d_b : d_a;
-            uint8_t *out = (launch & 1) ? d_a : d_b;
-            ++launch;
-            return two ? launch_life_tile2(f->h, in, out, s) : launch_life_tile(f->h, in, out, s);
-        };
-        for (int32_t i = 0; i < n1 / 2 && st == SQZ_OK; ++i) st = one(false);
-        for (int32_t i = 0; i < n2 && st == SQZ_OK; ++i) st = one(true);
-        for (int32_t i = n1 / 2; i < n1 && st == SQZ_OK; ++i) st = one(false);
+        for (size_t i = 0; i < plan.size() && st == SQZ_OK; ++i)
+            st = launch_life_tile_steps(f->h, (i & 1) ? d_b : d_a, (i & 1) ? d_a : d_b, plan[i], s);
         return st;
     }
     for (int32_t i = 0; i < steps; ++i) {

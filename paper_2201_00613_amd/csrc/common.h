@@ -245,7 +245,7 @@ unsigned batch_wg_per_cu(const BatchHost *H);
 uint64_t batch_total_cells(const BatchHost *H);
 const FractalHost &fractal_host_of(const sqz_fractal *f);
 sqz_status launch_life_tile(const FractalHost &F, const uint8_t *in, uint8_t *out, hipStream_t st);
-bool tile_two_step_ok(const FractalHost &F);  // two Life steps per launch available
-sqz_status launch_life_tile2(const FractalHost &F, const uint8_t *in, uint8_t *out, hipStream_t st);
+int tile_steps_per_launch(const FractalHost &F);  // most Life steps one tiled launch can take (0: no tiles)
+sqz_status launch_life_tile_steps(const FractalHost &F, const uint8_t *in, uint8_t *out, int steps, hipStream_t st);
 
 }  // namespace sqz

@@ -22,19 +22,19 @@ __global__ void __launch_bounds__(kBlock) k_life_tile(TileArgs A, const uint8_t 
     }
 }
 
-template <class Pat>
-__global__ void __launch_bounds__(kBlock) k_life_tile2(TileArgs A, const uint8_t *__restrict__ in,
+template <class Pat, int K>
+__global__ void __launch_bounds__(kBlock) k_life_tileK(TileArgs A, const uint8_t *__restrict__ in,
                                                        uint8_t *__restrict__ out)
 {
     using LDS = TileLds<Pat>;
-    __shared__ uint32_t s_a[LDS::IN_WORDS];
-    __shared__ uint32_t s_b[LDS::IN_WORDS];
-    __shared__ uint32_t s_c[LDS::WMAX + 1];
+    __shared__ uint32_t s_buf[3][LDS::IN_WORDS];
+    __shared__ uint32_t s_ex[kMaxSteps + 1];  // ring cells present (their tile exists)
+    uint32_t *const buf[3] = {s_buf[0], s_buf[1], s_buf[2]};
     const uint32_t G = gridDim.x;
     for (uint64_t round = 0; round * G < A.ntiles; ++round) {
         const uint64_t t = round * G + xcd_remap(blockIdx.x, G);
         if (t >= A.ntiles) break;  // uniform across the workgroup
-        tile_body2<Pat>(A, in, out, t, s_a, s_b, s_c);
+        tile_bodyK<Pat, K>(A, in, out, t, buf, s_ex);
     }
 }
 
@@ -114,45 +114,69 @@ sqz_status prepare(FractalHost &F)
     }
     T->nthalo = (uint32_t)slots.size();
     // table entry codes: a bit position relative to the tile's first bit (< 2^20), or
-    const uint32_t kSlot = 1u << 20, kZero = 1u << 21, kRing2 = 1u << 22;  // slot, zero, second-ring slot
+    const uint32_t kSlot = 1u << 20, kZero = 1u << 21, kRing = 1u << 22;  // ring-1 slot, zero, ring slot
 
-    // second ring (two steps per launch): for each tile-halo cell and each of
-    // its eight neighbours, where the neighbour's state lives in LDS -- a tile
-    // bit (local compact index, shifted by the alignment o below), another
-    // tile-halo bit, a second-ring bit, or the zero word.
-    std::vector<Slot> ring2;
-    std::vector<uint32_t> h1((size_t)T->nthalo * 8, kZero);
-    for (uint32_t h = 0; h < T->nthalo; ++h) {
-        int d = 0;
+    // rings 2..kMaxSteps (several steps per launch): breadth-first from ring 1
+    // over member cells outside the tile (ring d = graph distance d from the
+    // tile); each must fit one LDS word and all rings the 64 lanes of wave 0.
+    std::vector<Slot> ring = slots;  // rings in order, ring 1 first
+    std::vector<uint32_t> start = {0, (uint32_t)slots.size()};
+    auto find = [&](int64_t qx, int64_t qy) {
+        for (size_t i = 0; i < ring.size(); ++i)
+            if (ring[i].px == qx && ring[i].py == qy) return (int64_t)i;
+        return (int64_t)-1;
+    };
+    auto outside_member = [&](int64_t qx, int64_t qy, int &tdx, int &tdy) {
+        tdx = qx < 0 ? -1 : (qx >= side ? 1 : 0);
+        tdy = qy < 0 ? -1 : (qy >= side ? 1 : 0);
+        return host_nu(F, M, qx - tdx * side, qy - tdy * side);
+    };
+    uint32_t ksteps = 1;
+    for (int d = 2; d <= kMaxSteps; ++d) {
+        for (uint32_t c = start[d - 2]; c < start[d - 1]; ++c)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int64_t qx = ring[c].px + dx, qy = ring[c].py + dy;
+                    if (qx >= 0 && qy >= 0 && qx < side && qy < side) continue;
+                    int tdx, tdy;
+                    const int64_t j = outside_member(qx, qy, tdx, tdy);
+                    if (j >= 0 && find(qx, qy) < 0) ring.push_back(Slot{tdx, tdy, j, qx, qy});
+                }
+        start.push_back((uint32_t)ring.size());
+        if (T->nthalo == 0 || start[d] - start[d - 1] > 32 || start[d] > 64) break;
+        ksteps = (uint32_t)d;  // rings 1..d fit: d steps per launch
+    }
+    T->ksteps = ksteps;
+    for (int d = 0; d <= kMaxSteps; ++d) T->ring_start[d] = start[d <= (int)ksteps ? d : ksteps];
+    T->tstride = T->ring_start[ksteps];
+    T->nsrc = ksteps >= 2 ? T->ring_start[ksteps - 1] : 0;
+    ring.resize(T->tstride);
+    // LDS sources of the neighbours of every ring cell that is advanced
+    std::vector<uint32_t> rsrc((size_t)T->nsrc * 8, kZero);
+    for (uint32_t c = 0; c < T->nsrc; ++c) {
+        int n = 0;
         for (int dy = -1; dy <= 1; ++dy)
             for (int dx = -1; dx <= 1; ++dx) {
                 if (!dx && !dy) continue;
-                const int64_t qx = slots[h].px + dx, qy = slots[h].py + dy;
+                const int64_t qx = ring[c].px + dx, qy = ring[c].py + dy;
                 uint32_t e = kZero;
                 if (qx >= 0 && qy >= 0 && qx < side && qy < side) {
                     const int64_t j = host_nu(F, M, qx, qy);
                     if (j >= 0) e = (uint32_t)j;
                 } else {
-                    const int tdx = qx < 0 ? -1 : (qx >= side ? 1 : 0), tdy = qy < 0 ? -1 : (qy >= side ? 1 : 0);
-                    const int64_t j = host_nu(F, M, qx - tdx * side, qy - tdy * side);
-                    if (j >= 0) {
-                        for (size_t s2 = 0; s2 < slots.size(); ++s2)
-                            if (slots[s2].px == qx && slots[s2].py == qy) e = kSlot + (uint32_t)s2;
-                        if (e == kZero) {
-                            size_t s2 = 0;
-                            while (s2 < ring2.size() && !(ring2[s2].px == qx && ring2[s2].py == qy)) ++s2;
-                            if (s2 == ring2.size()) ring2.push_back(Slot{tdx, tdy, j, qx, qy});
-                            e = kRing2 + (uint32_t)s2;
+                    int tdx, tdy;
+                    if (outside_member(qx, qy, tdx, tdy) >= 0) {
+                        const int64_t i = find(qx, qy);  // always a loaded ring cell: ring d-1, d or d+1
+                        if (i >= 0 && i < (int64_t)T->tstride) {
+                            uint32_t d = 1;
+                            while ((uint32_t)i >= T->ring_start[d]) ++d;
+                            e = kRing + ((d << 5) | (uint32_t)(i - T->ring_start[d - 1]));
                         }
                     }
                 }
-                h1[(size_t)h * 8 + d++] = e;
+                rsrc[(size_t)c * 8 + n++] = e;
             }
     }
-    T->nh2 = ring2.size() <= 32 && T->nthalo > 0 ? (uint32_t)ring2.size() : 0u;
-    const bool two_step = T->nh2 > 0;
-    if (!two_step) ring2.clear();
-    T->tstride = T->nthalo + T->nh2;
 
     // block halo table: for block b and halo slot h, the source cell's bit
     // position relative to the tile's first bit (< 2^20), a tile-halo slot, or
@@ -183,9 +207,9 @@ sqz_status prepare(FractalHost &F)
         if (e & kZero) {
             word = T->halo_word + 1;
             bit = 0;
-        } else if (e & kRing2) {
-            word = T->halo_word + 2;
-            bit = e - kRing2;
+        } else if (e & kRing) {
+            word = ring_word(T->halo_word, (e - kRing) >> 5);
+            bit = (e - kRing) & 31;
         } else if (e & kSlot) {
             word = T->halo_word;
             bit = e - kSlot;
@@ -198,10 +222,9 @@ sqz_status prepare(FractalHost &F)
     std::vector<uint32_t> bho((size_t)32 * bh.size());
     for (uint32_t o = 0; o < 32; ++o)
         for (size_t i = 0; i < bh.size(); ++i) bho[o * bh.size() + i] = lds_entry(bh[i], o);
-    std::vector<uint32_t> h1o(two_step ? (size_t)32 * h1.size() : 1, 0);
-    if (two_step)
-        for (uint32_t o = 0; o < 32; ++o)
-            for (size_t i = 0; i < h1.size(); ++i) h1o[o * h1.size() + i] = lds_entry(h1[i], o);
+    std::vector<uint32_t> rso(rsrc.size() ? (size_t)32 * rsrc.size() : 1, 0);
+    for (uint32_t o = 0; o < 32; ++o)
+        for (size_t i = 0; i < rsrc.size(); ++i) rso[o * rsrc.size() + i] = lds_entry(rsrc[i], o);
 
     // coarse maps and per-tile halo indices
     sqz_status st = build_map_params(F, F.r - M, T->Pc, &T->d_coarse_tables);
@@ -212,16 +235,14 @@ sqz_status prepare(FractalHost &F)
     T->ntiles = T->Pc.N;
     T->d_block_halo = nullptr;
     T->d_tile_halo = nullptr;
-    T->d_h1src = nullptr;
+    T->d_ringsrc = nullptr;
     int4 *d_slots = nullptr;
     std::vector<int4> hs(T->tstride ? T->tstride : 1);
-    for (size_t s = 0; s < slots.size(); ++s) hs[s] = make_int4(slots[s].dx, slots[s].dy, (int)slots[s].idx, 0);
-    for (size_t s = 0; s < ring2.size(); ++s)
-        hs[slots.size() + s] = make_int4(ring2[s].dx, ring2[s].dy, (int)ring2[s].idx, 0);
+    for (size_t s = 0; s < T->tstride; ++s) hs[s] = make_int4(ring[s].dx, ring[s].dy, (int)ring[s].idx, 0);
     hipError_t e = hipMalloc(&T->d_block_halo, bho.size() * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMemcpy(T->d_block_halo, bho.data(), bho.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMalloc(&T->d_h1src, h1o.size() * sizeof(uint32_t));
-    if (e == hipSuccess) e = hipMemcpy(T->d_h1src, h1o.data(), h1o.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&T->d_ringsrc, rso.size() * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMemcpy(T->d_ringsrc, rso.data(), rso.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMalloc(&T->d_tile_halo, (size_t)T->ntiles * (T->tstride ? T->tstride : 1) * sizeof(uint64_t));
     if (e == hipSuccess) e = hipMalloc(&d_slots, hs.size() * sizeof(int4));
@@ -238,7 +259,7 @@ sqz_status prepare(FractalHost &F)
     if (e != hipSuccess) {
         if (T->d_block_halo) (void)hipFree(T->d_block_halo);
         if (T->d_tile_halo) (void)hipFree(T->d_tile_halo);
-        if (T->d_h1src) (void)hipFree(T->d_h1src);
+        if (T->d_ringsrc) (void)hipFree(T->d_ringsrc);
         (void)hipFree(T->d_coarse_tables);
         delete T;
         return hip_error(e, "tile table setup");
@@ -248,20 +269,24 @@ sqz_status prepare(FractalHost &F)
 }
 
 template <class Pat>
-sqz_status launch(const FractalHost &F, const uint8_t *in, uint8_t *out, bool two, hipStream_t st)
+sqz_status launch(const FractalHost &F, const uint8_t *in, uint8_t *out, int steps, hipStream_t st)
 {
     const TileConfig *T = F.tile;
     if (((uintptr_t)in & 15) || ((uintptr_t)out & 15))
         return set_error(SQZ_ERR_INVALID, "tiled kernel needs 16-byte aligned buffers");
-    if (two && !T->nh2) return set_error(SQZ_ERR_UNSUPPORTED, "no two-step tiled kernel for this fractal");
+    if (steps < 1 || steps > (int)T->ksteps)
+        return set_error(SQZ_ERR_UNSUPPORTED, "%d steps per launch exceed the %u this fractal's tiles allow", steps,
+                         T->ksteps);
     const TileArgs A = tile_args(F);
     const uint64_t grid = T->ntiles < (1ull << 20) ? T->ntiles : (1ull << 20);
-    if (two)
-        hipLaunchKernelGGL(k_life_tile2<Pat>, dim3((unsigned)grid), dim3(kBlock), 0, st, A, in, out);
-    else
-        hipLaunchKernelGGL(k_life_tile<Pat>, dim3((unsigned)grid), dim3(kBlock), 0, st, A, in, out);
+    switch (steps) {
+    case 1: hipLaunchKernelGGL(k_life_tile<Pat>, dim3((unsigned)grid), dim3(kBlock), 0, st, A, in, out); break;
+    case 2: hipLaunchKernelGGL((k_life_tileK<Pat, 2>), dim3((unsigned)grid), dim3(kBlock), 0, st, A, in, out); break;
+    case 3: hipLaunchKernelGGL((k_life_tileK<Pat, 3>), dim3((unsigned)grid), dim3(kBlock), 0, st, A, in, out); break;
+    default: hipLaunchKernelGGL((k_life_tileK<Pat, 4>), dim3((unsigned)grid), dim3(kBlock), 0, st, A, in, out); break;
+    }
     hipError_t e = hipGetLastError();
-    return e == hipSuccess ? SQZ_OK : hip_error(e, two ? "compact_run (two-step tile) launch" : "compact_step (tile) launch");
+    return e == hipSuccess ? SQZ_OK : hip_error(e, "compact step (tile) launch");
 }
 
 enum { kNone = 0, kTriangle = 1, kTrianglePaper = 2, kVicsek = 3 };
@@ -291,7 +316,7 @@ void tile_release(FractalHost &F)
     if (!F.tile) return;
     (void)hipFree(F.tile->d_block_halo);
     (void)hipFree(F.tile->d_tile_halo);
-    (void)hipFree(F.tile->d_h1src);
+    (void)hipFree(F.tile->d_ringsrc);
     (void)hipFree(F.tile->d_coarse_tables);
     delete F.tile;
     F.tile = nullptr;
@@ -301,22 +326,17 @@ int32_t tile_level_of(const FractalHost &F) { return F.tile ? F.tile->M : 0; }
 
 sqz_status launch_life_tile(const FractalHost &F, const uint8_t *in, uint8_t *out, hipStream_t st)
 {
-    switch (F.tile_kind) {
-    case kTriangle: return launch<PatTriangle>(F, in, out, false, st);
-    case kTrianglePaper: return launch<PatTrianglePaper>(F, in, out, false, st);
-    case kVicsek: return launch<PatVicsek>(F, in, out, false, st);
-    }
-    return set_error(SQZ_ERR_UNSUPPORTED, "no tiled kernel");
+    return launch_life_tile_steps(F, in, out, 1, st);
 }
 
-bool tile_two_step_ok(const FractalHost &F) { return F.tile && F.tile->nh2 > 0; }
+int tile_steps_per_launch(const FractalHost &F) { return F.tile ? (int)F.tile->ksteps : 0; }
 
-sqz_status launch_life_tile2(const FractalHost &F, const uint8_t *in, uint8_t *out, hipStream_t st)
+sqz_status launch_life_tile_steps(const FractalHost &F, const uint8_t *in, uint8_t *out, int steps, hipStream_t st)
 {
     switch (F.tile_kind) {
-    case kTriangle: return launch<PatTriangle>(F, in, out, true, st);
-    case kTrianglePaper: return launch<PatTrianglePaper>(F, in, out, true, st);
-    case kVicsek: return launch<PatVicsek>(F, in, out, true, st);
+    case kTriangle: return launch<PatTriangle>(F, in, out, steps, st);
+    case kTrianglePaper: return launch<PatTrianglePaper>(F, in, out, steps, st);
+    case kVicsek: return launch<PatVicsek>(F, in, out, steps, st);
     }
     return set_error(SQZ_ERR_UNSUPPORTED, "no tiled kernel");
 }

@@ -74,6 +74,7 @@ constexpr int cpow(int b, int e)
 }
 
 constexpr int kMaxHalo = 16;      // halo cells per block
+constexpr int kMaxSteps = 4;      // Life steps per launch of the multi-step tiled kernel
 constexpr int kMaxTileHalo = 32;  // halo cells per tile (one LDS word of bits)
 constexpr int kBlock = 256;
 
@@ -212,25 +213,28 @@ struct TileConfig {
     int M;                 // tile level
     uint32_t tile;         // K^M cells per tile
     uint32_t nblocks;      // K^(M-J)
-    uint32_t nthalo;       // tile halo slots (cells of other tiles adjacent to the tile)
-    uint32_t nh2;          // second-ring slots (adjacent to a tile-halo cell only); 0: no two-step kernel
-    uint32_t tstride;      // per-tile entries of d_tile_halo: nthalo + nh2
+    uint32_t nthalo;       // tile halo slots (ring 1: cells of other tiles adjacent to the tile)
+    uint32_t ksteps;       // Life steps one launch of the multi-step kernel can take (1: none)
+    uint32_t ring_start[kMaxSteps + 1];  // slots of ring d are [ring_start[d-1], ring_start[d])
+    uint32_t nsrc;         // ring cells whose next states are computed: ring_start[ksteps - 1]
+    uint32_t tstride;      // per-tile entries of d_tile_halo: ring_start[ksteps]
     uint32_t hstride;      // u32 entries per block in the block-halo table (multiple of 4)
-    uint32_t halo_word;    // LDS word index of the tile-halo bits (the next word is all zero)
+    uint32_t halo_word;    // LDS word index of the ring-1 bits (the next word is all zero)
     uint64_t ntiles;       // K^(r-M)
     uint32_t *d_block_halo;  // [32 alignments][nblocks][hstride]
-    uint64_t *d_tile_halo;   // [ntiles][tstride] global indices of the halo and second-ring cells
-    uint32_t *d_h1src;       // [32 alignments][nthalo][8] LDS sources of each tile-halo cell's neighbours
+    uint64_t *d_tile_halo;   // [ntiles][tstride] global indices of the ring cells
+    uint32_t *d_ringsrc;     // [32 alignments][nsrc][8] LDS sources of each ring cell's neighbours
     MapParams Pc;          // maps at the coarse level r-M
     void *d_coarse_tables;
 };
 
 struct TileArgs {
     uint64_t ntiles, N;
-    uint32_t tile, nblocks, nthalo, nh2, tstride, hstride, halo_word;
+    uint32_t tile, nblocks, nthalo, tstride, nsrc, hstride, halo_word;
+    uint32_t ring_start[kMaxSteps + 1];
     const uint32_t *block_halo;
     const uint64_t *tile_halo;
-    const uint32_t *h1src;
+    const uint32_t *ringsrc;
 };
 
 inline TileArgs tile_args(const FractalHost &F)
@@ -242,26 +246,31 @@ inline TileArgs tile_args(const FractalHost &F)
     A.tile = T->tile;
     A.nblocks = T->nblocks;
     A.nthalo = T->nthalo;
-    A.nh2 = T->nh2;
     A.tstride = T->tstride;
+    A.nsrc = T->nsrc;
+    for (int d = 0; d <= kMaxSteps; ++d) A.ring_start[d] = T->ring_start[d];
     A.hstride = T->hstride;
     A.halo_word = T->halo_word;
     A.block_halo = T->d_block_halo;
     A.tile_halo = T->d_tile_halo;
-    A.h1src = T->d_h1src;
+    A.ringsrc = T->d_ringsrc;
     return A;
 }
 
-// LDS words of one tile's bits: o + tile bits, then (from HALO_WORD) the
-// tile-halo bits, a zero word, the second-ring bits and the tile-halo
-// membership bits (absent adjacent tiles).
+// LDS words of one tile's state: o + tile bits, then from HALO_WORD the
+// ring-1 bits, a zero word, and the bits of rings 2..kMaxSteps (ring d at
+// HALO_WORD + d).  Ring d holds the cells of other tiles at graph distance d
+// from the tile (each neighbour of a ring-d cell is in ring d-1, d or d+1,
+// or in the tile for d = 1).
 template <class Pat>
 struct TileLds {
     static constexpr int TMAX = cpow(Pat::K, Pat::MMAX);
     static constexpr int WMAX = (TMAX + 31 + 31) / 32;  // words covering o + tile bits
     static constexpr int HALO_WORD = WMAX + 1;
-    static constexpr int IN_WORDS = HALO_WORD + 4;
+    static constexpr int IN_WORDS = HALO_WORD + kMaxSteps + 1;
 };
+
+__host__ __device__ constexpr uint32_t ring_word(uint32_t hw, uint32_t d) { return hw + (d == 1 ? 0u : d); }
 
 // Bit 0 of eight bytes (two words) -> one byte of bits, via 4-byte dot products.
 __device__ __forceinline__ uint32_t pack8(uint32_t d0, uint32_t d1)
@@ -481,15 +490,16 @@ __device__ __forceinline__ void tile_body(const TileArgs &A, const uint8_t *__re
     __syncthreads();  // LDS is reused by the next tile
 }
 
-// One tile, two steps (temporal blocking).  The tile-halo cells' states at
-// t+1 come from their own neighbours at t: tile cells, other tile-halo cells
-// and the second ring (cells adjacent to a tile-halo cell only), whose LDS
-// sources are the tile-invariant table h1src.  s_a, s_b: IN_WORDS words,
-// s_c: WMAX + 1 words.
-template <class Pat>
-__device__ __forceinline__ void tile_body2(const TileArgs &A, const uint8_t *__restrict__ in,
-                                           uint8_t *__restrict__ out, uint64_t t, uint32_t *s_a, uint32_t *s_b,
-                                           uint32_t *s_c)
+// One tile, K steps (temporal blocking).  The states of the ring cells are
+// loaded with the tile; in round j (computing t+j) the tile's blocks and the
+// cells of rings 1..K-j are advanced together, each ring cell by eight lanes
+// that read its neighbours at t+j-1 (tile bits or ring bits, through the
+// tile-invariant source table), a ballot and a popcount.  Three LDS buffers
+// rotate: round j reads buf[(j-1)%3], writes buf[j%3] and clears buf[(j+1)%3].
+template <class Pat, int K>
+__device__ __forceinline__ void tile_bodyK(const TileArgs &A, const uint8_t *__restrict__ in,
+                                           uint8_t *__restrict__ out, uint64_t t, uint32_t *const buf[3],
+                                           uint32_t *s_ex)
 {
     const uint32_t tid = threadIdx.x, HW = A.halo_word;
     const uint64_t S0 = t * A.tile;
@@ -498,52 +508,59 @@ __device__ __forceinline__ void tile_body2(const TileArgs &A, const uint8_t *__r
     const uint32_t W = (o + A.tile + 31) / 32;
     const uint32_t *bh_o = A.block_halo + (size_t)o * A.nblocks * A.hstride;
 
-    // lanes 0..31: tile-halo slots, lanes 32..63: second-ring slots
+    // ring slots (at most 64: wave 0)
     uint64_t gi = kHole64;
-    if (tid < A.nthalo)
-        gi = A.tile_halo[t * A.tstride + tid];
-    else if (tid >= 32 && tid < 32 + A.nh2)
-        gi = A.tile_halo[t * A.tstride + A.nthalo + (tid - 32)];
-    tile_pack(A, in, A0, W, s_a);
-    for (uint32_t w = tid; w <= W; w += kBlock) {
-        s_b[w] = 0;
-        s_c[w] = 0;
-    }
+    if (tid < A.tstride) gi = A.tile_halo[t * A.tstride + tid];
+    tile_pack(A, in, A0, W, buf[0]);
+    for (uint32_t w = tid; w <= W; w += kBlock) buf[1][w] = 0;
+    if (tid <= K) buf[1][HW + tid] = 0;
     if (tid < 64) {
         const uint32_t v = gi != kHole64 ? (in[gi] & 1u) : 0u;
-        const uint64_t m = __ballot(v), ex = __ballot(gi != kHole64);
+        const uint64_t m = __ballot(v), x = __ballot(gi != kHole64);
         if (tid == 0) {
-            s_a[HW] = (uint32_t)m;
-            s_a[HW + 1] = 0u;
-            s_a[HW + 2] = (uint32_t)(m >> 32);
-            s_a[HW + 3] = (uint32_t)ex;
-            s_b[HW] = 0u;
-            s_b[HW + 1] = 0u;
+            buf[0][HW + 1] = 0u;
+#pragma unroll
+            for (int d = 1; d <= K; ++d) {
+                const uint32_t n = A.ring_start[d] - A.ring_start[d - 1];
+                const uint64_t mask = n >= 32 ? 0xFFFFFFFFull : ((1ull << n) - 1);
+                buf[0][ring_word(HW, d)] = (uint32_t)((m >> A.ring_start[d - 1]) & mask);
+                s_ex[d] = (uint32_t)((x >> A.ring_start[d - 1]) & mask);
+            }
         }
     }
     __syncthreads();
-    tile_blocks<Pat>(A, o, bh_o, s_a, s_b);
-    {
-        // tile-halo cell h = tid / 8 at t+1; eight lanes read its eight neighbours
-        const uint32_t h = tid >> 3;
-        uint32_t bit = 0;
-        if (h < A.nthalo) {
-            const uint32_t e = A.h1src[((size_t)o * A.nthalo + h) * 8 + (tid & 7)];
-            bit = __builtin_amdgcn_ubfe(*reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(s_a) + (e >> 16)),
-                                        e, 1);
+#pragma unroll
+    for (int j = 1; j <= K; ++j) {
+        const uint32_t *src = buf[(j - 1) % 3];
+        uint32_t *dst = buf[j % 3];
+        tile_blocks<Pat>(A, o, bh_o, src, dst);
+        if (j < K) {
+            uint32_t *clr = buf[(j + 1) % 3];
+            for (uint32_t w = tid; w <= W; w += kBlock) clr[w] = 0;
+            if (tid <= K) clr[HW + tid] = 0;
+            const uint32_t ncell = A.ring_start[K - j];
+            for (uint32_t c0 = 0; c0 < ncell; c0 += kBlock / 8) {
+                const uint32_t c = c0 + (tid >> 3);
+                uint32_t bit = 0;
+                if (c < ncell) {
+                    const uint32_t e = A.ringsrc[((size_t)o * A.nsrc + c) * 8 + (tid & 7)];
+                    bit = __builtin_amdgcn_ubfe(
+                        *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(src) + (e >> 16)), e, 1);
+                }
+                const uint64_t m = __ballot(bit);
+                if (c < ncell && (tid & 7) == 0) {
+                    uint32_t d = 1;
+                    while (c >= A.ring_start[d]) ++d;
+                    const uint32_t i = c - A.ring_start[d - 1];
+                    const uint32_t cnt = __builtin_popcountll((m >> (tid & 56)) & 0xFFull);
+                    const uint32_t self = (src[ring_word(HW, d)] >> i) & 1u, present = (s_ex[d] >> i) & 1u;
+                    if (present & ((cnt == 3) | (self & (cnt == 2)))) atomicOr(&dst[ring_word(HW, d)], 1u << i);
+                }
+            }
         }
-        const uint64_t m = __ballot(bit);
-        if (h < A.nthalo && (tid & 7) == 0) {
-            const uint32_t cnt = __builtin_popcountll((m >> (tid & 56)) & 0xFFull);
-            const uint32_t self = (s_a[HW] >> h) & 1u, present = (s_a[HW + 3] >> h) & 1u;
-            const uint32_t nv = present & ((cnt == 3) | (self & (cnt == 2)));
-            if (nv) atomicOr(&s_b[HW], 1u << h);
-        }
+        __syncthreads();
     }
-    __syncthreads();
-    tile_blocks<Pat>(A, o, bh_o, s_b, s_c);
-    __syncthreads();
-    tile_store(A, out, A0, o, W, s_c);
+    tile_store(A, out, A0, o, W, buf[K % 3]);
     __syncthreads();
 }
 

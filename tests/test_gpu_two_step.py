@@ -1,6 +1,7 @@
-"""GPU parity of the two-step tiled kernel (two Life steps per launch, used by
-sqz_compact_run): every step count, every tiled pattern, bit-exact against
-one-step launches and the oracle, with the result in the documented buffer."""
+"""GPU parity of the multi-step tiled kernels (up to four Life steps per launch,
+used by sqz_compact_run): every step count, every tiled pattern, bit-exact
+against one-step launches and the oracle, with the result in the documented
+buffer."""
 import numpy as np
 import pytest
 
@@ -18,10 +19,10 @@ def test_run_equals_single_steps_and_oracle(name, r):
     torch = torch_or_skip()
     F, O = gpu_fractal(name, r), oracle_fractal(name, r)
     assert F.has_tile
-    assert F.run_steps_per_launch == 2  # tile-halo slots exist even for a single tile (all absent)
+    assert F.run_steps_per_launch == 4  # ring slots exist even for a single tile (all absent)
     start = O.fill_compact(2201, 0.5)
     nb = O.neighbour_table() if F.cells <= 3 ** 11 else None
-    for steps in range(0, 8):
+    for steps in range(0, 13):
         a = F.fill_bernoulli(2201, 0.5)
         b = torch.zeros_like(a)
         res = F.compact_run(a, b, steps)
@@ -31,18 +32,19 @@ def test_run_equals_single_steps_and_oracle(name, r):
             F.compact_step(x, y, impl="tile")
             x, y = y, x
         assert torch.equal(res, x), (name, r, steps)
-        if nb is not None and steps in (2, 3, 6):
+        if nb is not None and steps in (2, 3, 4, 7, 12):
             mismatch(to_np(res), O.life_steps(start, steps, nb), f"{name} r={r} {steps} steps")
 
 
-def test_all_alive_two_steps():
-    """All cells alive at t = 0: tile-halo cells change state in the first step, so the
-    second step depends on their recomputed states."""
+@pytest.mark.parametrize("steps", [2, 3, 4, 8])
+def test_all_alive_multi_step(steps):
+    """All cells alive at t = 0: ring cells change state in the first step, so later
+    steps depend on their recomputed states."""
     torch = torch_or_skip()
     F, O = gpu_fractal("triangle", 10), oracle_fractal("triangle", 10)
     a = torch.ones(F.cells, dtype=torch.uint8, device="cuda")
-    res = F.compact_run(a, torch.empty_like(a), 2)
-    mismatch(to_np(res), O.life_steps(np.ones(F.cells, np.uint8), 2), "all alive, 2 steps")
+    res = F.compact_run(a, torch.empty_like(a), steps)
+    mismatch(to_np(res), O.life_steps(np.ones(F.cells, np.uint8), steps), f"all alive, {steps} steps")
 
 
 def test_r16_run_equals_single_steps():
