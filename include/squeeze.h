@@ -114,6 +114,12 @@ typedef struct sqz_diffusion {
     float coef;             /* a = dt * alpha; the update is stable for coef <= 1/8 */
     sqz_impl impl;          /* AUTO (= XTILE when available) / CELL / XTILE */
     uint64_t seed;
+    int32_t steps_per_launch; /* sqz_diffuse_run with expanded tiles: 0 or 1 = one step per
+                                 launch (the default; the update is LDS-bound, so more steps
+                                 per launch are slower), 2..3 = that many steps per launch with
+                                 multi-step tiles (same results bit for bit); larger values
+                                 than the fractal's tiles allow: SQZ_ERR_UNSUPPORTED */
+    int32_t reserved;
 } sqz_diffusion;
 
 typedef struct sqz_fractal sqz_fractal;

@@ -221,8 +221,8 @@ class Fractal:
         return dst
 
     # -- diffusion ------------------------------------------------------------
-    def _diffusion(self, dtype, coef, rounding, impl, seed):
-        return Diffusion(DTYPES[dtype], ROUNDINGS[rounding], coef, IMPLS[impl], seed)
+    def _diffusion(self, dtype, coef, rounding, impl, seed, steps_per_launch=0):
+        return Diffusion(DTYPES[dtype], ROUNDINGS[rounding], coef, IMPLS[impl], seed, steps_per_launch, 0)
 
     def _field_dtype(self, dtype):
         torch = _torch()
@@ -240,13 +240,14 @@ class Fractal:
         return dst
 
     def diffuse_run(self, a, b, steps: int, coef: float, dtype: str = "f32", first_step: int = 0,
-                    rounding: str = "nearest", impl: str = "auto", seed: int = 0):
-        """steps diffusion steps ping-ponging a -> b -> ...; returns the tensor holding the result."""
+                    rounding: str = "nearest", impl: str = "auto", seed: int = 0, steps_per_launch: int = 0):
+        """steps diffusion steps ping-ponging a -> b -> ...; returns the tensor holding the result.
+        steps_per_launch 2..3 selects multi-step expanded tiles (same results)."""
         torch, dev, st = self._ctx()
         td = self._field_dtype(dtype)
         self._need(a, td, self.cells, "a")
         self._need(b, td, self.cells, "b")
-        d = self._diffusion(dtype, coef, rounding, impl, seed)
+        d = self._diffusion(dtype, coef, rounding, impl, seed, steps_per_launch)
         with dev:
             check(lib().sqz_diffuse_run(self._h, ctypes.byref(d), first_step, steps, _ptr(a), _ptr(b), st))
         return a if steps % 2 == 0 else b

@@ -36,7 +36,8 @@ class Info(ctypes.Structure):
 
 class Diffusion(ctypes.Structure):
     _fields_ = [("dtype", ctypes.c_int), ("rounding", ctypes.c_int), ("coef", ctypes.c_float),
-                ("impl", ctypes.c_int), ("seed", ctypes.c_uint64)]
+                ("impl", ctypes.c_int), ("seed", ctypes.c_uint64), ("steps_per_launch", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 _lib = None

@@ -351,7 +351,10 @@ sqz_status sqz_fractal_info(const sqz_fractal *f, sqz_info *out)
     out->has_tile = f->h.tile_kind != 0;
     out->tile_level = tile_level_of(f->h);
     out->xtile_level = xtile_level_of(f->h);
-    out->run_steps_per_launch = tile_steps_per_launch(f->h) > 1 ? tile_steps_per_launch(f->h) : 1;
+    {
+        const int kt = tile_steps_per_launch(f->h), kx = xtile_steps_per_launch(f->h);
+        out->run_steps_per_launch = f->h.tile_kind ? (kt > 1 ? kt : 1) : (kx > 1 ? kx : 1);
+    }
     return SQZ_OK;
 }
 
@@ -477,6 +480,25 @@ sqz_status sqz_compact_step(const sqz_fractal *f, const uint8_t *d_in, uint8_t *
     return sqz_compact_step_impl(f, SQZ_IMPL_AUTO, d_in, d_out, stream);
 }
 
+// Launch sizes for `steps` steps with at most K per launch (temporal
+// blocking): launches of K steps and one of the remainder.  Every launch swaps
+// the two buffers, so the launch count must have the parity of `steps` for the
+// result to land where one-step launches would leave it; if it does not, the
+// last launch of two or more steps is split into (n - 1) + 1.
+static std::vector<int> plan_launches(int32_t steps, int K)
+{
+    std::vector<int> plan((size_t)(steps / K), K);
+    if (steps % K) plan.push_back(steps % K);
+    if ((plan.size() & 1) != (size_t)(steps & 1))
+        for (size_t i = plan.size(); i-- > 0;)
+            if (plan[i] >= 2) {
+                plan[i] -= 1;
+                plan.push_back(1);
+                break;
+            }
+    return plan;
+}
+
 sqz_status sqz_compact_run(const sqz_fractal *f, uint8_t *d_a, uint8_t *d_b, int32_t steps, void *stream)
 {
     sqz_status st = check_handle(f);
@@ -485,25 +507,17 @@ sqz_status sqz_compact_run(const sqz_fractal *f, uint8_t *d_a, uint8_t *d_b, int
     if (!d_a || !d_b) return set_error(SQZ_ERR_INVALID, "NULL buffer");
     if (overlap(d_a, d_b, f->h.N)) return set_error(SQZ_ERR_INVALID, "d_a and d_b overlap");
     const bool aligned = !(((uintptr_t)d_a | (uintptr_t)d_b) & 15);
-    const int K = f->h.tile_kind && aligned ? tile_steps_per_launch(f->h) : 0;
+    const bool tiled = f->h.tile_kind && aligned;
+    const int K = tiled ? tile_steps_per_launch(f->h) : xtile_steps_per_launch(f->h);
     if (K >= 2) {
-        // Several steps per launch (temporal blocking): launches of K steps and
-        // one of the remainder.  Every launch swaps the buffers, so the launch
-        // count must have the parity of `steps` for the result to land where
-        // one-step launches would leave it; if it does not, the last launch of
-        // two or more steps is split into (n - 1) + 1.
-        std::vector<int> plan((size_t)(steps / K), K);
-        if (steps % K) plan.push_back(steps % K);
-        if ((plan.size() & 1) != (size_t)(steps & 1))
-            for (size_t i = plan.size(); i-- > 0;)
-                if (plan[i] >= 2) {
-                    plan[i] -= 1;
-                    plan.push_back(1);
-                    break;
-                }
+        const std::vector<int> plan = plan_launches(steps, K);
         const hipStream_t s = (hipStream_t)stream;
-        for (size_t i = 0; i < plan.size() && st == SQZ_OK; ++i)
-            st = launch_life_tile_steps(f->h, (i & 1) ? d_b : d_a, (i & 1) ? d_a : d_b, plan[i], s);
+        for (size_t i = 0; i < plan.size() && st == SQZ_OK; ++i) {
+            const uint8_t *in = (i & 1) ? d_b : d_a;
+            uint8_t *out = (i & 1) ? d_a : d_b;
+            st = tiled ? launch_life_tile_steps(f->h, in, out, plan[i], s)
+                       : launch_life_xtile_steps(f->h, in, out, plan[i], s);
+        }
         return st;
     }
     for (int32_t i = 0; i < steps; ++i) {
@@ -603,6 +617,10 @@ static sqz_status check_diffusion(const sqz_fractal *f, const sqz_diffusion *d)
     if (d->impl != SQZ_IMPL_AUTO && d->impl != SQZ_IMPL_CELL && d->impl != SQZ_IMPL_XTILE)
         return set_error(SQZ_ERR_INVALID, "diffusion implementation %d is not AUTO, CELL or XTILE", (int)d->impl);
     if (d->impl == SQZ_IMPL_XTILE && !f->h.xtile) return set_error(SQZ_ERR_UNSUPPORTED, "no expanded tile fits this fractal");
+    if (d->steps_per_launch < 0) return set_error(SQZ_ERR_INVALID, "steps_per_launch < 0");
+    if (d->steps_per_launch > 1 && (d->impl == SQZ_IMPL_CELL || d->steps_per_launch > xtile_steps_per_launch(f->h)))
+        return set_error(SQZ_ERR_UNSUPPORTED, "%d diffusion steps per launch need multi-step expanded tiles (%d here)",
+                         d->steps_per_launch, d->impl == SQZ_IMPL_CELL ? 1 : xtile_steps_per_launch(f->h));
     return SQZ_OK;
 }
 
@@ -627,6 +645,17 @@ sqz_status sqz_diffuse_run(const sqz_fractal *f, const sqz_diffusion *d, uint64_
     if (steps < 0) return set_error(SQZ_ERR_INVALID, "steps < 0");
     if (!d_a || !d_b) return set_error(SQZ_ERR_INVALID, "NULL buffer");
     if (overlap(d_a, d_b, f->h.N * dtype_size(d->dtype))) return set_error(SQZ_ERR_INVALID, "d_a and d_b overlap");
+    const int K = d->steps_per_launch;
+    if (K >= 2) {
+        const std::vector<int> plan = plan_launches(steps, K);
+        uint64_t done = 0;
+        for (size_t i = 0; i < plan.size() && st == SQZ_OK; ++i) {
+            st = launch_diffuse_xtile_steps(f->h, d->dtype, d->coef, d->rounding, d->seed, first_step + done,
+                                            (i & 1) ? d_b : d_a, (i & 1) ? d_a : d_b, plan[i], (hipStream_t)stream);
+            done += (uint64_t)plan[i];
+        }
+        return st;
+    }
     for (int32_t i = 0; i < steps; ++i) {
         st = launch_diffuse(f->h, d->dtype, d->coef, d->rounding, d->seed, first_step + (uint64_t)i, (i & 1) ? d_b : d_a,
                             (i & 1) ? d_a : d_b, d->impl != SQZ_IMPL_CELL, (hipStream_t)stream);

@@ -223,6 +223,10 @@ int32_t tile_level_of(const FractalHost &F);
 sqz_status xtile_prepare(FractalHost &F);
 void xtile_release(FractalHost &F);
 int32_t xtile_level_of(const FractalHost &F);
+int xtile_steps_per_launch(const FractalHost &F);  // most steps one expanded-tile launch can take (0: none)
+sqz_status launch_life_xtile_steps(const FractalHost &F, const uint8_t *in, uint8_t *out, int steps, hipStream_t st);
+sqz_status launch_diffuse_xtile_steps(const FractalHost &F, int dtype, float coef, int rounding, uint64_t seed,
+                                      uint64_t step, const void *in, void *out, int steps, hipStream_t st);
 sqz_status launch_life_xtile(const FractalHost &F, const uint8_t *in, uint8_t *out, hipStream_t st);
 sqz_status launch_diffuse(const FractalHost &F, int dtype, float coef, int rounding, uint64_t seed, uint64_t step,
                           const void *in, void *out, int use_tile, hipStream_t st);

@@ -40,6 +40,9 @@ namespace sqz {
 #ifndef SQZ_TRI_TILE_LEVEL  // triangle tile level for large fractals
 #define SQZ_TRI_TILE_LEVEL 9
 #endif
+#ifndef SQZ_TRI_TILE_BIG_FROM  // fractal level from which triangle tiles use SQZ_TRI_TILE_LEVEL (else 8)
+#define SQZ_TRI_TILE_BIG_FROM 16
+#endif
 #ifndef SQZ_NT_LOAD
 #define SQZ_NT_LOAD 0
 #endif
@@ -48,15 +51,15 @@ namespace sqz {
 #endif
 
 // Tile level M: MMAX for fractals of level >= MBIG, else MSMALL (more,
-// smaller tiles keep a smaller fractal's launch balanced; at level 20 the
-// larger triangle tile is faster).
+// smaller tiles keep a smaller fractal's launch balanced; from level 16 the
+// larger triangle tile is faster with several steps per launch).
 struct PatTriangle {  // Sierpinski triangle, member iff x & y == 0
-    static constexpr int S = 2, K = 3, J = 3, MMAX = SQZ_TRI_TILE_LEVEL, MSMALL = 8, MBIG = 20;
+    static constexpr int S = 2, K = 3, J = 3, MMAX = SQZ_TRI_TILE_LEVEL, MSMALL = 8, MBIG = SQZ_TRI_TILE_BIG_FROM;
     static constexpr int OX[3] = {0, 1, 0};
     static constexpr int OY[3] = {0, 0, 1};
 };
 struct PatTrianglePaper {  // the paper's orientation: top, middle, right
-    static constexpr int S = 2, K = 3, J = 3, MMAX = SQZ_TRI_TILE_LEVEL, MSMALL = 8, MBIG = 20;
+    static constexpr int S = 2, K = 3, J = 3, MMAX = SQZ_TRI_TILE_LEVEL, MSMALL = 8, MBIG = SQZ_TRI_TILE_BIG_FROM;
     static constexpr int OX[3] = {0, 0, 1};
     static constexpr int OY[3] = {0, 1, 1};
 };

@@ -29,6 +29,19 @@ __global__ void __launch_bounds__(kXBlock) k_xtile(XArgs A, const typename Op::G
         for (uint64_t t = t0; t < t1; ++t) xtile_body<Op, PT>(A, in, out, t, op, S);
 }
 
+// K steps per launch (multi-step expanded tiles).
+template <class Op, int PT, int K>
+__global__ void __launch_bounds__(kXBlock) k_xtileK(XArgs A, const typename Op::G *__restrict__ in,
+                                                    typename Op::G *__restrict__ out, XOp op)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    xtile_setupK<Op>(A, smem);
+    const uint64_t chunk = (A.ntiles + gridDim.x - 1) / gridDim.x;
+    const uint64_t t0 = (uint64_t)blockIdx.x * chunk;
+    const uint64_t t1 = t0 + chunk < A.ntiles ? t0 + chunk : A.ntiles;
+    xtile_runK<Op, PT, 16, 4, K>(A, in, out, t0, t1, op, smem);
+}
+
 // ---------------------------------------------------------------------------
 // Thread-level diffusion (one lambda and eight nu per cell), for patterns or
 // levels without an expanded tile.
@@ -174,6 +187,8 @@ static unsigned occupancy_grid(size_t lds, uint64_t ntiles, int device)
     return (unsigned)(g < 1 ? 1 : g);
 }
 
+static sqz_status xtile_prepare_multi(FractalHost &F, XTileConfig *X);
+
 sqz_status xtile_prepare(FractalHost &F)
 {
     F.xtile = nullptr;
@@ -251,13 +266,131 @@ sqz_status xtile_prepare(FractalHost &F)
     X->lds_diff = xt_layout(P, KM, R, 4, true, false, nullptr);
     X->grid_life = occupancy_grid<XLife, 0>(X->lds_life, X->ntiles, F.device);
     X->grid_diff = occupancy_grid<XDiffF32, 0>(X->lds_diff, X->ntiles, F.device);
+    st = xtile_prepare_multi(F, X);
+    if (st != SQZ_OK) {
+        (void)hipFree(X->d_tab);
+        (void)hipFree(X->d_coarse);
+        delete X;
+        return st;
+    }
     F.xtile = X;
+    return SQZ_OK;
+}
+
+// Multi-step form of an expanded-tile configuration: the same tile level with a
+// border of K cells (K = 3 or 2, the largest whose tables fit the LDS budget).
+static constexpr size_t kXLdsBudgetK = 53 * 1024;  // three workgroups per CU
+
+template <class Op, int PT, int K>
+static unsigned occupancy_gridK(size_t lds, uint64_t ntiles, int device)
+{
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_xtileK<Op, PT, K>, kXBlock, lds) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    hipDeviceProp_t prop;
+    int cus = 256;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) cus = prop.multiProcessorCount;
+    uint64_t g = (uint64_t)cus * (uint64_t)per_cu;
+    if (g > ntiles) g = ntiles;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+static sqz_status xtile_prepare_multi(FractalHost &F, XTileConfig *X)
+{
+    X->K = 0;
+    X->d_tabk = nullptr;
+    const int M = X->M;
+    const int64_t B = X->B;
+    const uint32_t KM = X->KM;
+    if (KM > 16 * 256 || X->ntiles < 2) return SQZ_OK;
+    for (int K = 3; K >= 2; --K) {
+        if (K > B) continue;
+        const uint32_t P = (uint32_t)((B + 2 * K + 3) / 4 * 4), rows = (uint32_t)(B + 2 * K);
+        if ((uint64_t)P * rows > 65535) continue;
+        // ring slots by layer: member cells of the adjacent tiles within K of the box
+        struct Slot {
+            uint16_t pos;
+            uint32_t info;
+        };
+        std::vector<Slot> ring;
+        std::vector<uint32_t> start(1, 0);
+        for (int d = 1; d <= K; ++d) {
+            for (int64_t qy = -K; qy < B + K; ++qy)
+                for (int64_t qx = -K; qx < B + K; ++qx) {
+                    const int64_t ex = qx < 0 ? -qx : (qx >= B ? qx - B + 1 : 0);
+                    const int64_t ey = qy < 0 ? -qy : (qy >= B ? qy - B + 1 : 0);
+                    if ((ex > ey ? ex : ey) != d) continue;
+                    const int tdx = qx < 0 ? -1 : (qx >= B ? 1 : 0), tdy = qy < 0 ? -1 : (qy >= B ? 1 : 0);
+                    const int64_t j = host_nu(F, M, qx - tdx * B, qy - tdy * B);
+                    if (j < 0) continue;
+                    const int dd = (tdy + 1) * 3 + (tdx + 1);
+                    const uint32_t d8 = (uint32_t)(dd < 4 ? dd : dd - 1);
+                    ring.push_back(Slot{(uint16_t)((qy + K) * P + (qx + K)), (d8 << 16) | (uint32_t)j});
+                }
+            start.push_back((uint32_t)ring.size());
+        }
+        const uint32_t R = (uint32_t)ring.size();
+        if (R > 4 * 256) continue;
+        const size_t lds_life = xt_layoutK(P, rows, KM, R, 1, true, nullptr);
+        const size_t lds_diff = xt_layoutK(P, rows, KM, R, 4, false, nullptr);
+        if (lds_life > kXLdsBudgetK || lds_diff > kXLdsBudgetK) continue;
+        // tables: lambda positions, membership of the tile's cells, ring slots
+        std::vector<uint16_t> lam(KM);
+        std::vector<uint8_t> mem((size_t)P * rows, 0);
+        for (uint32_t c = 0; c < KM; ++c) {
+            int64_t x, y;
+            host_lambda(F, M, c, x, y);
+            lam[c] = (uint16_t)((y + K) * P + (x + K));
+            mem[lam[c]] = 1;
+        }
+        const size_t o_lam = 0, o_mem = xt_align16(o_lam + KM * 2), o_rpos = xt_align16(o_mem + (size_t)P * rows),
+                     o_rinfo = xt_align16(o_rpos + (size_t)R * 2), total = xt_align16(o_rinfo + (size_t)R * 4 + 4);
+        std::vector<uint8_t> blob(total, 0);
+        memcpy(blob.data() + o_lam, lam.data(), KM * 2);
+        memcpy(blob.data() + o_mem, mem.data(), (size_t)P * rows);
+        for (uint32_t j = 0; j < R; ++j) {
+            memcpy(blob.data() + o_rpos + 2 * j, &ring[j].pos, 2);
+            memcpy(blob.data() + o_rinfo + 4 * j, &ring[j].info, 4);
+        }
+        hipError_t e = hipMalloc(&X->d_tabk, total);
+        if (e == hipSuccess) e = hipMemcpy(X->d_tabk, blob.data(), total, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            if (X->d_tabk) (void)hipFree(X->d_tabk);
+            X->d_tabk = nullptr;
+            return hip_error(e, "multi-step expanded-tile tables");
+        }
+        const uint8_t *b = (const uint8_t *)X->d_tabk;
+        XArgs &A = X->kbase;
+        A = X->base;
+        A.P = P;
+        A.rows = rows;
+        A.K = (uint32_t)K;
+        A.R = R;
+        for (int d = 0; d < 4; ++d) A.ring_start[d] = start[d <= K ? d : K];
+        A.lam = (const uint16_t *)(b + o_lam);
+        A.mem_in = b + o_mem;
+        A.rpos = (const uint16_t *)(b + o_rpos);
+        A.rinfo = (const uint32_t *)(b + o_rinfo);
+        X->ldsk_life = lds_life;
+        X->ldsk_diff = lds_diff;
+        if (K == 3) {
+            X->gridk_life = occupancy_gridK<XLife, 0, 3>(lds_life, X->ntiles, F.device);
+            X->gridk_diff = occupancy_gridK<XDiffF32, 0, 3>(lds_diff, X->ntiles, F.device);
+        } else {
+            X->gridk_life = occupancy_gridK<XLife, 0, 2>(lds_life, X->ntiles, F.device);
+            X->gridk_diff = occupancy_gridK<XDiffF32, 0, 2>(lds_diff, X->ntiles, F.device);
+        }
+        X->K = (uint32_t)K;
+        return SQZ_OK;
+    }
     return SQZ_OK;
 }
 
 void xtile_release(FractalHost &F)
 {
     if (!F.xtile) return;
+    if (F.xtile->d_tabk) (void)hipFree(F.xtile->d_tabk);
     (void)hipFree(F.xtile->d_tab);
     (void)hipFree(F.xtile->d_coarse);
     delete F.xtile;
@@ -285,6 +418,58 @@ static sqz_status launch_x(const FractalHost &F, const void *in, void *out, cons
     }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? SQZ_OK : hip_error(e, "expanded-tile launch");
+}
+
+// `steps` (1..K) steps per launch with the multi-step form (1: the one-step kernel).
+template <class Op>
+static sqz_status launch_xK(const FractalHost &F, const void *in, void *out, const XOp &op, int steps, hipStream_t st)
+{
+    const XTileConfig *X = F.xtile;
+    if (steps == 1) return launch_x<Op>(F, in, out, op, st);
+    if (steps < 1 || steps > (int)X->K)
+        return set_error(SQZ_ERR_UNSUPPORTED, "%d steps per launch exceed the %u of this fractal's tiles", steps, X->K);
+    XArgs A = X->kbase;
+    const bool life = !Op::kMem;
+    const size_t lds = xt_layoutK(A.P, A.rows, A.KM, A.R, sizeof(typename Op::L), life, &A);
+    const unsigned grid = life ? X->gridk_life : X->gridk_diff;
+    using G = typename Op::G;
+    const G *i = (const G *)in;
+    G *o = (G *)out;
+    if (steps == 3) {
+        if (A.P == 88)
+            hipLaunchKernelGGL((k_xtileK<Op, 88, 3>), dim3(grid), dim3(kXBlock), lds, st, A, i, o, op);
+        else
+            hipLaunchKernelGGL((k_xtileK<Op, 0, 3>), dim3(grid), dim3(kXBlock), lds, st, A, i, o, op);
+    } else {
+        if (A.P == 88)
+            hipLaunchKernelGGL((k_xtileK<Op, 88, 2>), dim3(grid), dim3(kXBlock), lds, st, A, i, o, op);
+        else
+            hipLaunchKernelGGL((k_xtileK<Op, 0, 2>), dim3(grid), dim3(kXBlock), lds, st, A, i, o, op);
+    }
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SQZ_OK : hip_error(e, "multi-step expanded-tile launch");
+}
+
+int xtile_steps_per_launch(const FractalHost &F) { return F.xtile ? (F.xtile->K > 1 ? (int)F.xtile->K : 1) : 0; }
+
+sqz_status launch_life_xtile_steps(const FractalHost &F, const uint8_t *in, uint8_t *out, int steps, hipStream_t st)
+{
+    if (!F.xtile) return set_error(SQZ_ERR_UNSUPPORTED, "no expanded tile for this fractal");
+    XOp op{};
+    return launch_xK<XLife>(F, in, out, op, steps, st);
+}
+
+sqz_status launch_diffuse_xtile_steps(const FractalHost &F, int dtype, float coef, int rounding, uint64_t seed,
+                                      uint64_t step, const void *in, void *out, int steps, hipStream_t st)
+{
+    if (!F.xtile) return set_error(SQZ_ERR_UNSUPPORTED, "no expanded tile for this fractal");
+    XOp op;
+    op.coef = coef;
+    op.rounding = (uint32_t)rounding;
+    op.seed = seed;
+    op.step = step;
+    return dtype == SQZ_F32 ? launch_xK<XDiffF32>(F, in, out, op, steps, st)
+                            : launch_xK<XDiffBF16>(F, in, out, op, steps, st);
 }
 
 sqz_status launch_life_xtile(const FractalHost &F, const uint8_t *in, uint8_t *out, hipStream_t st)

@@ -37,6 +37,10 @@ struct XArgs {
     uint32_t KM, P, R, B;  // cells per tile, row pitch (multiple of 4), ring slots, box side
     uint32_t off_val, off_res, off_mem, off_lam, off_rpos, off_rinfo, off_nbase;
     uint32_t vec;  // 1 when a tile is a whole number of 16-byte vectors
+    // multi-step tiles: border of K cells, `rows` box rows; ring slots of layer d
+    // (Chebyshev distance d from the tile's box) are [ring_start[d-1], ring_start[d])
+    uint32_t K, rows;
+    uint32_t ring_start[4];
     const uint16_t *lam;
     const uint8_t *mem_in;
     const uint16_t *rpos;
@@ -378,6 +382,12 @@ struct XTileConfig {
     size_t lds_life, lds_diff;
     unsigned grid_life, grid_diff;
     void *d_coarse;
+    // multi-step form (K steps per launch; K = 0: none)
+    uint32_t K;
+    void *d_tabk;
+    XArgs kbase;
+    size_t ldsk_life, ldsk_diff;
+    unsigned gridk_life, gridk_diff;
 };
 
 // LDS layout: values, membership bytes (diffusion), lambda table, ring tables, 8 bases.
@@ -409,6 +419,221 @@ inline size_t xt_layout(uint32_t P, uint32_t KM, uint32_t R, size_t val_bytes, b
         A->off_nbase = (uint32_t)off_nbase;
     }
     return off;
+}
+
+// LDS layout of the multi-step form: values (Life: two boxes), membership,
+// lambda table, ring tables, 2 x 8 bases.  Boxes are P x rows with 16 zero
+// bytes on both sides (row updates read one word past each end).
+inline size_t xt_layoutK(uint32_t P, uint32_t rows, uint32_t KM, uint32_t R, size_t val_bytes, bool life, XArgs *A)
+{
+    const size_t box = (size_t)P * rows;
+    const size_t off_val = 16;
+    size_t off = xt_align16(off_val + box * val_bytes + 16);
+    const size_t off_res = off + 16;
+    if (life) off = xt_align16(off_res + box + 16);
+    const size_t off_mem = off;
+    off = xt_align16(off + box);
+    const size_t off_lam = off;
+    off = xt_align16(off + (size_t)KM * 2);
+    const size_t off_rpos = off;
+    off = xt_align16(off + (size_t)R * 2);
+    const size_t off_rinfo = off;
+    off = xt_align16(off + (size_t)R * 4);
+    const size_t off_nbase = off;
+    off += 16 * 8;
+    if (A) {
+        A->off_val = (uint32_t)off_val;
+        A->off_res = (uint32_t)off_res;
+        A->off_mem = (uint32_t)off_mem;
+        A->off_lam = (uint32_t)off_lam;
+        A->off_rpos = (uint32_t)off_rpos;
+        A->off_rinfo = (uint32_t)off_rinfo;
+        A->off_nbase = (uint32_t)off_nbase;
+    }
+    return off;
+}
+
+// Zero both boxes (with their pads) and the membership box, then copy the
+// tile-invariant tables into LDS (membership of the tile's own cells included).
+template <class Op>
+__device__ __forceinline__ void xtile_setupK(const XArgs &A, unsigned char *smem)
+{
+    const uint32_t tid = threadIdx.x, box = A.P * A.rows;
+    const uint32_t end = Op::kSwar ? A.off_res + box + 16 : A.off_val + box * (uint32_t)sizeof(typename Op::L) + 16;
+    for (uint32_t i = tid; i < end / 4; i += kXBlock) reinterpret_cast<uint32_t *>(smem)[i] = 0;
+    uint8_t *mem = smem + A.off_mem;
+    for (uint32_t i = tid; i < box; i += kXBlock) mem[i] = A.mem_in[i];
+    uint16_t *lam = reinterpret_cast<uint16_t *>(smem + A.off_lam);
+    for (uint32_t i = tid; i < A.KM; i += kXBlock) lam[i] = A.lam[i];
+    uint16_t *rpos = reinterpret_cast<uint16_t *>(smem + A.off_rpos);
+    uint32_t *rinfo = reinterpret_cast<uint32_t *>(smem + A.off_rinfo);
+    for (uint32_t i = tid; i < A.R; i += kXBlock) {
+        rpos[i] = A.rpos[i];
+        rinfo[i] = A.rinfo[i];
+    }
+}
+
+// Life on box rows 1..rows-2, four positions per word, masked by membership.
+__device__ __forceinline__ void xt_life_rows(const uint8_t *src, uint8_t *dst, const uint8_t *mem, uint32_t P,
+                                             uint32_t rows)
+{
+    const uint32_t W4 = P / 4, n = (rows - 2) * W4;
+    const uint32_t *v32 = reinterpret_cast<const uint32_t *>(src);
+    const uint32_t *m32 = reinterpret_cast<const uint32_t *>(mem);
+    uint32_t *r32 = reinterpret_cast<uint32_t *>(dst);
+    for (uint32_t idx = threadIdx.x; idx < n; idx += kXBlock) {
+        const uint32_t y = 1 + idx / W4, w = idx - (y - 1) * W4;
+        const uint32_t *q = v32 + (y - 1) * W4 + w;
+        const uint32_t a0 = q[-1], b0 = q[0], c0 = q[1];
+        const uint32_t a1 = q[W4 - 1], b1 = q[W4], c1 = q[W4 + 1];
+        const uint32_t a2 = q[2 * W4 - 1], b2 = q[2 * W4], c2 = q[2 * W4 + 1];
+        const uint32_t cnt = b0 + __builtin_amdgcn_alignbyte(b0, a0, 3) + __builtin_amdgcn_alignbyte(c0, b0, 1) +
+                             b2 + __builtin_amdgcn_alignbyte(b2, a2, 3) + __builtin_amdgcn_alignbyte(c2, b2, 1) +
+                             __builtin_amdgcn_alignbyte(b1, a1, 3) + __builtin_amdgcn_alignbyte(c1, b1, 1);
+        const uint32_t z = (cnt | b1) ^ 0x03030303u;
+        const uint32_t live = (~(((z & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | z) >> 7) & 0x01010101u;
+        r32[y * W4 + w] = live & m32[y * W4 + w];
+    }
+}
+
+// K steps of every tile in [t0, t1), software-pipelined as xtile_run.  The
+// box has a border of K cells; all member cells of layers 1..K are loaded
+// with the tile (their membership, which depends on whether the adjacent tile
+// exists, goes into the membership box).  Round j is exact on the tile and on
+// layers 1..K-j, which is all that round j+1 reads.  Life: whole rows per
+// round, two boxes alternating.  Diffusion: the cells of the tile and of
+// layers 1..K-j, results held in registers until every lane has read the
+// round's inputs; intermediate states are rounded to the storage type exactly
+// as a one-step launch stores them.
+template <class Op, int PT, int KPL, int RPL, int K>
+__device__ __forceinline__ void xtile_runK(const XArgs &A, const typename Op::G *__restrict__ in,
+                                           typename Op::G *__restrict__ out, uint64_t t0, uint64_t t1, const XOp &op,
+                                           unsigned char *smem)
+{
+    using G = typename Op::G;
+    using L = typename Op::L;
+    const uint32_t P = PT ? (uint32_t)PT : A.P;
+    const uint32_t KM = A.KM, R = A.R, tid = threadIdx.x;
+    L *val = reinterpret_cast<L *>(smem + A.off_val);
+    uint8_t *res = smem + A.off_res;
+    uint8_t *mem = smem + A.off_mem;
+    const uint16_t *lam = reinterpret_cast<const uint16_t *>(smem + A.off_lam);
+    const uint16_t *rpos = reinterpret_cast<const uint16_t *>(smem + A.off_rpos);
+    const uint32_t *rinfo = reinterpret_cast<const uint32_t *>(smem + A.off_rinfo);
+    uint64_t *nbase = reinterpret_cast<uint64_t *>(smem + A.off_nbase);
+    if (t0 >= t1) return;
+    G cur[KPL];
+    L rv[RPL];
+    bool rm[RPL];
+    __syncthreads();
+    xtile_bases(A, t0, nbase + 8 * (t0 & 1));
+    __syncthreads();
+    auto fetch = [&](uint64_t t) {
+        const G *src = in + t * KM;
+        const uint64_t *nb = nbase + 8 * (t & 1);
+#pragma unroll
+        for (int k = 0; k < KPL; ++k) {
+            const uint32_t l = (uint32_t)k * 256 + tid;
+            if (l < KM) cur[k] = src[l];
+        }
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) {
+            const uint32_t j = (uint32_t)k * 256 + tid;
+            rv[k] = (L)0;
+            rm[k] = false;
+            if (j < R) {
+                const uint32_t info = rinfo[j];
+                const uint64_t b = nb[info >> 16];
+                if (b != kHole64) {
+                    rv[k] = to_lds(in[b + (info & 0xFFFFu)]);
+                    rm[k] = true;
+                }
+            }
+        }
+    };
+    fetch(t0);
+    for (uint64_t t = t0; t < t1; ++t) {
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < KPL; ++k) {
+            const uint32_t l = (uint32_t)k * 256 + tid;
+            if (l < KM) val[lam[l]] = to_lds(cur[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) {
+            const uint32_t j = (uint32_t)k * 256 + tid;
+            if (j < R) {
+                val[rpos[j]] = rv[k];
+                mem[rpos[j]] = rm[k];
+            }
+        }
+        const uint64_t *nbt = nbase + 8 * (t & 1);
+        const bool more = t + 1 < t1;
+        if (more) xtile_bases(A, t + 1, nbase + 8 * ((t + 1) & 1));
+        __syncthreads();
+        if (more) fetch(t + 1);
+        G *dst = out + t * KM;
+        const uint64_t gbase = t * KM;
+        if constexpr (Op::kSwar) {
+            uint8_t *a = reinterpret_cast<uint8_t *>(val), *b = res;
+#pragma unroll
+            for (int j = 1; j <= K; ++j) {
+                xt_life_rows(a, b, mem, P, A.rows);
+                __syncthreads();
+                uint8_t *c = a;
+                a = b;
+                b = c;
+            }
+#pragma unroll
+            for (int k = 0; k < KPL; ++k) {
+                const uint32_t l = (uint32_t)k * 256 + tid;
+                if (l < KM) dst[l] = a[lam[l]];
+            }
+        } else {
+#pragma unroll
+            for (int j = 1; j <= K; ++j) {
+                XOp oj = op;
+                oj.step = op.step + (uint64_t)(j - 1);
+                G nv[KPL];
+#pragma unroll
+                for (int k = 0; k < KPL; ++k) {
+                    const uint32_t l = (uint32_t)k * 256 + tid;
+                    if (l < KM) nv[k] = cell_update<Op>(val, mem, lam[l], P, oj, gbase + l);
+                }
+                if (j == K) {
+#pragma unroll
+                    for (int k = 0; k < KPL; ++k) {
+                        const uint32_t l = (uint32_t)k * 256 + tid;
+                        if (l < KM) dst[l] = nv[k];
+                    }
+                } else {
+                    const uint32_t nring = A.ring_start[K - j];
+                    G rn[RPL];
+#pragma unroll
+                    for (int k = 0; k < RPL; ++k) {
+                        const uint32_t jj = (uint32_t)k * 256 + tid;
+                        if (jj < nring) {
+                            const uint32_t info = rinfo[jj];
+                            const uint64_t b = nbt[info >> 16];
+                            rn[k] = cell_update<Op>(val, mem, rpos[jj], P, oj, b + (info & 0xFFFFu));
+                        }
+                    }
+                    __syncthreads();  // every lane has read the round's inputs
+#pragma unroll
+                    for (int k = 0; k < KPL; ++k) {
+                        const uint32_t l = (uint32_t)k * 256 + tid;
+                        if (l < KM) val[lam[l]] = to_lds(nv[k]);
+                    }
+#pragma unroll
+                    for (int k = 0; k < RPL; ++k) {
+                        const uint32_t jj = (uint32_t)k * 256 + tid;
+                        if (jj < nring && mem[rpos[jj]]) val[rpos[jj]] = to_lds(rn[k]);
+                    }
+                    __syncthreads();
+                }
+            }
+        }
+    }
 }
 
 }  // namespace sqz
