@@ -217,7 +217,8 @@ def batch_leg(torch, sqz, steps: int) -> dict:
     sec = e0.elapsed_time(e1) / 1e3
     res = {"instances": len(inst), "cells": B.total_cells, "steps": steps, "ms_per_step": sec * 1e3 / steps,
            "cell_updates_per_s": B.total_cells * steps / sec,
-           "algorithmic_gbs": 2 * B.total_cells * steps / sec / 1e9, "wg_per_cu": wg, "graph": True,
+           "algorithmic_gbs_per_step": 2 * B.total_cells * steps / sec / 1e9, "wg_per_cu": wg, "graph": True,
+           "steps_per_launch": B.steps_per_launch,
            "mix": {k: sum(1 for x in inst if x[0] == k) for k in ("triangle", "carpet", "vicsek")}}
     del a, b, B, fr, cache
     torch.cuda.empty_cache()

@@ -331,9 +331,14 @@ SQZ_API sqz_status sqz_batch_fill_bernoulli(const sqz_batch *b, const uint64_t *
 /* One step of every instance: one kernel launch.  Buffers 16-byte aligned, non-overlapping. */
 SQZ_API sqz_status sqz_batch_step(const sqz_batch *b, const uint8_t *d_in, uint8_t *d_out, void *stream);
 
-/* `steps` steps ping-ponging from d_a (result in d_a if steps is even, else d_b).  For steps >= 2 the
- * launches are captured once into a hipGraph (cached for the same buffers and step count) and replayed. */
+/* `steps` steps ping-ponging from d_a (result in d_a if steps is even, else d_b).  Each launch takes
+ * up to sqz_batch_steps_per_launch steps (multi-step tiles, when every instance has them; the
+ * launch count keeps the parity of `steps`).  For steps >= 2 the launches are captured once into a
+ * hipGraph (cached for the same buffers and step count) and replayed. */
 SQZ_API sqz_status sqz_batch_run(sqz_batch *b, uint8_t *d_a, uint8_t *d_b, int32_t steps, void *stream);
+
+/* Most steps one launch of sqz_batch_run takes (1 when some instance has no multi-step tiles). */
+SQZ_API sqz_status sqz_batch_steps_per_launch(const sqz_batch *b, int32_t *steps);
 
 /* Time candidate grid sizes (workgroups per compute unit) on the given buffers (their contents are
  * advanced by a few steps) and keep the fastest for this batch and for later batches of the same

@@ -301,6 +301,9 @@ class Batch:
         self.total_bytes = self.offsets[-1]
         self.total_cells = int(total.value)
         self.device = self.fractals[0].device
+        k = ctypes.c_int32()
+        check(lib().sqz_batch_steps_per_launch(h, ctypes.byref(k)))
+        self.steps_per_launch = int(k.value)
 
     def close(self):
         if getattr(self, "_h", None):

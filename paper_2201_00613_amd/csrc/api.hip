@@ -480,25 +480,6 @@ sqz_status sqz_compact_step(const sqz_fractal *f, const uint8_t *d_in, uint8_t *
     return sqz_compact_step_impl(f, SQZ_IMPL_AUTO, d_in, d_out, stream);
 }
 
-// Launch sizes for `steps` steps with at most K per launch (temporal
-// blocking): launches of K steps and one of the remainder.  Every launch swaps
-// the two buffers, so the launch count must have the parity of `steps` for the
-// result to land where one-step launches would leave it; if it does not, the
-// last launch of two or more steps is split into (n - 1) + 1.
-static std::vector<int> plan_launches(int32_t steps, int K)
-{
-    std::vector<int> plan((size_t)(steps / K), K);
-    if (steps % K) plan.push_back(steps % K);
-    if ((plan.size() & 1) != (size_t)(steps & 1))
-        for (size_t i = plan.size(); i-- > 0;)
-            if (plan[i] >= 2) {
-                plan[i] -= 1;
-                plan.push_back(1);
-                break;
-            }
-    return plan;
-}
-
 sqz_status sqz_compact_run(const sqz_fractal *f, uint8_t *d_a, uint8_t *d_b, int32_t steps, void *stream)
 {
     sqz_status st = check_handle(f);
@@ -727,6 +708,13 @@ sqz_status sqz_batch_layout(const sqz_batch *b, uint64_t *offsets, uint64_t *tot
     if (offsets)
         for (int32_t i = 0; i <= n; ++i) offsets[i] = i < n ? batch_offset(b->h, i) : batch_total_bytes(b->h);
     if (total_cells) *total_cells = batch_total_cells(b->h);
+    return SQZ_OK;
+}
+
+sqz_status sqz_batch_steps_per_launch(const sqz_batch *b, int32_t *steps)
+{
+    if (!b || !steps) return set_error(SQZ_ERR_INVALID, "NULL argument");
+    *steps = batch_steps_per_launch(b->h);
     return SQZ_OK;
 }
 

@@ -45,6 +45,7 @@ struct BatchInst {
     uint64_t cells;
     TileArgs tile;
     XArgs x;
+    XArgs xk;  // multi-step expanded tiles (LDS offsets of the Life layout)
     MapParams P;
 };
 
@@ -80,16 +81,22 @@ __device__ __forceinline__ void life_cell_unit(const MapParams &P, const uint8_t
     }
 }
 
-template <class Pat>
+template <class Pat, int K>
 __device__ __forceinline__ void bitsliced_unit(const BatchInst &I, const uint8_t *in, uint8_t *out, uint64_t t,
                                                unsigned char *smem)
 {
     using LDS = TileLds<Pat>;
     uint32_t *s_in = reinterpret_cast<uint32_t *>(smem);
-    uint32_t *s_out = s_in + LDS::IN_WORDS;
-    tile_body<Pat>(I.tile, in, out, t, s_in, s_out);
+    if constexpr (K == 1) {
+        tile_body<Pat>(I.tile, in, out, t, s_in, s_in + LDS::IN_WORDS);
+    } else {
+        uint32_t *const buf[3] = {s_in, s_in + LDS::IN_WORDS, s_in + 2 * LDS::IN_WORDS};
+        tile_bodyK<Pat, K>(I.tile, in, out, t, buf, s_in + 3 * LDS::IN_WORDS);
+    }
 }
 
+// K Life steps of every instance (K > 1: every instance has multi-step tiles).
+template <int K>
 __global__ void __launch_bounds__(256) k_batch_life(BatchArgs B, const uint8_t *__restrict__ in,
                                                     uint8_t *__restrict__ out)
 {
@@ -127,30 +134,42 @@ __global__ void __launch_bounds__(256) k_batch_life(BatchArgs B, const uint8_t *
         switch (I.kind) {
         case kBTri:
             loaded = -1;
-            bitsliced_unit<PatTriangle>(I, ii, oo, j, smem);
+            bitsliced_unit<PatTriangle, K>(I, ii, oo, j, smem);
             ++j;
             break;
         case kBTriPaper:
             loaded = -1;
-            bitsliced_unit<PatTrianglePaper>(I, ii, oo, j, smem);
+            bitsliced_unit<PatTrianglePaper, K>(I, ii, oo, j, smem);
             ++j;
             break;
         case kBVicsek:
             loaded = -1;
-            bitsliced_unit<PatVicsek>(I, ii, oo, j, smem);
+            bitsliced_unit<PatVicsek, K>(I, ii, oo, j, smem);
             ++j;
             break;
         case kBX68:
         case kBX84:
         case kBXAny: {
+            // this workgroup's run of consecutive tiles of the instance
+            uint64_t je = (hi - I.cost_start + I.unit_cost - 1) / I.unit_cost;
+            if (je > I.units) je = I.units;
+            if constexpr (K > 1) {
+                if (loaded != (int)I.xcfg) {
+                    xtile_setupK<XLife>(I.xk, smem);
+                    loaded = (int)I.xcfg;
+                }
+                if (I.xk.P == 88)
+                    xtile_runK<XLife, 88, 16, 4, K>(I.xk, ii, oo, j, je, op, smem);
+                else
+                    xtile_runK<XLife, 0, 16, 4, K>(I.xk, ii, oo, j, je, op, smem);
+                j = je;
+                break;
+            }
             const XLds<XLife> S(smem, I.x);
             if (loaded != (int)I.xcfg) {
                 xtile_setup<XLife>(I.x, S);
                 loaded = (int)I.xcfg;
             }
-            // this workgroup's run of consecutive tiles of the instance
-            uint64_t je = (hi - I.cost_start + I.unit_cost - 1) / I.unit_cost;
-            if (je > I.units) je = I.units;
             if (I.kind == kBX84 && I.x.KM == 16 * 256 && I.x.R <= 2 * 256) {
                 xtile_run<XLife, 84, 16, 2, true>(I.x, ii, oo, j, je, op, S);
             } else if (I.x.KM <= 16 * 256 && I.x.R <= 2 * 256) {
@@ -190,7 +209,8 @@ struct BatchHost {
     uint64_t *d_cost_start;
     uint64_t total_cost;
     unsigned xt_weight;  // cost per cell of the expanded-tile path (bit-sliced = 2, thread-level = 32)
-    size_t lds;
+    size_t lds, ldsk;  // dynamic LDS of the one-step and the K-step kernel
+    int K;              // steps per launch of batch runs (1: one-step only)
     unsigned wg_per_cu, max_wg_per_cu;
     std::string key;
     hipStream_t cap;
@@ -215,14 +235,18 @@ static uint32_t kind_of(const FractalHost &F)
 }
 
 template <class Pat>
-static size_t tile_lds() { return (size_t)(TileLds<Pat>::IN_WORDS + TileLds<Pat>::WMAX + 1) * 4; }
+static size_t tile_lds(bool multi)
+{
+    return multi ? (size_t)(3 * TileLds<Pat>::IN_WORDS + kMaxSteps + 1) * 4
+                 : (size_t)(TileLds<Pat>::IN_WORDS + TileLds<Pat>::WMAX + 1) * 4;
+}
 
-static size_t tile_lds_of(const FractalHost &F)
+static size_t tile_lds_of(const FractalHost &F, bool multi)
 {
     switch (F.tile_kind) {
-    case 1: return tile_lds<PatTriangle>();
-    case 2: return tile_lds<PatTrianglePaper>();
-    default: return tile_lds<PatVicsek>();
+    case 1: return tile_lds<PatTriangle>(multi);
+    case 2: return tile_lds<PatTrianglePaper>(multi);
+    default: return tile_lds<PatVicsek>(multi);
     }
 }
 
@@ -265,7 +289,8 @@ sqz_status batch_create(const sqz_fractal *const *fr, int32_t count, BatchHost *
     std::map<std::string, uint32_t> xcfg_ids;
     std::vector<uint64_t> cell_start(count + 1);
     uint64_t off = 0, cstart = 0;
-    size_t lds = 0;
+    size_t lds = 0, ldsk = 0;
+    int kmin = kMaxSteps;
     char buf[64];
     for (int32_t i = 0; i < count; ++i) {
         const FractalHost &F = fractal_host_of(fr[i]);
@@ -284,13 +309,22 @@ sqz_status batch_create(const sqz_fractal *const *fr, int32_t count, BatchHost *
             I.tile = tile_args(F);
             I.units = I.tile.ntiles;
             I.unit_cells = I.tile.tile;
-            lds = std::max(lds, tile_lds_of(F));
+            lds = std::max(lds, tile_lds_of(F, false));
+            ldsk = std::max(ldsk, tile_lds_of(F, true));
+            kmin = std::min(kmin, tile_steps_per_launch(F));
         } else if (I.kind != kBCell) {
             const XTileConfig *X = F.xtile;
             I.x = X->base;
             const size_t need = xt_layout(X->P, X->KM, X->R, 1, false, true, &I.x);
             I.x.vec = (X->KM % 16 == 0) ? 1u : 0u;
             lds = std::max(lds, need);
+            if (X->K >= 2) {
+                I.xk = X->kbase;
+                ldsk = std::max(ldsk, xt_layoutK(I.xk.P, I.xk.rows, I.xk.KM, I.xk.R, 1, true, &I.xk));
+                kmin = std::min(kmin, (int)X->K);
+            } else {
+                kmin = 1;
+            }
             std::string key = std::to_string(F.s) + ":" + std::to_string(X->M);
             for (int j = 0; j < F.k; ++j) key += "," + std::to_string(F.ox[j]) + "/" + std::to_string(F.oy[j]);
             auto it = xcfg_ids.find(key);
@@ -311,6 +345,7 @@ sqz_status batch_create(const sqz_fractal *const *fr, int32_t count, BatchHost *
         } else {
             I.units = (F.N + kCellUnit - 1) / kCellUnit;
             I.unit_cells = kCellUnit;
+            kmin = 1;
         }
         snprintf(buf, sizeof buf, "%d:%d:%d;", (int)I.kind, F.s, F.r);
         H->key += buf;
@@ -325,6 +360,8 @@ sqz_status batch_create(const sqz_fractal *const *fr, int32_t count, BatchHost *
     H->total_cells = cstart;
     H->total_bytes = off;
     H->lds = std::max<size_t>(lds, 16);
+    H->K = count > 0 && kmin >= 2 ? std::min(kmin, 3) : 1;
+    H->ldsk = std::max<size_t>(ldsk, 16);
     H->d_inst = nullptr;
     H->d_cost_start = nullptr;
     H->cap = nullptr;
@@ -340,7 +377,13 @@ sqz_status batch_create(const sqz_fractal *const *fr, int32_t count, BatchHost *
     if (e == hipSuccess) e = upload_costs(H);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&H->cap, hipStreamNonBlocking);
     int per_cu = 0;
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_life, 256, H->lds);
+    if (e == hipSuccess) {
+        switch (H->K) {
+        case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_life<3>, 256, H->ldsk); break;
+        case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_life<2>, 256, H->ldsk); break;
+        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_life<1>, 256, H->lds); break;
+        }
+    }
     if (e != hipSuccess) {
         if (H->d_inst) (void)hipFree(H->d_inst);
         if (H->d_cost_start) (void)hipFree(H->d_cost_start);
@@ -369,7 +412,9 @@ void batch_destroy(BatchHost *H)
     delete H;
 }
 
-static sqz_status launch_batch(const BatchHost *H, unsigned wg_per_cu, const uint8_t *in, uint8_t *out, hipStream_t st)
+// One launch of `steps` (1..H->K) steps.
+static sqz_status launch_batch(const BatchHost *H, unsigned wg_per_cu, const uint8_t *in, uint8_t *out, int steps,
+                               hipStream_t st)
 {
     BatchArgs A;
     A.inst = H->d_inst;
@@ -378,14 +423,18 @@ static sqz_status launch_batch(const BatchHost *H, unsigned wg_per_cu, const uin
     A.total_cost = H->total_cost;
     uint64_t grid = (uint64_t)H->cus * wg_per_cu;
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(k_batch_life, dim3((unsigned)grid), dim3(256), H->lds, st, A, in, out);
+    switch (steps) {
+    case 3: hipLaunchKernelGGL(k_batch_life<3>, dim3((unsigned)grid), dim3(256), H->ldsk, st, A, in, out); break;
+    case 2: hipLaunchKernelGGL(k_batch_life<2>, dim3((unsigned)grid), dim3(256), H->ldsk, st, A, in, out); break;
+    default: hipLaunchKernelGGL(k_batch_life<1>, dim3((unsigned)grid), dim3(256), H->lds, st, A, in, out); break;
+    }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? SQZ_OK : hip_error(e, "batch launch");
 }
 
 sqz_status batch_step(const BatchHost *H, const uint8_t *in, uint8_t *out, hipStream_t st)
 {
-    return launch_batch(H, H->wg_per_cu, in, out, st);
+    return launch_batch(H, H->wg_per_cu, in, out, 1, st);
 }
 
 sqz_status batch_run(BatchHost *H, uint8_t *a, uint8_t *b, int32_t steps, hipStream_t st)
@@ -400,8 +449,9 @@ sqz_status batch_run(BatchHost *H, uint8_t *a, uint8_t *b, int32_t steps, hipStr
         hipError_t e = hipStreamBeginCapture(H->cap, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_error(e, "hipStreamBeginCapture");
         sqz_status s2 = SQZ_OK;
-        for (int32_t i = 0; i < steps && s2 == SQZ_OK; ++i)
-            s2 = launch_batch(H, H->wg_per_cu, (i & 1) ? b : a, (i & 1) ? a : b, H->cap);
+        const std::vector<int> plan = plan_launches(steps, H->K);
+        for (size_t i = 0; i < plan.size() && s2 == SQZ_OK; ++i)
+            s2 = launch_batch(H, H->wg_per_cu, (i & 1) ? b : a, (i & 1) ? a : b, plan[i], H->cap);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(H->cap, &g);
         if (s2 != SQZ_OK) {
@@ -444,10 +494,11 @@ sqz_status batch_autotune(BatchHost *H, uint8_t *a, uint8_t *b, hipStream_t st, 
             }
         }
         for (unsigned w = 1; w <= H->max_wg_per_cu && st2 == SQZ_OK; w = (w < 4 ? w + 1 : w * 2)) {
-            st2 = launch_batch(H, w, a, b, st);  // warm-up
+            st2 = launch_batch(H, w, a, b, H->K, st);  // warm-up
             if (st2 != SQZ_OK) break;
             (void)hipEventRecord(e0, st);
-            for (int i = 0; i < 4 && st2 == SQZ_OK; ++i) st2 = launch_batch(H, w, (i & 1) ? b : a, (i & 1) ? a : b, st);
+            for (int i = 0; i < 4 && st2 == SQZ_OK; ++i)
+                st2 = launch_batch(H, w, (i & 1) ? b : a, (i & 1) ? a : b, H->K, st);
             (void)hipEventRecord(e1, st);
             if (hipEventSynchronize(e1) != hipSuccess) {
                 st2 = set_error(SQZ_ERR_HIP, "autotune synchronisation failed");
@@ -485,6 +536,7 @@ uint64_t batch_total_bytes(const BatchHost *H) { return H->total_bytes; }
 uint64_t batch_offset(const BatchHost *H, int32_t i) { return H->offsets[i]; }
 int32_t batch_count(const BatchHost *H) { return (int32_t)H->inst.size(); }
 unsigned batch_wg_per_cu(const BatchHost *H) { return H->wg_per_cu; }
+int batch_steps_per_launch(const BatchHost *H) { return H->K; }
 uint64_t batch_total_cells(const BatchHost *H) { return H->total_cells; }
 
 }  // namespace sqz

@@ -11,6 +11,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "squeeze.h"
 
 namespace sqz {
@@ -178,6 +180,25 @@ struct FractalHost {
     MfmaParams *mfma;             // matrix-core map variants, null if unsupported (k > 127)
 };
 
+// Launch sizes for `steps` steps with at most K per launch (temporal
+// blocking): launches of K steps and one of the remainder.  Every launch swaps
+// the two buffers, so the launch count must have the parity of `steps` for the
+// result to land where one-step launches would leave it; if it does not, the
+// last launch of two or more steps is split into (n - 1) + 1.
+inline std::vector<int> plan_launches(int32_t steps, int K)
+{
+    std::vector<int> plan((size_t)(steps / K), K);
+    if (steps % K) plan.push_back(steps % K);
+    if ((plan.size() & 1) != (size_t)(steps & 1))
+        for (size_t i = plan.size(); i-- > 0;)
+            if (plan[i] >= 2) {
+                plan[i] -= 1;
+                plan.push_back(1);
+                break;
+            }
+    return plan;
+}
+
 // Host helpers (api.cpp)
 sqz_status set_error(sqz_status st, const char *fmt, ...);
 sqz_status hip_error(hipError_t e, const char *what);
@@ -246,6 +267,7 @@ uint64_t batch_total_bytes(const BatchHost *H);
 uint64_t batch_offset(const BatchHost *H, int32_t i);
 int32_t batch_count(const BatchHost *H);
 unsigned batch_wg_per_cu(const BatchHost *H);
+int batch_steps_per_launch(const BatchHost *H);
 uint64_t batch_total_cells(const BatchHost *H);
 const FractalHost &fractal_host_of(const sqz_fractal *f);
 sqz_status launch_life_tile(const FractalHost &F, const uint8_t *in, uint8_t *out, hipStream_t st);

@@ -303,7 +303,7 @@ static sqz_status xtile_prepare_multi(FractalHost &F, XTileConfig *X)
     const int M = X->M;
     const int64_t B = X->B;
     const uint32_t KM = X->KM;
-    if (KM > 16 * 256 || X->ntiles < 2) return SQZ_OK;
+    if (KM > 16 * 256) return SQZ_OK;
     for (int K = 3; K >= 2; --K) {
         if (K > B) continue;
         const uint32_t P = (uint32_t)((B + 2 * K + 3) / 4 * 4), rows = (uint32_t)(B + 2 * K);

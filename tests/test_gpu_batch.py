@@ -47,6 +47,26 @@ def test_small_mixed_batch_matches_oracle():
         mismatch(to_np(B.instance(res, i)), O.life_steps(starts[i], 9, nb), f"batch run {n} r={r}")
 
 
+def test_multi_step_runs_equal_eager_steps():
+    """Every instance has multi-step tiles (single-tile ones included), so runs take
+    three steps per launch; any step count equals that many one-step launches."""
+    torch = torch_or_skip()
+    spec = [("triangle", 9), ("carpet", 5), ("vicsek", 6), ("carpet", 2), ("triangle", 12), ("vicsek", 3),
+            ("triangle_paper", 10), ("carpet", 6)]
+    fr, B = build(spec)
+    assert B.steps_per_launch == 3
+    seeds = [31 * i + 1 for i in range(len(fr))]
+    for steps in (1, 2, 3, 4, 5, 7, 9):
+        a, b = B.fill_bernoulli(seeds, 0.5), B.empty_state()
+        res = B.run(a, b, steps)
+        assert res is (a if steps % 2 == 0 else b)
+        x, y = B.fill_bernoulli(seeds, 0.5), B.empty_state()
+        for _ in range(steps):
+            B.step(x, y)
+            x, y = y, x
+        assert torch.equal(res, x), steps
+
+
 def test_large_batch_equals_single_instance_runs():
     torch = torch_or_skip()
     spec = [("triangle", 12), ("carpet", 6), ("vicsek", 8), ("triangle", 14), ("carpet", 7), ("vicsek", 9),
