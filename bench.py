@@ -107,7 +107,7 @@ def profiled_traffic(workload: str):
     h = hashlib.sha256()
     for f in ("life_tile.hip", "tile_device.h", "common.h"):
         h.update(open(os.path.join(src, f), "rb").read())
-    path = os.path.join(ROOT, "profiles", "k_life_tile2_triangle_r16.md")
+    path = os.path.join(ROOT, "profiles", "k_life_tileK_triangle_r16.md")
     if not os.path.exists(path):
         return None
     m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
@@ -225,6 +225,23 @@ def batch_leg(torch, sqz, steps: int) -> dict:
     return res
 
 
+def carpet_life_leg(torch, sqz, steps: int) -> dict:
+    """Life on the level-9 Sierpinski carpet (134,217,728 cells; expanded tiles, several
+    steps per launch), Bernoulli(0.5), `steps` steps as one sqz_compact_run call."""
+    from paper_2201_00613_amd import workloads as W
+
+    F = sqz.Fractal(*W.CARPET, 9)
+    sec = compact_run(torch, F, 2201, 0.5, steps, 3)
+    launches = run_launches(F, steps)
+    res = {"fractal": "sierpinski carpet s=3 k=8", "level": 9, "cells": F.cells, "steps": steps,
+           "steps_per_launch": F.run_steps_per_launch, "launches": launches, "ms_per_step": sec * 1e3 / steps,
+           "cell_updates_per_s": F.cells * steps / sec,
+           "algorithmic_gbs_per_launch": BYTES_PER_UPDATE * F.cells * launches / sec / 1e9}
+    del F
+    torch.cuda.empty_cache()
+    return res
+
+
 def diffusion_leg(torch, sqz, steps: int) -> dict:
     """Carpet r=9 (134,217,728 cells), coef 0.1, U(0,1) start: binary32 and bfloat16
     (offset storage, stochastic rounding) for `steps` steps; binary64 mass drift."""
@@ -280,6 +297,8 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-diffusion", action="store_true")
+    ap.add_argument("--no-carpet-life", action="store_true")
+    ap.add_argument("--carpet-life-steps", type=int, default=30)
     ap.add_argument("--no-maps", action="store_true")
     ap.add_argument("--no-blocks", action="store_true")
     ap.add_argument("--blocks-steps", type=int, default=5)
@@ -332,7 +351,7 @@ def main() -> int:
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs / HBM_PEAK_GBS, "traffic": None},
     }
-    if args.impl == "auto" and F.run_steps_per_launch == 2:
+    if args.impl == "auto" and F.run_steps_per_launch >= 2:
         s1 = compact_run(torch, F, seed, p, args.steps, args.warmup, "tile")
         out["one_step_per_launch"] = {"ms_per_step": s1 * 1e3 / args.steps,
                                       "cell_updates_per_s": F.cells * args.steps / s1,
@@ -382,6 +401,10 @@ def main() -> int:
         out["batch"] = batch_leg(torch, sqz, args.batch_steps)
         log(f"[bench] batch: {out['batch']['instances']} instances, {out['batch']['cells']} cells, "
             f"{out['batch']['ms_per_step']:.3f} ms/step, {out['batch']['cell_updates_per_s']:.3e} cell-updates/s")
+    if not args.no_carpet_life:
+        out["carpet_life"] = cl = carpet_life_leg(torch, sqz, args.carpet_life_steps)
+        log(f"[bench] carpet r=9 Life: {cl['ms_per_step']:.4f} ms/step, {cl['cell_updates_per_s']:.3e} cell-updates/s "
+            f"({cl['steps_per_launch']} steps per launch)")
     if not args.no_diffusion:
         out["diffusion"] = diffusion_leg(torch, sqz, args.diffusion_steps)
         d = out["diffusion"]
