@@ -225,6 +225,17 @@ def batch_leg(torch, sqz, steps: int) -> dict:
     return res
 
 
+def repeat_stats(torch, F, seed, p, steps: int, reps: int) -> dict:
+    """Mean and standard error of ms per step over `reps` further timed runs of the
+    same `steps` (each one sqz_compact_run call on freshly filled buffers)."""
+    import statistics
+
+    ms = [compact_run(torch, F, seed, p, steps, 2) * 1e3 / steps for _ in range(reps)]
+    return {"n": reps, "mean_ms_per_step": statistics.fmean(ms),
+            "stderr_ms_per_step": statistics.stdev(ms) / len(ms) ** 0.5 if reps > 1 else 0.0,
+            "min_ms_per_step": min(ms), "max_ms_per_step": max(ms)}
+
+
 def carpet_life_leg(torch, sqz, steps: int) -> dict:
     """Life on the level-9 Sierpinski carpet (134,217,728 cells; expanded tiles, several
     steps per launch), Bernoulli(0.5), `steps` steps as one sqz_compact_run call."""
@@ -303,6 +314,7 @@ def main() -> int:
     ap.add_argument("--no-blocks", action="store_true")
     ap.add_argument("--blocks-steps", type=int, default=5)
     ap.add_argument("--maps-steps", type=int, default=10)
+    ap.add_argument("--reps", type=int, default=10, help="further timed runs for mean / standard error")
     ap.add_argument("--batch-steps", type=int, default=50)
     ap.add_argument("--diffusion-steps", type=int, default=1000)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -311,8 +323,8 @@ def main() -> int:
                     help="only time a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the multi-GPU "
-              "design is described in DESIGN.md, nothing here runs on more than one device)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the library has a "
+              "sharding design but nothing here runs on more than one device)", file=sys.stderr)
         return 2
 
     import torch
@@ -357,6 +369,12 @@ def main() -> int:
                                       "cell_updates_per_s": F.cells * args.steps / s1,
                                       "algorithmic_gbs": BYTES_PER_UPDATE * F.cells * args.steps / s1 / 1e9}
         log(f"[bench] one step per launch: {s1 * 1e3 / args.steps:.4f} ms/step")
+    if args.reps > 0:
+        out["repeats"] = repeat_stats(torch, F, seed, p, args.steps, args.reps)
+    out["memory_reduction_factor"] = F.n * F.n / F.cells  # n^2 bytes expanded vs N bytes compact
+    out["paper_context"] = {"hardware": "NVIDIA A100-40GB", "speedup_vs_bb": "~12x (level 16, its best block size)",
+                            "memory_reduction_factor": "~315x at level 20; 99.8x at level 16 (rho = 1)",
+                            "note": "the paper's figures, context only"}
     rec = profiled_traffic(out["config"]["workload"]) if args.impl == "auto" else None
     if rec:
         out["roofline"]["traffic"] = rec["traffic_bytes_per_launch"] / (sec / launches) / 1e9
@@ -389,6 +407,8 @@ def main() -> int:
         l20 = run_launches(F20, args.r20_steps)
         gbs20 = BYTES_PER_UPDATE * F20.cells * l20 / s20 / 1e9
         out["r20"] = {"cells": F20.cells, "steps": args.r20_steps, "launches": l20, "ms_per_step": ms20,
+                      "memory_reduction_factor": F20.n * F20.n / F20.cells,
+                      "repeats": repeat_stats(torch, F20, seed, 0.3, args.r20_steps, min(args.reps, 5)) if args.reps > 0 else None,
                       "ms_per_launch": s20 * 1e3 / l20, "cell_updates_per_s": F20.cells * args.r20_steps / s20,
                       "algorithmic_gbs_per_launch": gbs20, "hbm_frac": gbs20 / HBM_PEAK_GBS,
                       "step_equivalent_gbs": BYTES_PER_UPDATE * F20.cells * args.r20_steps / s20 / 1e9,

@@ -43,7 +43,9 @@ int orc_num_threads(void) { return omp_get_max_threads(); }
  * level mu is made of k copies of level mu-1, copy j translated by
  * tau_j * s^(mu-1).  The compact order is the concatenation of the copies
  * in replica order, which is the "unrolling" of Section "Compacting NBB
- * Fractals" laid out as one linear array (layout reading: see DESIGN).
+ * Fractals" laid out as one linear array (the paper fixes the compact
+ * rectangle's size but no memory layout; this linear order is the reading
+ * used throughout).
  * Output: xy[2c], xy[2c+1] = expanded coordinate of compact cell c,
  * for c in [0, k^r).
  */
