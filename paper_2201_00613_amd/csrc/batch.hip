@@ -88,10 +88,10 @@ __device__ __forceinline__ void bitsliced_unit(const BatchInst &I, const uint8_t
     using LDS = TileLds<Pat>;
     uint32_t *s_in = reinterpret_cast<uint32_t *>(smem);
     if constexpr (K == 1) {
-        tile_body<Pat>(I.tile, in, out, t, s_in, s_in + LDS::IN_WORDS);
+        tile_body<Pat>(I.tile, in, out, t, s_in, s_in + LDS::WORDS);
     } else {
-        uint32_t *const buf[3] = {s_in, s_in + LDS::IN_WORDS, s_in + 2 * LDS::IN_WORDS};
-        tile_bodyK<Pat, K>(I.tile, in, out, t, buf, s_in + 3 * LDS::IN_WORDS);
+        uint32_t *const buf[3] = {s_in, s_in + LDS::WORDS, s_in + 2 * LDS::WORDS};
+        tile_bodyK<Pat, K>(I.tile, in, out, t, buf, s_in + 3 * LDS::WORDS);
     }
 }
 
@@ -237,8 +237,7 @@ static uint32_t kind_of(const FractalHost &F)
 template <class Pat>
 static size_t tile_lds(bool multi)
 {
-    return multi ? (size_t)(3 * TileLds<Pat>::IN_WORDS + kMaxSteps + 1) * 4
-                 : (size_t)(TileLds<Pat>::IN_WORDS + TileLds<Pat>::WMAX + 1) * 4;
+    return multi ? (size_t)(3 * TileLds<Pat>::WORDS + 2) * 4 : (size_t)(2 * TileLds<Pat>::WORDS) * 4;
 }
 
 static size_t tile_lds_of(const FractalHost &F, bool multi)

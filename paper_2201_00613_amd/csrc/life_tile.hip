@@ -12,8 +12,8 @@ __global__ void __launch_bounds__(kBlock) k_life_tile(TileArgs A, const uint8_t 
                                                       uint8_t *__restrict__ out)
 {
     using LDS = TileLds<Pat>;
-    __shared__ uint32_t s_in[LDS::IN_WORDS];
-    __shared__ uint32_t s_out[LDS::WMAX + 1];  // +1: a block's high half may land one word past the tile
+    __shared__ uint32_t s_in[LDS::WORDS];
+    __shared__ uint32_t s_out[LDS::WORDS];
     const uint32_t G = gridDim.x;
     for (uint64_t round = 0; round * G < A.ntiles; ++round) {
         const uint64_t t = round * G + xcd_remap(blockIdx.x, G);
@@ -23,12 +23,12 @@ __global__ void __launch_bounds__(kBlock) k_life_tile(TileArgs A, const uint8_t 
 }
 
 template <class Pat, int K>
-__global__ void __launch_bounds__(kBlock) k_life_tileK(TileArgs A, const uint8_t *__restrict__ in,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) k_life_tileK(TileArgs A, const uint8_t *__restrict__ in,
                                                        uint8_t *__restrict__ out)
 {
     using LDS = TileLds<Pat>;
-    __shared__ uint32_t s_buf[3][LDS::IN_WORDS];
-    __shared__ uint32_t s_ex[kMaxSteps + 1];  // ring cells present (their tile exists)
+    __shared__ uint32_t s_buf[3][LDS::WORDS];
+    __shared__ uint32_t s_ex[2];  // ring cells present (their tile exists)
     uint32_t *const buf[3] = {s_buf[0], s_buf[1], s_buf[2]};
     const uint32_t G = gridDim.x;
     for (uint64_t round = 0; round * G < A.ntiles; ++round) {
@@ -82,10 +82,8 @@ sqz_status prepare(FractalHost &F)
     const int M = T->M;
     T->tile = (uint32_t)cpow(Pat::K, M);
     T->nblocks = (uint32_t)cpow(Pat::K, M - J);
-    T->halo_word = TileLds<Pat>::HALO_WORD;
-    T->hstride = (uint32_t)((PL.nhalo + 3) / 4 * 4);
-    if (T->hstride == 0) T->hstride = 4;
-    const int64_t side = cpow(Pat::S, M);
+    using LDS = TileLds<Pat>;
+    const int64_t side = cpow(Pat::S, M), box = PL.box;
 
     // tile halo slots: cells of adjacent tiles that touch a cell of this tile
     struct Slot {
@@ -113,8 +111,6 @@ sqz_status prepare(FractalHost &F)
         return set_error(SQZ_ERR_UNSUPPORTED, "tile halo of %zu cells exceeds %d", slots.size(), kMaxTileHalo);
     }
     T->nthalo = (uint32_t)slots.size();
-    // table entry codes: a bit position relative to the tile's first bit (< 2^20), or
-    const uint32_t kSlot = 1u << 20, kZero = 1u << 21, kRing = 1u << 22;  // ring-1 slot, zero, ring slot
 
     // rings 2..kMaxSteps (several steps per launch): breadth-first from ring 1
     // over member cells outside the tile (ring d = graph distance d from the
@@ -151,80 +147,80 @@ sqz_status prepare(FractalHost &F)
     T->tstride = T->ring_start[ksteps];
     T->nsrc = ksteps >= 2 ? T->ring_start[ksteps - 1] : 0;
     ring.resize(T->tstride);
+
+    // adjacent blocks of other tiles that hold ring-1 cells (one LDS word each)
+    auto floor_div = [](int64_t a, int64_t b) { return a >= 0 ? a / b : -((-a + b - 1) / b); };
+    std::vector<std::pair<int64_t, int64_t>> vblk;
+    auto virt_of = [&](int64_t bx, int64_t by) {
+        for (size_t g = 0; g < vblk.size(); ++g)
+            if (vblk[g].first == bx && vblk[g].second == by) return (int64_t)g;
+        return (int64_t)-1;
+    };
+    for (const Slot &s : slots) {
+        const int64_t bx = floor_div(s.px, box), by = floor_div(s.py, box);
+        if (virt_of(bx, by) < 0) vblk.emplace_back(bx, by);
+    }
+    // LDS entry (byte offset of the word << 16 | bit) of a tile cell and of ring cell i
+    auto entry = [](uint32_t word, uint32_t bit) { return (4u * word) << 16 | bit; };
+    const uint32_t zero_entry = entry(LDS::ZERO, 0);
+    auto tile_entry = [&](int64_t j) { return entry((uint32_t)(j / PL.nc), (uint32_t)(j % PL.nc)); };
+    auto ring_entry = [&](size_t i) {
+        uint32_t d = 1;
+        while ((uint32_t)i >= T->ring_start[d]) ++d;
+        if (d == 1) {
+            const Slot &s = ring[i];
+            const int64_t g = virt_of(floor_div(s.px, box), floor_div(s.py, box));
+            return entry(LDS::VIRT + (uint32_t)g, (uint32_t)(s.idx % PL.nc));
+        }
+        return entry(LDS::RING2 + d - 2, (uint32_t)i - T->ring_start[d - 1]);
+    };
+    std::vector<uint32_t> home(T->tstride ? T->tstride : 1, zero_entry);
+    for (uint32_t i = 0; i < T->tstride; ++i) home[i] = ring_entry(i);
     // LDS sources of the neighbours of every ring cell that is advanced
-    std::vector<uint32_t> rsrc((size_t)T->nsrc * 8, kZero);
+    std::vector<uint32_t> rsrc(T->nsrc ? (size_t)T->nsrc * 8 : 1, zero_entry);
     for (uint32_t c = 0; c < T->nsrc; ++c) {
         int n = 0;
         for (int dy = -1; dy <= 1; ++dy)
             for (int dx = -1; dx <= 1; ++dx) {
                 if (!dx && !dy) continue;
                 const int64_t qx = ring[c].px + dx, qy = ring[c].py + dy;
-                uint32_t e = kZero;
+                uint32_t e = zero_entry;
                 if (qx >= 0 && qy >= 0 && qx < side && qy < side) {
                     const int64_t j = host_nu(F, M, qx, qy);
-                    if (j >= 0) e = (uint32_t)j;
+                    if (j >= 0) e = tile_entry(j);
                 } else {
                     int tdx, tdy;
                     if (outside_member(qx, qy, tdx, tdy) >= 0) {
                         const int64_t i = find(qx, qy);  // always a loaded ring cell: ring d-1, d or d+1
-                        if (i >= 0 && i < (int64_t)T->tstride) {
-                            uint32_t d = 1;
-                            while ((uint32_t)i >= T->ring_start[d]) ++d;
-                            e = kRing + ((d << 5) | (uint32_t)(i - T->ring_start[d - 1]));
-                        }
+                        if (i >= 0 && i < (int64_t)T->tstride) e = ring_entry((size_t)i);
                     }
                 }
                 rsrc[(size_t)c * 8 + n++] = e;
             }
     }
 
-    // block halo table: for block b and halo slot h, the source cell's bit
-    // position relative to the tile's first bit (< 2^20), a tile-halo slot, or
-    // nothing.  Expanded below into LDS (word address << 16 | bit) entries for
-    // each of the 32 possible alignments o of a tile's first bit.
-    std::vector<uint32_t> bh((size_t)T->nblocks * T->hstride, kZero);
+    // adjacent-block words of every block: a block of the tile, the word of
+    // an adjacent block of another tile, or a zero word (no such block)
+    const int NG = PL.ngrp, NP = (NG + 1) / 2;
+    T->nbstride = NP > 4 ? (uint32_t)((NP + 3) / 4 * 4) : 4u;
+    std::vector<uint32_t> nbt((size_t)T->nblocks * T->nbstride, 0);
     const int64_t bside = cpow(Pat::S, M - J);
     for (uint32_t b = 0; b < T->nblocks; ++b) {
         int64_t bx, by;
         host_lambda(F, M - J, b, bx, by);
-        for (int h = 0; h < PL.nhalo; ++h) {
-            const int64_t nbx = bx + PL.h_dx[h], nby = by + PL.h_dy[h];
-            uint32_t e = kZero;
+        for (int g = 0; g < NG; ++g) {
+            const int64_t nbx = bx + PL.g_dx[g], nby = by + PL.g_dy[g];
+            uint32_t w = LDS::ZERO;
             if (nbx >= 0 && nby >= 0 && nbx < bside && nby < bside) {
                 const int64_t nb = host_nu(F, M - J, nbx, nby);
-                if (nb >= 0) e = (uint32_t)(nb * PL.nc + PL.h_idx[h]);
+                if (nb >= 0) w = (uint32_t)nb;
             } else {
-                const int64_t px = nbx * PL.box + PL.lx[PL.h_idx[h]], py = nby * PL.box + PL.ly[PL.h_idx[h]];
-                for (size_t s = 0; s < slots.size(); ++s)
-                    if (slots[s].px == px && slots[s].py == py) e = kSlot + (uint32_t)s;
+                const int64_t v = virt_of(nbx, nby);
+                if (v >= 0) w = LDS::VIRT + (uint32_t)v;
             }
-            bh[(size_t)b * T->hstride + h] = e;
+            nbt[(size_t)b * T->nbstride + g / 2] |= (4u * w) << (16 * (g & 1));
         }
     }
-    // (LDS byte address of the word << 16 | bit) for alignment o
-    auto lds_entry = [&](uint32_t e, uint32_t o) {
-        uint32_t word, bit;
-        if (e & kZero) {
-            word = T->halo_word + 1;
-            bit = 0;
-        } else if (e & kRing) {
-            word = ring_word(T->halo_word, (e - kRing) >> 5);
-            bit = (e - kRing) & 31;
-        } else if (e & kSlot) {
-            word = T->halo_word;
-            bit = e - kSlot;
-        } else {
-            word = (e + o) >> 5;
-            bit = (e + o) & 31;
-        }
-        return ((4 * word) << 16) | bit;
-    };
-    std::vector<uint32_t> bho((size_t)32 * bh.size());
-    for (uint32_t o = 0; o < 32; ++o)
-        for (size_t i = 0; i < bh.size(); ++i) bho[o * bh.size() + i] = lds_entry(bh[i], o);
-    std::vector<uint32_t> rso(rsrc.size() ? (size_t)32 * rsrc.size() : 1, 0);
-    for (uint32_t o = 0; o < 32; ++o)
-        for (size_t i = 0; i < rsrc.size(); ++i) rso[o * rsrc.size() + i] = lds_entry(rsrc[i], o);
 
     // coarse maps and per-tile halo indices
     sqz_status st = build_map_params(F, F.r - M, T->Pc, &T->d_coarse_tables);
@@ -233,16 +229,20 @@ sqz_status prepare(FractalHost &F)
         return st;
     }
     T->ntiles = T->Pc.N;
-    T->d_block_halo = nullptr;
+    T->d_nbtab = nullptr;
     T->d_tile_halo = nullptr;
     T->d_ringsrc = nullptr;
+    T->d_ringhome = nullptr;
     int4 *d_slots = nullptr;
     std::vector<int4> hs(T->tstride ? T->tstride : 1);
     for (size_t s = 0; s < T->tstride; ++s) hs[s] = make_int4(ring[s].dx, ring[s].dy, (int)ring[s].idx, 0);
-    hipError_t e = hipMalloc(&T->d_block_halo, bho.size() * sizeof(uint32_t));
-    if (e == hipSuccess) e = hipMemcpy(T->d_block_halo, bho.data(), bho.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMalloc(&T->d_ringsrc, rso.size() * sizeof(uint32_t));
-    if (e == hipSuccess) e = hipMemcpy(T->d_ringsrc, rso.data(), rso.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+    auto upload = [](uint32_t **d, const std::vector<uint32_t> &h) {
+        hipError_t e = hipMalloc(d, h.size() * sizeof(uint32_t));
+        return e == hipSuccess ? hipMemcpy(*d, h.data(), h.size() * sizeof(uint32_t), hipMemcpyHostToDevice) : e;
+    };
+    hipError_t e = upload(&T->d_nbtab, nbt);
+    if (e == hipSuccess) e = upload(&T->d_ringsrc, rsrc);
+    if (e == hipSuccess) e = upload(&T->d_ringhome, home);
     if (e == hipSuccess)
         e = hipMalloc(&T->d_tile_halo, (size_t)T->ntiles * (T->tstride ? T->tstride : 1) * sizeof(uint64_t));
     if (e == hipSuccess) e = hipMalloc(&d_slots, hs.size() * sizeof(int4));
@@ -257,9 +257,10 @@ sqz_status prepare(FractalHost &F)
     }
     if (d_slots) (void)hipFree(d_slots);
     if (e != hipSuccess) {
-        if (T->d_block_halo) (void)hipFree(T->d_block_halo);
+        if (T->d_nbtab) (void)hipFree(T->d_nbtab);
         if (T->d_tile_halo) (void)hipFree(T->d_tile_halo);
         if (T->d_ringsrc) (void)hipFree(T->d_ringsrc);
+        if (T->d_ringhome) (void)hipFree(T->d_ringhome);
         (void)hipFree(T->d_coarse_tables);
         delete T;
         return hip_error(e, "tile table setup");
@@ -314,9 +315,10 @@ sqz_status tile_prepare(FractalHost &F)
 void tile_release(FractalHost &F)
 {
     if (!F.tile) return;
-    (void)hipFree(F.tile->d_block_halo);
+    (void)hipFree(F.tile->d_nbtab);
     (void)hipFree(F.tile->d_tile_halo);
     (void)hipFree(F.tile->d_ringsrc);
+    (void)hipFree(F.tile->d_ringhome);
     (void)hipFree(F.tile->d_coarse_tables);
     delete F.tile;
     F.tile = nullptr;

@@ -10,21 +10,21 @@
 //           (bit i = state of the block's cell i).  One lane per block.
 // Inside a tile nothing is mapped per cell: the neighbours of a block's cells
 // are either cells of the same block -- a fixed set of (bit shift, bit mask)
-// moves derived from the replica pattern at compile time -- or one of a fixed
-// set of "block halo" cells of the adjacent blocks, found through a table that
-// is the same for every tile (the micro brute force the paper applies inside a
-// block).  Neighbour counts are summed with bit-sliced full adders over up to
-// eight single-bit layers, then B3/S23 is applied to all cells of the block
-// with a few logic operations.
+// moves derived from the replica pattern at compile time -- or fixed cells
+// ("block halo") of a few adjacent blocks, whose words are found through a
+// table that is the same for every tile (the micro brute force the paper
+// applies inside a block).  Neighbour counts are summed with bit-sliced full
+// adders over up to eight single-bit layers, then B3/S23 is applied to all
+// cells of the block with a few logic operations.
 //
 // Memory path per tile: coalesced 16-byte loads of the tile's bytes, packed to
 // bits in LDS (pack: a 4-byte dot product with byte weights 1,2,4,8 (then
-// 16..128) turns eight 0/1 bytes into one byte of bits); results are OR-ed into
-// an LDS bit array and written back with coalesced 16-byte stores (unpack:
-// (v * 0x204081) & 0x01010101 spreads four bits over four bytes).  Tile
-// boundaries are not 16-byte aligned: the two edge words of a tile are stored
-// byte by byte, one byte per lane, so neighbouring tiles never overwrite each
-// other.
+// 16..128) turns eight 0/1 bytes into one byte of bits), cut into one word
+// per block; results are joined back into 32-cell words and written with
+// coalesced 16-byte stores (unpack: (v * 0x204081) & 0x01010101 spreads four
+// bits over four bytes).  Tile boundaries are not 16-byte aligned: the two
+// edge words of a tile are stored byte by byte, one byte per lane, so
+// neighbouring tiles never overwrite each other.
 #pragma once
 
 #include <utility>
@@ -95,6 +95,9 @@ struct BlockPlan {
     int h_dx[kMaxHalo], h_dy[kMaxHalo], h_idx[kMaxHalo];
     int nhterm;                      // L[layer] |= halo_bit[slot] << bit
     int ht_layer[64], ht_slot[64], ht_bit[64];
+    int ngrp;                        // distinct adjacent blocks holding halo cells
+    int g_dx[8], g_dy[8];
+    int h_grp[kMaxHalo];             // adjacent block of each halo cell
     bool ok;
 };
 
@@ -200,6 +203,17 @@ constexpr BlockPlan derive_plan()
         }
         if (nused > p.nlayer) p.nlayer = nused;
     }
+    for (int h = 0; h < p.nhalo; ++h) {
+        int g = -1;
+        for (int q = 0; q < p.ngrp; ++q)
+            if (p.g_dx[q] == p.h_dx[h] && p.g_dy[q] == p.h_dy[h]) g = q;
+        if (g < 0) {
+            g = p.ngrp++;
+            p.g_dx[g] = p.h_dx[h];
+            p.g_dy[g] = p.h_dy[h];
+        }
+        p.h_grp[h] = g;
+    }
     return p;
 }
 
@@ -221,23 +235,24 @@ struct TileConfig {
     uint32_t ring_start[kMaxSteps + 1];  // slots of ring d are [ring_start[d-1], ring_start[d])
     uint32_t nsrc;         // ring cells whose next states are computed: ring_start[ksteps - 1]
     uint32_t tstride;      // per-tile entries of d_tile_halo: ring_start[ksteps]
-    uint32_t hstride;      // u32 entries per block in the block-halo table (multiple of 4)
-    uint32_t halo_word;    // LDS word index of the ring-1 bits (the next word is all zero)
+    uint32_t nbstride;     // u32 entries per block in d_nbtab (multiple of 4)
     uint64_t ntiles;       // K^(r-M)
-    uint32_t *d_block_halo;  // [32 alignments][nblocks][hstride]
-    uint64_t *d_tile_halo;   // [ntiles][tstride] global indices of the ring cells
-    uint32_t *d_ringsrc;     // [32 alignments][nsrc][8] LDS sources of each ring cell's neighbours
+    uint32_t *d_nbtab;     // [nblocks][nbstride] LDS byte offsets (16-bit pairs) of each block's adjacent-block words
+    uint64_t *d_tile_halo; // [ntiles][tstride] global indices of the ring cells
+    uint32_t *d_ringsrc;   // [nsrc][8] LDS sources of each advanced ring cell's neighbours
+    uint32_t *d_ringhome;  // [tstride] LDS word and bit of each ring cell
     MapParams Pc;          // maps at the coarse level r-M
     void *d_coarse_tables;
 };
 
 struct TileArgs {
     uint64_t ntiles, N;
-    uint32_t tile, nblocks, nthalo, tstride, nsrc, hstride, halo_word;
+    uint32_t tile, nblocks, nthalo, tstride, nsrc, nbstride;
     uint32_t ring_start[kMaxSteps + 1];
-    const uint32_t *block_halo;
+    const uint32_t *nbtab;
     const uint64_t *tile_halo;
     const uint32_t *ringsrc;
+    const uint32_t *ringhome;
 };
 
 inline TileArgs tile_args(const FractalHost &F)
@@ -251,29 +266,53 @@ inline TileArgs tile_args(const FractalHost &F)
     A.nthalo = T->nthalo;
     A.tstride = T->tstride;
     A.nsrc = T->nsrc;
+    A.nbstride = T->nbstride;
     for (int d = 0; d <= kMaxSteps; ++d) A.ring_start[d] = T->ring_start[d];
-    A.hstride = T->hstride;
-    A.halo_word = T->halo_word;
-    A.block_halo = T->d_block_halo;
+    A.nbtab = T->d_nbtab;
     A.tile_halo = T->d_tile_halo;
     A.ringsrc = T->d_ringsrc;
+    A.ringhome = T->d_ringhome;
     return A;
 }
 
-// LDS words of one tile's state: o + tile bits, then from HALO_WORD the
-// ring-1 bits, a zero word, and the bits of rings 2..kMaxSteps (ring d at
-// HALO_WORD + d).  Ring d holds the cells of other tiles at graph distance d
-// from the tile (each neighbour of a ring-d cell is in ring d-1, d or d+1,
-// or in the tile for d = 1).
+// LDS words of one tile's state, one word per level-J block (bit i = cell i
+// of the block, bits from K^J up zero): blocks [0, NBMAX), two words that
+// stay zero (absent neighbours), one word per adjacent block of another tile
+// that holds ring-1 cells (each at its bit within that block), then the bits
+// of rings 2..kMaxSteps, one word per ring.  Ring d holds the cells of other
+// tiles at graph distance d from the tile (each neighbour of a ring-d cell is
+// in ring d-1, d or d+1, or in the tile for d = 1).  The layout does not
+// depend on where the tile starts within a 32-byte word, so every table that
+// addresses it is the same for all tiles.  The tile's bytes are first packed
+// to bits at their 32-byte alignment in the low words of another buffer
+// (STAGE words) and then cut into block words.
 template <class Pat>
 struct TileLds {
+    static constexpr int NC = PlanOf<Pat>::value.nc;
     static constexpr int TMAX = cpow(Pat::K, Pat::MMAX);
-    static constexpr int WMAX = (TMAX + 31 + 31) / 32;  // words covering o + tile bits
-    static constexpr int HALO_WORD = WMAX + 1;
-    static constexpr int IN_WORDS = HALO_WORD + kMaxSteps + 1;
+    static constexpr int NBMAX = TMAX / NC;
+    static constexpr int ZERO = NBMAX;
+    static constexpr int VIRT = ZERO + 2;
+    static constexpr int RING2 = VIRT + kMaxTileHalo;
+    static constexpr int WORDS = RING2 + kMaxSteps - 1;
+    static constexpr int STAGE = (TMAX + 31 + 31) / 32 + 1;
+    static constexpr int NSLOT = (NBMAX + kBlock - 1) / kBlock;  // blocks per lane
+    static constexpr int NGRP = PlanOf<Pat>::value.ngrp > 0 ? PlanOf<Pat>::value.ngrp : 1;
+    static_assert(STAGE <= NBMAX, "packed tile overlaps the special words");
+    static_assert(NC > 16, "a 32-bit word must span at most three blocks");
+    static_assert(WORDS - ZERO <= kBlock, "special words are cleared by one pass of the workgroup");
 };
 
-__host__ __device__ constexpr uint32_t ring_word(uint32_t hw, uint32_t d) { return hw + (d == 1 ? 0u : d); }
+// LDS entry: byte offset of a word within a buffer << 16 | bit.
+__device__ __forceinline__ uint32_t lds_bit(const uint32_t *base, uint32_t e)
+{
+    return __builtin_amdgcn_ubfe(*reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(base) + (e >> 16)),
+                                 e, 1);
+}
+__device__ __forceinline__ uint32_t *lds_word(uint32_t *base, uint32_t e)
+{
+    return reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(base) + (e >> 16));
+}
 
 // Bit 0 of eight bytes (two words) -> one byte of bits, via 4-byte dot products.
 __device__ __forceinline__ uint32_t pack8(uint32_t d0, uint32_t d1)
@@ -319,17 +358,21 @@ __device__ __forceinline__ void apply_moves(uint32_t x, uint32_t (&L)[NL], std::
     (move_term<PL.t_layer[I], PL.t_shift[I], PL.t_mask[I], NL>(x, L), ...);
 }
 
-template <int Layer, int Slot, int Bit, int NL, int NH>
-__device__ __forceinline__ void halo_term(const uint32_t (&hb)[NH], uint32_t (&L)[NL])
+// Halo cell `Src` of an adjacent block's word -> bit `Bit` of layer `Layer`.
+template <int Layer, int Grp, int Src, int Bit, int NL, int NG>
+__device__ __forceinline__ void halo_term(const uint32_t (&w)[NG], uint32_t (&L)[NL])
 {
-    L[Layer] |= hb[Slot] << Bit;
+    if constexpr (Bit >= Src)
+        L[Layer] |= (w[Grp] << (Bit - Src)) & (1u << Bit);
+    else
+        L[Layer] |= (w[Grp] >> (Src - Bit)) & (1u << Bit);
 }
 
-template <class Pat, int NL, int NH, size_t... I>
-__device__ __forceinline__ void apply_halo(const uint32_t (&hb)[NH], uint32_t (&L)[NL], std::index_sequence<I...>)
+template <class Pat, int NL, int NG, size_t... I>
+__device__ __forceinline__ void apply_halo(const uint32_t (&w)[NG], uint32_t (&L)[NL], std::index_sequence<I...>)
 {
     constexpr const BlockPlan &PL = PlanOf<Pat>::value;
-    (halo_term<PL.ht_layer[I], PL.ht_slot[I], PL.ht_bit[I], NL, NH>(hb, L), ...);
+    (halo_term<PL.ht_layer[I], PL.h_grp[PL.ht_slot[I]], PL.h_idx[PL.ht_slot[I]], PL.ht_bit[I], NL, NG>(w, L), ...);
 }
 
 // B3/S23 on all cells of a block: alive' = (count == 3) | (alive & count == 2).
@@ -366,58 +409,129 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t G)
     return xcd < rem ? xcd * (q + 1) + pos : rem * (q + 1) + (xcd - rem) * q + pos;
 }
 
-// Phase C: one lane per level-J block.  Reads the tile's bits and halo words
-// from `src`, ORs the new states into `dst` (zeroed beforehand).
+// LDS byte offsets of the adjacent-block words of this lane's blocks
+// (blocks threadIdx.x + s * kBlock), two 16-bit offsets per register; the
+// table is the same for every tile, so it is read once per tile and kept in
+// registers for all steps.
 template <class Pat>
-__device__ __forceinline__ void tile_blocks(const TileArgs &A, uint32_t o, const uint32_t *bh_o, const uint32_t *src,
-                                            uint32_t *dst)
+struct NbRegs {
+    static constexpr int NP = (TileLds<Pat>::NGRP + 1) / 2;
+    uint32_t a[TileLds<Pat>::NSLOT][NP];
+    __device__ __forceinline__ uint32_t at(int s, int g) const { return g & 1 ? a[s][g >> 1] >> 16 : a[s][g >> 1] & 0xFFFFu; }
+    // Keeps the compiler from unpacking the offsets once for all steps,
+    // which would double the registers they take.
+    __device__ __forceinline__ void keep_packed()
+    {
+#pragma unroll
+        for (int s = 0; s < TileLds<Pat>::NSLOT; ++s)
+#pragma unroll
+            for (int p = 0; p < NP; ++p) asm volatile("" : "+v"(a[s][p]));
+    }
+};
+
+template <class Pat>
+__device__ __forceinline__ void load_nb(const TileArgs &A, NbRegs<Pat> &R)
 {
+    using LDS = TileLds<Pat>;
+    constexpr int NP = NbRegs<Pat>::NP;
+#pragma unroll
+    for (int s = 0; s < LDS::NSLOT; ++s) {
+        const uint32_t b = threadIdx.x + s * kBlock;
+        const uint32_t *e = A.nbtab + (size_t)(b < A.nblocks ? b : 0u) * A.nbstride;
+#pragma unroll
+        for (int g0 = 0; g0 < NP; g0 += 4) {
+            const uint4 q = *reinterpret_cast<const uint4 *>(e + g0);
+            const uint32_t qq[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+            for (int g = g0; g < NP && g < g0 + 4; ++g) R.a[s][g] = qq[g - g0];
+        }
+    }
+}
+
+// Phase C: one lane per level-J block.  Reads the block's word and the words
+// of its adjacent blocks from `src`, writes the block's new word to `dst`.
+template <class Pat>
+__device__ __forceinline__ void tile_blocks(const TileArgs &A, NbRegs<Pat> &R, const uint32_t *src, uint32_t *dst)
+{
+    R.keep_packed();
+    using LDS = TileLds<Pat>;
     constexpr const BlockPlan &PL = PlanOf<Pat>::value;
     constexpr int NC = PL.nc;
     constexpr uint32_t CELLS = NC == 32 ? 0xFFFFFFFFu : ((1u << NC) - 1u);
     constexpr int NL = PL.nlayer;
-    constexpr int NH = PL.nhalo;
-    for (uint32_t b = threadIdx.x; b < A.nblocks; b += kBlock) {
-        const uint32_t pos = o + b * NC;
-        const uint32_t lo = src[pos >> 5], hi = src[(pos >> 5) + 1];
-        const uint32_t x = __builtin_amdgcn_alignbit(hi, lo, pos) & CELLS;  // shift = pos mod 32
-        uint32_t hb[NH > 0 ? NH : 1] = {};
-        const uint32_t *he = bh_o + (size_t)b * A.hstride;
+    constexpr int NG = LDS::NGRP;
 #pragma unroll
-        for (int h0 = 0; h0 < NH; h0 += 4) {
-            const uint4 q = *reinterpret_cast<const uint4 *>(he + h0);
-            const uint32_t qq[4] = {q.x, q.y, q.z, q.w};
+    for (int s = 0; s < LDS::NSLOT; ++s) {
+        const uint32_t b = threadIdx.x + s * kBlock;
+        if (b < A.nblocks) {
+            const uint32_t x = src[b];
+            uint32_t w[NG];
 #pragma unroll
-            for (int h = h0; h < NH && h < h0 + 4; ++h) {
-                // entry: LDS byte address of the word << 16 | bit within the word
-                const uint32_t e = qq[h - h0];
-                const uint32_t word = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(src) + (e >> 16));
-                hb[h] = __builtin_amdgcn_ubfe(word, e, 1);
-            }
+            for (int g = 0; g < NG; ++g)
+                w[g] = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(src) + R.at(s, g));
+            uint32_t L[NL];
+#pragma unroll
+            for (int l = 0; l < NL; ++l) L[l] = 0;
+            apply_moves<Pat, NL>(x, L, std::make_index_sequence<PL.nterm>{});
+            apply_halo<Pat, NL, NG>(w, L, std::make_index_sequence<PL.nhterm>{});
+            dst[b] = life_rule<NL>(x, L) & CELLS;
         }
-        uint32_t L[NL];
-#pragma unroll
-        for (int l = 0; l < NL; ++l) L[l] = 0;
-        apply_moves<Pat, NL>(x, L, std::make_index_sequence<PL.nterm>{});
-        apply_halo<Pat, NL, (NH > 0 ? NH : 1)>(hb, L, std::make_index_sequence<PL.nhterm>{});
-        const uint32_t res = life_rule<NL>(x, L) & CELLS;
-        const uint64_t sh = (uint64_t)res << (pos & 31);
-        atomicOr(&dst[pos >> 5], (uint32_t)sh);
-        atomicOr(&dst[(pos >> 5) + 1], (uint32_t)(sh >> 32));
     }
 }
 
-// Phase D: unpack the bits in `src` and store whole words; the (at most two)
-// edge words of the tile go out byte by byte, one byte per lane of wave 0.
-__device__ __forceinline__ void tile_store(const TileArgs &A, uint8_t *__restrict__ out, uint64_t A0, uint32_t o,
-                                           uint32_t W, const uint32_t *src)
+// Phase A: load and pack the tile (plus the bytes of its first and last
+// 32-byte words that belong to the neighbouring tiles) into stg: bit i of
+// word w = byte A0 + 32 w + i.
+__device__ __forceinline__ void tile_pack(const TileArgs &A, const uint8_t *__restrict__ in, uint64_t A0, uint32_t W,
+                                          uint32_t *stg)
 {
+    for (uint32_t w = threadIdx.x; w < W; w += kBlock) {
+        const uint64_t g = A0 + 32ull * w;
+        uint32_t bits = 0;
+        if (g + 32 <= A.N) {
+            const uint4 a = load16(in + g);
+            const uint4 b = load16(in + g + 16);
+            bits = pack8(a.x, a.y) | pack8(a.z, a.w) << 8 | pack8(b.x, b.y) << 16 | pack8(b.z, b.w) << 24;
+        } else {
+            for (uint32_t i = 0; i < 32; ++i)
+                if (g + i < A.N) bits |= (uint32_t)(in[g + i] & 1u) << i;
+        }
+        stg[w] = bits;
+    }
+}
+
+// Phase A, second half: cut the packed bits (the tile starts at bit o of
+// word 0) into block words.  Word W of stg (never written) only feeds bits
+// that the mask drops.
+template <class Pat>
+__device__ __forceinline__ void tile_convert(const TileArgs &A, uint32_t o, const uint32_t *stg, uint32_t *blk)
+{
+    constexpr int NC = PlanOf<Pat>::value.nc;
+    constexpr uint32_t CELLS = NC == 32 ? 0xFFFFFFFFu : ((1u << NC) - 1u);
+    for (uint32_t b = threadIdx.x; b < A.nblocks; b += kBlock) {
+        const uint32_t pos = o + b * NC;
+        blk[b] = __builtin_amdgcn_alignbit(stg[(pos >> 5) + 1], stg[pos >> 5], pos) & CELLS;
+    }
+}
+
+// Phase D: join block words back into 32-cell words, unpack and store whole
+// 32-byte words; the (at most two) edge words of the tile go out byte by
+// byte, one byte per lane of wave 0.  A whole word reads at most the blocks
+// b0 .. b0+2 <= nblocks + 1; bits of blocks past the tile fall beyond bit 31.
+template <class Pat>
+__device__ __forceinline__ void tile_store(const TileArgs &A, uint8_t *__restrict__ out, uint64_t A0, uint32_t o,
+                                           uint32_t W, const uint32_t *blk)
+{
+    constexpr uint32_t NC = PlanOf<Pat>::value.nc;
     const uint32_t tid = threadIdx.x, last = W - 1;
     const bool first_partial = o != 0, last_partial = ((o + A.tile) & 31) != 0;
     for (uint32_t w = tid; w < W; w += kBlock) {
-        const uint32_t v = src[w];
-        const uint64_t g = A0 + 32ull * w;
         if (!((w == 0 && first_partial) || (w == last && last_partial))) {
+            const uint32_t p0 = 32 * w - o;  // w > 0 or o == 0 here
+            const uint32_t b0 = p0 / NC, r0 = p0 - b0 * NC;
+            uint32_t v = (blk[b0] >> r0) | (blk[b0 + 1] << (NC - r0));
+            if (2 * NC - r0 < 32) v |= blk[b0 + 2] << (2 * NC - r0);
+            const uint64_t g = A0 + 32ull * w;
             uint4 a, b;
             a.x = spread4(v & 15);
             a.y = spread4((v >> 4) & 15);
@@ -434,62 +548,48 @@ __device__ __forceinline__ void tile_store(const TileArgs &A, uint8_t *__restric
     if (tid < 64) {
         const uint32_t w = tid < 32 ? 0u : last, i = tid & 31u, lp = 32 * w + i;
         const bool mine = tid < 32 ? first_partial : (last_partial && (last != 0 || !first_partial));
-        if (mine && lp >= o && lp < o + A.tile) out[A0 + lp] = (uint8_t)((src[w] >> i) & 1u);
-    }
-}
-
-// Phase A: load and pack the tile (plus the bytes of its first and last
-// 32-byte words that belong to the neighbouring tiles) into s_in.
-__device__ __forceinline__ void tile_pack(const TileArgs &A, const uint8_t *__restrict__ in, uint64_t A0, uint32_t W,
-                                          uint32_t *s_in)
-{
-    for (uint32_t w = threadIdx.x; w < W; w += kBlock) {
-        const uint64_t g = A0 + 32ull * w;
-        uint32_t bits = 0;
-        if (g + 32 <= A.N) {
-            const uint4 a = load16(in + g);
-            const uint4 b = load16(in + g + 16);
-            bits = pack8(a.x, a.y) | pack8(a.z, a.w) << 8 | pack8(b.x, b.y) << 16 | pack8(b.z, b.w) << 24;
-        } else {
-            for (uint32_t i = 0; i < 32; ++i)
-                if (g + i < A.N) bits |= (uint32_t)(in[g + i] & 1u) << i;
+        if (mine && lp >= o && lp < o + A.tile) {
+            const uint32_t q = lp - o;
+            out[A0 + lp] = (uint8_t)((blk[q / NC] >> (q % NC)) & 1u);
         }
-        s_in[w] = bits;
     }
 }
 
-// One tile, one step (phases A to D).  s_in / s_out: TileLds<Pat>::IN_WORDS
-// and WMAX + 1 words of LDS.  Called by every lane of the workgroup.
+// One tile, one step.  s_in / s_out: TileLds<Pat>::WORDS words of LDS each
+// (s_out first holds the packed bytes).  Called by every lane of the workgroup.
 template <class Pat>
 __device__ __forceinline__ void tile_body(const TileArgs &A, const uint8_t *__restrict__ in, uint8_t *__restrict__ out,
                                           uint64_t t, uint32_t *s_in, uint32_t *s_out)
 {
+    using LDS = TileLds<Pat>;
     const uint32_t tid = threadIdx.x;
     const uint64_t S0 = t * A.tile;  // first byte of the tile
     const uint64_t A0 = S0 & ~31ull;
     const uint32_t o = (uint32_t)(S0 - A0);
     const uint32_t W = (o + A.tile + 31) / 32;
-    const uint32_t *bh_o = A.block_halo + (size_t)o * A.nblocks * A.hstride;
 
-    // Phase B, first half: the global indices of the tile's halo cells are
+    // Phase B, first half: the global indices of the ring-1 cells are
     // requested before the tile's own bytes so the two latencies overlap.
     uint64_t gi = kHole64;
-    if (tid < A.nthalo) gi = A.tile_halo[t * A.tstride + tid];
-    tile_pack(A, in, A0, W, s_in);
-    for (uint32_t w = tid; w <= W; w += kBlock) s_out[w] = 0;
-    // Phase B, second half: the halo cells themselves, gathered by ballot.
-    if (tid < 64) {
-        const uint32_t v = gi != kHole64 ? (in[gi] & 1u) : 0u;
-        const uint64_t m = __ballot(v);
-        if (tid == 0) {
-            s_in[A.halo_word] = (uint32_t)m;
-            s_in[A.halo_word + 1] = 0u;
-        }
+    uint32_t home = 0;
+    if (tid < A.nthalo) {
+        gi = A.tile_halo[t * A.tstride + tid];
+        home = A.ringhome[tid];
     }
+    NbRegs<Pat> R;
+    load_nb<Pat>(A, R);
+    tile_pack(A, in, A0, W, s_out);
+    if (tid < LDS::WORDS - LDS::ZERO) s_in[LDS::ZERO + tid] = 0;
+    // Phase B, second half: the ring-1 cells themselves
+    uint32_t v = 0;
+    if (tid < 64) v = gi != kHole64 ? (in[gi] & 1u) : 0u;
     __syncthreads();
-    tile_blocks<Pat>(A, o, bh_o, s_in, s_out);
+    tile_convert<Pat>(A, o, s_out, s_in);
+    if (v) atomicOr(lds_word(s_in, home), 1u << (home & 31));
     __syncthreads();
-    tile_store(A, out, A0, o, W, s_out);
+    tile_blocks<Pat>(A, R, s_in, s_out);
+    __syncthreads();
+    tile_store<Pat>(A, out, A0, o, W, s_out);
     __syncthreads();  // LDS is reused by the next tile
 }
 
@@ -498,72 +598,75 @@ __device__ __forceinline__ void tile_body(const TileArgs &A, const uint8_t *__re
 // cells of rings 1..K-j are advanced together, each ring cell by eight lanes
 // that read its neighbours at t+j-1 (tile bits or ring bits, through the
 // tile-invariant source table), a ballot and a popcount.  Three LDS buffers
-// rotate: round j reads buf[(j-1)%3], writes buf[j%3] and clears buf[(j+1)%3].
+// rotate: round j reads buf[(j-1)%3], writes buf[j%3] and clears the ring
+// words of buf[(j+1)%3]; buf[2] first holds the packed bytes.  s_ex: two
+// words, bit c = ring slot c's tile exists.
 template <class Pat, int K>
 __device__ __forceinline__ void tile_bodyK(const TileArgs &A, const uint8_t *__restrict__ in,
                                            uint8_t *__restrict__ out, uint64_t t, uint32_t *const buf[3],
                                            uint32_t *s_ex)
 {
-    const uint32_t tid = threadIdx.x, HW = A.halo_word;
+    using LDS = TileLds<Pat>;
+    const uint32_t tid = threadIdx.x;
     const uint64_t S0 = t * A.tile;
     const uint64_t A0 = S0 & ~31ull;
     const uint32_t o = (uint32_t)(S0 - A0);
     const uint32_t W = (o + A.tile + 31) / 32;
-    const uint32_t *bh_o = A.block_halo + (size_t)o * A.nblocks * A.hstride;
 
     // ring slots (at most 64: wave 0)
     uint64_t gi = kHole64;
-    if (tid < A.tstride) gi = A.tile_halo[t * A.tstride + tid];
-    tile_pack(A, in, A0, W, buf[0]);
-    for (uint32_t w = tid; w <= W; w += kBlock) buf[1][w] = 0;
-    if (tid <= K) buf[1][HW + tid] = 0;
+    uint32_t home = 0;
+    if (tid < A.tstride) {
+        gi = A.tile_halo[t * A.tstride + tid];
+        home = A.ringhome[tid];
+    }
+    NbRegs<Pat> R;
+    load_nb<Pat>(A, R);
+    tile_pack(A, in, A0, W, buf[2]);
+    if (tid < LDS::WORDS - LDS::ZERO) {
+        buf[0][LDS::ZERO + tid] = 0;
+        buf[1][LDS::ZERO + tid] = 0;
+        buf[2][LDS::ZERO + tid] = 0;
+    }
+    uint32_t v = 0;
     if (tid < 64) {
-        const uint32_t v = gi != kHole64 ? (in[gi] & 1u) : 0u;
-        const uint64_t m = __ballot(v), x = __ballot(gi != kHole64);
+        v = gi != kHole64 ? (in[gi] & 1u) : 0u;
+        const uint64_t x = __ballot(gi != kHole64);
         if (tid == 0) {
-            buf[0][HW + 1] = 0u;
-#pragma unroll
-            for (int d = 1; d <= K; ++d) {
-                const uint32_t n = A.ring_start[d] - A.ring_start[d - 1];
-                const uint64_t mask = n >= 32 ? 0xFFFFFFFFull : ((1ull << n) - 1);
-                buf[0][ring_word(HW, d)] = (uint32_t)((m >> A.ring_start[d - 1]) & mask);
-                s_ex[d] = (uint32_t)((x >> A.ring_start[d - 1]) & mask);
-            }
+            s_ex[0] = (uint32_t)x;
+            s_ex[1] = (uint32_t)(x >> 32);
         }
     }
     __syncthreads();
+    tile_convert<Pat>(A, o, buf[2], buf[0]);
+    if (v) atomicOr(lds_word(buf[0], home), 1u << (home & 31));
+    __syncthreads();
+    const uint64_t present = (uint64_t)s_ex[1] << 32 | s_ex[0];
 #pragma unroll
     for (int j = 1; j <= K; ++j) {
         const uint32_t *src = buf[(j - 1) % 3];
         uint32_t *dst = buf[j % 3];
-        tile_blocks<Pat>(A, o, bh_o, src, dst);
+        tile_blocks<Pat>(A, R, src, dst);
         if (j < K) {
             uint32_t *clr = buf[(j + 1) % 3];
-            for (uint32_t w = tid; w <= W; w += kBlock) clr[w] = 0;
-            if (tid <= K) clr[HW + tid] = 0;
+            if (tid < LDS::WORDS - LDS::VIRT) clr[LDS::VIRT + tid] = 0;
             const uint32_t ncell = A.ring_start[K - j];
             for (uint32_t c0 = 0; c0 < ncell; c0 += kBlock / 8) {
                 const uint32_t c = c0 + (tid >> 3);
                 uint32_t bit = 0;
-                if (c < ncell) {
-                    const uint32_t e = A.ringsrc[((size_t)o * A.nsrc + c) * 8 + (tid & 7)];
-                    bit = __builtin_amdgcn_ubfe(
-                        *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(src) + (e >> 16)), e, 1);
-                }
+                if (c < ncell) bit = lds_bit(src, A.ringsrc[c * 8 + (tid & 7)]);
                 const uint64_t m = __ballot(bit);
                 if (c < ncell && (tid & 7) == 0) {
-                    uint32_t d = 1;
-                    while (c >= A.ring_start[d]) ++d;
-                    const uint32_t i = c - A.ring_start[d - 1];
+                    const uint32_t h = A.ringhome[c];
                     const uint32_t cnt = __builtin_popcountll((m >> (tid & 56)) & 0xFFull);
-                    const uint32_t self = (src[ring_word(HW, d)] >> i) & 1u, present = (s_ex[d] >> i) & 1u;
-                    if (present & ((cnt == 3) | (self & (cnt == 2)))) atomicOr(&dst[ring_word(HW, d)], 1u << i);
+                    const uint32_t self = lds_bit(src, h), here = (uint32_t)(present >> c) & 1u;
+                    if (here & ((cnt == 3) | (self & (cnt == 2)))) atomicOr(lds_word(dst, h), 1u << (h & 31));
                 }
             }
         }
         __syncthreads();
     }
-    tile_store(A, out, A0, o, W, buf[K % 3]);
+    tile_store<Pat>(A, out, A0, o, W, buf[K % 3]);
     __syncthreads();
 }
 
