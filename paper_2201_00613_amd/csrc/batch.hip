@@ -81,6 +81,13 @@ __device__ __forceinline__ void life_cell_unit(const MapParams &P, const uint8_t
     }
 }
 
+// LDS word offset of the ring tables in the multi-step layout (16-byte aligned)
+template <class Pat>
+__host__ __device__ constexpr int ring_tab_offset()
+{
+    return (3 * TileLds<Pat>::WORDS + 2 + 3) / 4 * 4;
+}
+
 template <class Pat, int K>
 __device__ __forceinline__ void bitsliced_unit(const BatchInst &I, const uint8_t *in, uint8_t *out, uint64_t t,
                                                unsigned char *smem)
@@ -91,7 +98,7 @@ __device__ __forceinline__ void bitsliced_unit(const BatchInst &I, const uint8_t
         tile_body<Pat>(I.tile, in, out, t, s_in, s_in + LDS::WORDS);
     } else {
         uint32_t *const buf[3] = {s_in, s_in + LDS::WORDS, s_in + 2 * LDS::WORDS};
-        tile_bodyK<Pat, K>(I.tile, in, out, t, buf, s_in + 3 * LDS::WORDS);
+        tile_bodyK<Pat, K>(I.tile, in, out, t, buf, s_in + 3 * LDS::WORDS, s_in + ring_tab_offset<Pat>());
     }
 }
 
@@ -237,7 +244,7 @@ static uint32_t kind_of(const FractalHost &F)
 template <class Pat>
 static size_t tile_lds(bool multi)
 {
-    return multi ? (size_t)(3 * TileLds<Pat>::WORDS + 2) * 4 : (size_t)(2 * TileLds<Pat>::WORDS) * 4;
+    return multi ? (size_t)(ring_tab_offset<Pat>() + kRingTab) * 4 : (size_t)(2 * TileLds<Pat>::WORDS) * 4;
 }
 
 static size_t tile_lds_of(const FractalHost &F, bool multi)

@@ -7,9 +7,14 @@
 
 namespace sqz {
 
-template <class Pat>
-__global__ void __launch_bounds__(kBlock) k_life_tile(TileArgs A, const uint8_t *__restrict__ in,
-                                                      uint8_t *__restrict__ out)
+#ifndef SQZ_TILE_NT  // lanes per workgroup of the compact tiled kernels
+#define SQZ_TILE_NT 256
+#endif
+constexpr int kTileNT = SQZ_TILE_NT;
+
+template <class Pat, int NT>
+__global__ void __launch_bounds__(NT) k_life_tile(TileArgs A, const uint8_t *__restrict__ in,
+                                                  uint8_t *__restrict__ out)
 {
     using LDS = TileLds<Pat>;
     __shared__ uint32_t s_in[LDS::WORDS];
@@ -18,23 +23,24 @@ __global__ void __launch_bounds__(kBlock) k_life_tile(TileArgs A, const uint8_t 
     for (uint64_t round = 0; round * G < A.ntiles; ++round) {
         const uint64_t t = round * G + xcd_remap(blockIdx.x, G);
         if (t >= A.ntiles) break;  // uniform across the workgroup
-        tile_body<Pat>(A, in, out, t, s_in, s_out);
+        tile_body<Pat, NT>(A, in, out, t, s_in, s_out);
     }
 }
 
-template <class Pat, int K>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) k_life_tileK(TileArgs A, const uint8_t *__restrict__ in,
-                                                       uint8_t *__restrict__ out)
+template <class Pat, int K, int NT>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 256 ? 8 : 7)))
+k_life_tileK(TileArgs A, const uint8_t *__restrict__ in, uint8_t *__restrict__ out)
 {
     using LDS = TileLds<Pat>;
     __shared__ uint32_t s_buf[3][LDS::WORDS];
     __shared__ uint32_t s_ex[2];  // ring cells present (their tile exists)
+    __shared__ __align__(16) uint32_t s_ring[kRingTab];
     uint32_t *const buf[3] = {s_buf[0], s_buf[1], s_buf[2]};
     const uint32_t G = gridDim.x;
     for (uint64_t round = 0; round * G < A.ntiles; ++round) {
         const uint64_t t = round * G + xcd_remap(blockIdx.x, G);
         if (t >= A.ntiles) break;  // uniform across the workgroup
-        tile_bodyK<Pat, K>(A, in, out, t, buf, s_ex);
+        tile_bodyK<Pat, K, NT>(A, in, out, t, buf, s_ex, s_ring);
     }
 }
 
@@ -139,7 +145,7 @@ sqz_status prepare(FractalHost &F)
                     if (j >= 0 && find(qx, qy) < 0) ring.push_back(Slot{tdx, tdy, j, qx, qy});
                 }
         start.push_back((uint32_t)ring.size());
-        if (T->nthalo == 0 || start[d] - start[d - 1] > 32 || start[d] > 64) break;
+        if (T->nthalo == 0 || start[d] - start[d - 1] > 32 || start[d] > (uint32_t)kMaxRing) break;
         ksteps = (uint32_t)d;  // rings 1..d fit: d steps per launch
     }
     T->ksteps = ksteps;
@@ -280,11 +286,12 @@ sqz_status launch(const FractalHost &F, const uint8_t *in, uint8_t *out, int ste
                          T->ksteps);
     const TileArgs A = tile_args(F);
     const uint64_t grid = T->ntiles < (1ull << 20) ? T->ntiles : (1ull << 20);
+    constexpr int NT = kTileNT;
     switch (steps) {
-    case 1: hipLaunchKernelGGL(k_life_tile<Pat>, dim3((unsigned)grid), dim3(kBlock), 0, st, A, in, out); break;
-    case 2: hipLaunchKernelGGL((k_life_tileK<Pat, 2>), dim3((unsigned)grid), dim3(kBlock), 0, st, A, in, out); break;
-    case 3: hipLaunchKernelGGL((k_life_tileK<Pat, 3>), dim3((unsigned)grid), dim3(kBlock), 0, st, A, in, out); break;
-    default: hipLaunchKernelGGL((k_life_tileK<Pat, 4>), dim3((unsigned)grid), dim3(kBlock), 0, st, A, in, out); break;
+    case 1: hipLaunchKernelGGL((k_life_tile<Pat, NT>), dim3((unsigned)grid), dim3(NT), 0, st, A, in, out); break;
+    case 2: hipLaunchKernelGGL((k_life_tileK<Pat, 2, NT>), dim3((unsigned)grid), dim3(NT), 0, st, A, in, out); break;
+    case 3: hipLaunchKernelGGL((k_life_tileK<Pat, 3, NT>), dim3((unsigned)grid), dim3(NT), 0, st, A, in, out); break;
+    default: hipLaunchKernelGGL((k_life_tileK<Pat, 4, NT>), dim3((unsigned)grid), dim3(NT), 0, st, A, in, out); break;
     }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? SQZ_OK : hip_error(e, "compact step (tile) launch");

@@ -79,6 +79,8 @@ constexpr int cpow(int b, int e)
 constexpr int kMaxHalo = 16;      // halo cells per block
 constexpr int kMaxSteps = 4;      // Life steps per launch of the multi-step tiled kernel
 constexpr int kMaxTileHalo = 32;  // halo cells per tile (one LDS word of bits)
+constexpr int kMaxRing = 64;      // ring cells of all rings (one wave)
+constexpr int kRingTab = kMaxRing * 9;  // LDS words of a tile's ring tables: 8 sources per cell, then homes
 constexpr int kBlock = 256;
 
 // ---------------------------------------------------------------------------
@@ -296,11 +298,9 @@ struct TileLds {
     static constexpr int RING2 = VIRT + kMaxTileHalo;
     static constexpr int WORDS = RING2 + kMaxSteps - 1;
     static constexpr int STAGE = (TMAX + 31 + 31) / 32 + 1;
-    static constexpr int NSLOT = (NBMAX + kBlock - 1) / kBlock;  // blocks per lane
     static constexpr int NGRP = PlanOf<Pat>::value.ngrp > 0 ? PlanOf<Pat>::value.ngrp : 1;
     static_assert(STAGE <= NBMAX, "packed tile overlaps the special words");
     static_assert(NC > 16, "a 32-bit word must span at most three blocks");
-    static_assert(WORDS - ZERO <= kBlock, "special words are cleared by one pass of the workgroup");
 };
 
 // LDS entry: byte offset of a word within a buffer << 16 | bit.
@@ -410,33 +410,35 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t G)
 }
 
 // LDS byte offsets of the adjacent-block words of this lane's blocks
-// (blocks threadIdx.x + s * kBlock), two 16-bit offsets per register; the
+// (blocks threadIdx.x + s * NT), two 16-bit offsets per register; the
 // table is the same for every tile, so it is read once per tile and kept in
 // registers for all steps.
-template <class Pat>
+template <class Pat, int NT>
 struct NbRegs {
+    static constexpr int NSLOT = (TileLds<Pat>::NBMAX + NT - 1) / NT;  // blocks per lane
     static constexpr int NP = (TileLds<Pat>::NGRP + 1) / 2;
-    uint32_t a[TileLds<Pat>::NSLOT][NP];
+    static_assert(NT % 64 == 0 && TileLds<Pat>::WORDS - TileLds<Pat>::ZERO <= NT,
+                  "whole waves; special words are cleared by one pass of the workgroup");
+    uint32_t a[NSLOT][NP];
     __device__ __forceinline__ uint32_t at(int s, int g) const { return g & 1 ? a[s][g >> 1] >> 16 : a[s][g >> 1] & 0xFFFFu; }
     // Keeps the compiler from unpacking the offsets once for all steps,
     // which would double the registers they take.
     __device__ __forceinline__ void keep_packed()
     {
 #pragma unroll
-        for (int s = 0; s < TileLds<Pat>::NSLOT; ++s)
+        for (int s = 0; s < NSLOT; ++s)
 #pragma unroll
             for (int p = 0; p < NP; ++p) asm volatile("" : "+v"(a[s][p]));
     }
 };
 
-template <class Pat>
-__device__ __forceinline__ void load_nb(const TileArgs &A, NbRegs<Pat> &R)
+template <class Pat, int NT>
+__device__ __forceinline__ void load_nb(const TileArgs &A, NbRegs<Pat, NT> &R)
 {
-    using LDS = TileLds<Pat>;
-    constexpr int NP = NbRegs<Pat>::NP;
+    constexpr int NP = NbRegs<Pat, NT>::NP;
 #pragma unroll
-    for (int s = 0; s < LDS::NSLOT; ++s) {
-        const uint32_t b = threadIdx.x + s * kBlock;
+    for (int s = 0; s < NbRegs<Pat, NT>::NSLOT; ++s) {
+        const uint32_t b = threadIdx.x + s * NT;
         const uint32_t *e = A.nbtab + (size_t)(b < A.nblocks ? b : 0u) * A.nbstride;
 #pragma unroll
         for (int g0 = 0; g0 < NP; g0 += 4) {
@@ -450,8 +452,8 @@ __device__ __forceinline__ void load_nb(const TileArgs &A, NbRegs<Pat> &R)
 
 // Phase C: one lane per level-J block.  Reads the block's word and the words
 // of its adjacent blocks from `src`, writes the block's new word to `dst`.
-template <class Pat>
-__device__ __forceinline__ void tile_blocks(const TileArgs &A, NbRegs<Pat> &R, const uint32_t *src, uint32_t *dst)
+template <class Pat, int NT>
+__device__ __forceinline__ void tile_blocks(const TileArgs &A, NbRegs<Pat, NT> &R, const uint32_t *src, uint32_t *dst)
 {
     R.keep_packed();
     using LDS = TileLds<Pat>;
@@ -461,8 +463,8 @@ __device__ __forceinline__ void tile_blocks(const TileArgs &A, NbRegs<Pat> &R, c
     constexpr int NL = PL.nlayer;
     constexpr int NG = LDS::NGRP;
 #pragma unroll
-    for (int s = 0; s < LDS::NSLOT; ++s) {
-        const uint32_t b = threadIdx.x + s * kBlock;
+    for (int s = 0; s < NbRegs<Pat, NT>::NSLOT; ++s) {
+        const uint32_t b = threadIdx.x + s * NT;
         if (b < A.nblocks) {
             const uint32_t x = src[b];
             uint32_t w[NG];
@@ -482,10 +484,11 @@ __device__ __forceinline__ void tile_blocks(const TileArgs &A, NbRegs<Pat> &R, c
 // Phase A: load and pack the tile (plus the bytes of its first and last
 // 32-byte words that belong to the neighbouring tiles) into stg: bit i of
 // word w = byte A0 + 32 w + i.
+template <int NT>
 __device__ __forceinline__ void tile_pack(const TileArgs &A, const uint8_t *__restrict__ in, uint64_t A0, uint32_t W,
                                           uint32_t *stg)
 {
-    for (uint32_t w = threadIdx.x; w < W; w += kBlock) {
+    for (uint32_t w = threadIdx.x; w < W; w += NT) {
         const uint64_t g = A0 + 32ull * w;
         uint32_t bits = 0;
         if (g + 32 <= A.N) {
@@ -503,12 +506,12 @@ __device__ __forceinline__ void tile_pack(const TileArgs &A, const uint8_t *__re
 // Phase A, second half: cut the packed bits (the tile starts at bit o of
 // word 0) into block words.  Word W of stg (never written) only feeds bits
 // that the mask drops.
-template <class Pat>
+template <class Pat, int NT>
 __device__ __forceinline__ void tile_convert(const TileArgs &A, uint32_t o, const uint32_t *stg, uint32_t *blk)
 {
     constexpr int NC = PlanOf<Pat>::value.nc;
     constexpr uint32_t CELLS = NC == 32 ? 0xFFFFFFFFu : ((1u << NC) - 1u);
-    for (uint32_t b = threadIdx.x; b < A.nblocks; b += kBlock) {
+    for (uint32_t b = threadIdx.x; b < A.nblocks; b += NT) {
         const uint32_t pos = o + b * NC;
         blk[b] = __builtin_amdgcn_alignbit(stg[(pos >> 5) + 1], stg[pos >> 5], pos) & CELLS;
     }
@@ -518,14 +521,14 @@ __device__ __forceinline__ void tile_convert(const TileArgs &A, uint32_t o, cons
 // 32-byte words; the (at most two) edge words of the tile go out byte by
 // byte, one byte per lane of wave 0.  A whole word reads at most the blocks
 // b0 .. b0+2 <= nblocks + 1; bits of blocks past the tile fall beyond bit 31.
-template <class Pat>
+template <class Pat, int NT>
 __device__ __forceinline__ void tile_store(const TileArgs &A, uint8_t *__restrict__ out, uint64_t A0, uint32_t o,
                                            uint32_t W, const uint32_t *blk)
 {
     constexpr uint32_t NC = PlanOf<Pat>::value.nc;
     const uint32_t tid = threadIdx.x, last = W - 1;
     const bool first_partial = o != 0, last_partial = ((o + A.tile) & 31) != 0;
-    for (uint32_t w = tid; w < W; w += kBlock) {
+    for (uint32_t w = tid; w < W; w += NT) {
         if (!((w == 0 && first_partial) || (w == last && last_partial))) {
             const uint32_t p0 = 32 * w - o;  // w > 0 or o == 0 here
             const uint32_t b0 = p0 / NC, r0 = p0 - b0 * NC;
@@ -557,7 +560,7 @@ __device__ __forceinline__ void tile_store(const TileArgs &A, uint8_t *__restric
 
 // One tile, one step.  s_in / s_out: TileLds<Pat>::WORDS words of LDS each
 // (s_out first holds the packed bytes).  Called by every lane of the workgroup.
-template <class Pat>
+template <class Pat, int NT = kBlock>
 __device__ __forceinline__ void tile_body(const TileArgs &A, const uint8_t *__restrict__ in, uint8_t *__restrict__ out,
                                           uint64_t t, uint32_t *s_in, uint32_t *s_out)
 {
@@ -576,35 +579,36 @@ __device__ __forceinline__ void tile_body(const TileArgs &A, const uint8_t *__re
         gi = A.tile_halo[t * A.tstride + tid];
         home = A.ringhome[tid];
     }
-    NbRegs<Pat> R;
-    load_nb<Pat>(A, R);
-    tile_pack(A, in, A0, W, s_out);
+    NbRegs<Pat, NT> R;
+    load_nb<Pat, NT>(A, R);
+    tile_pack<NT>(A, in, A0, W, s_out);
     if (tid < LDS::WORDS - LDS::ZERO) s_in[LDS::ZERO + tid] = 0;
     // Phase B, second half: the ring-1 cells themselves
     uint32_t v = 0;
     if (tid < 64) v = gi != kHole64 ? (in[gi] & 1u) : 0u;
     __syncthreads();
-    tile_convert<Pat>(A, o, s_out, s_in);
+    tile_convert<Pat, NT>(A, o, s_out, s_in);
     if (v) atomicOr(lds_word(s_in, home), 1u << (home & 31));
     __syncthreads();
-    tile_blocks<Pat>(A, R, s_in, s_out);
+    tile_blocks<Pat, NT>(A, R, s_in, s_out);
     __syncthreads();
-    tile_store<Pat>(A, out, A0, o, W, s_out);
+    tile_store<Pat, NT>(A, out, A0, o, W, s_out);
     __syncthreads();  // LDS is reused by the next tile
 }
 
 // One tile, K steps (temporal blocking).  The states of the ring cells are
 // loaded with the tile; in round j (computing t+j) the tile's blocks and the
-// cells of rings 1..K-j are advanced together, each ring cell by eight lanes
-// that read its neighbours at t+j-1 (tile bits or ring bits, through the
-// tile-invariant source table), a ballot and a popcount.  Three LDS buffers
-// rotate: round j reads buf[(j-1)%3], writes buf[j%3] and clears the ring
-// words of buf[(j+1)%3]; buf[2] first holds the packed bytes.  s_ex: two
-// words, bit c = ring slot c's tile exists.
-template <class Pat, int K>
+// cells of rings 1..K-j are advanced together, each ring cell by one lane of
+// wave 0 that reads its eight neighbours at t+j-1 (tile bits or ring bits,
+// through the tile-invariant source table, copied to LDS with the tile).
+// Three LDS buffers rotate: round j reads buf[(j-1)%3], writes buf[j%3] and
+// clears the ring words of buf[(j+1)%3]; buf[2] first holds the packed bytes.
+// s_ex: two words, bit c = ring slot c's tile exists.  s_ring: kRingTab words,
+// 16-byte aligned.
+template <class Pat, int K, int NT = kBlock>
 __device__ __forceinline__ void tile_bodyK(const TileArgs &A, const uint8_t *__restrict__ in,
                                            uint8_t *__restrict__ out, uint64_t t, uint32_t *const buf[3],
-                                           uint32_t *s_ex)
+                                           uint32_t *s_ex, uint32_t *s_ring)
 {
     using LDS = TileLds<Pat>;
     const uint32_t tid = threadIdx.x;
@@ -620,9 +624,10 @@ __device__ __forceinline__ void tile_bodyK(const TileArgs &A, const uint8_t *__r
         gi = A.tile_halo[t * A.tstride + tid];
         home = A.ringhome[tid];
     }
-    NbRegs<Pat> R;
-    load_nb<Pat>(A, R);
-    tile_pack(A, in, A0, W, buf[2]);
+    NbRegs<Pat, NT> R;
+    load_nb<Pat, NT>(A, R);
+    for (uint32_t i = tid; i < A.nsrc * 8; i += NT) s_ring[i] = A.ringsrc[i];
+    tile_pack<NT>(A, in, A0, W, buf[2]);
     if (tid < LDS::WORDS - LDS::ZERO) {
         buf[0][LDS::ZERO + tid] = 0;
         buf[1][LDS::ZERO + tid] = 0;
@@ -631,6 +636,7 @@ __device__ __forceinline__ void tile_bodyK(const TileArgs &A, const uint8_t *__r
     uint32_t v = 0;
     if (tid < 64) {
         v = gi != kHole64 ? (in[gi] & 1u) : 0u;
+        s_ring[kMaxRing * 8 + tid] = home;
         const uint64_t x = __ballot(gi != kHole64);
         if (tid == 0) {
             s_ex[0] = (uint32_t)x;
@@ -638,7 +644,7 @@ __device__ __forceinline__ void tile_bodyK(const TileArgs &A, const uint8_t *__r
         }
     }
     __syncthreads();
-    tile_convert<Pat>(A, o, buf[2], buf[0]);
+    tile_convert<Pat, NT>(A, o, buf[2], buf[0]);
     if (v) atomicOr(lds_word(buf[0], home), 1u << (home & 31));
     __syncthreads();
     const uint64_t present = (uint64_t)s_ex[1] << 32 | s_ex[0];
@@ -646,27 +652,24 @@ __device__ __forceinline__ void tile_bodyK(const TileArgs &A, const uint8_t *__r
     for (int j = 1; j <= K; ++j) {
         const uint32_t *src = buf[(j - 1) % 3];
         uint32_t *dst = buf[j % 3];
-        tile_blocks<Pat>(A, R, src, dst);
+        tile_blocks<Pat, NT>(A, R, src, dst);
         if (j < K) {
             uint32_t *clr = buf[(j + 1) % 3];
             if (tid < LDS::WORDS - LDS::VIRT) clr[LDS::VIRT + tid] = 0;
-            const uint32_t ncell = A.ring_start[K - j];
-            for (uint32_t c0 = 0; c0 < ncell; c0 += kBlock / 8) {
-                const uint32_t c = c0 + (tid >> 3);
-                uint32_t bit = 0;
-                if (c < ncell) bit = lds_bit(src, A.ringsrc[c * 8 + (tid & 7)]);
-                const uint64_t m = __ballot(bit);
-                if (c < ncell && (tid & 7) == 0) {
-                    const uint32_t h = A.ringhome[c];
-                    const uint32_t cnt = __builtin_popcountll((m >> (tid & 56)) & 0xFFull);
-                    const uint32_t self = lds_bit(src, h), here = (uint32_t)(present >> c) & 1u;
-                    if (here & ((cnt == 3) | (self & (cnt == 2)))) atomicOr(lds_word(dst, h), 1u << (h & 31));
-                }
+            if (tid < A.ring_start[K - j]) {  // wave 0
+                const uint4 e0 = *reinterpret_cast<const uint4 *>(s_ring + tid * 8);
+                const uint4 e1 = *reinterpret_cast<const uint4 *>(s_ring + tid * 8 + 4);
+                const uint32_t cnt = lds_bit(src, e0.x) + lds_bit(src, e0.y) + lds_bit(src, e0.z) +
+                                     lds_bit(src, e0.w) + lds_bit(src, e1.x) + lds_bit(src, e1.y) +
+                                     lds_bit(src, e1.z) + lds_bit(src, e1.w);
+                const uint32_t h = s_ring[kMaxRing * 8 + tid];
+                const uint32_t self = lds_bit(src, h), here = (uint32_t)(present >> tid) & 1u;
+                if (here & ((cnt == 3) | (self & (cnt == 2)))) atomicOr(lds_word(dst, h), 1u << (h & 31));
             }
         }
         __syncthreads();
     }
-    tile_store<Pat>(A, out, A0, o, W, buf[K % 3]);
+    tile_store<Pat, NT>(A, out, A0, o, W, buf[K % 3]);
     __syncthreads();
 }
 
