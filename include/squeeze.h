@@ -136,7 +136,8 @@ typedef struct sqz_info {
     int32_t has_tile;    /* 1 if SQZ_IMPL_TILE is available for this pattern */
     int32_t xtile_level; /* level of the expanded tiles of SQZ_IMPL_XTILE (0 if none) */
     int32_t run_steps_per_launch; /* Life steps per launch in sqz_compact_run with 16-byte aligned
-                                     buffers: 2 with the two-step tiled kernel, else 1 */
+                                     buffers: up to 7 with multi-step tiled kernels (temporal
+                                     blocking), else 1 */
     int32_t reserved;
 } sqz_info;
 

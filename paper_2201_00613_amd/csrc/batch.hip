@@ -85,7 +85,7 @@ __device__ __forceinline__ void life_cell_unit(const MapParams &P, const uint8_t
 template <class Pat>
 __host__ __device__ constexpr int ring_tab_offset()
 {
-    return (3 * TileLds<Pat>::WORDS + 2 + 3) / 4 * 4;
+    return (3 * TileLds<Pat>::WORDS + 3) / 4 * 4;
 }
 
 template <class Pat, int K>
@@ -98,7 +98,7 @@ __device__ __forceinline__ void bitsliced_unit(const BatchInst &I, const uint8_t
         tile_body<Pat>(I.tile, in, out, t, s_in, s_in + LDS::WORDS);
     } else {
         uint32_t *const buf[3] = {s_in, s_in + LDS::WORDS, s_in + 2 * LDS::WORDS};
-        tile_bodyK<Pat, K>(I.tile, in, out, t, buf, s_in + 3 * LDS::WORDS, s_in + ring_tab_offset<Pat>());
+        tile_bodyK<Pat, K>(I.tile, in, out, t, buf, s_in + ring_tab_offset<Pat>());
     }
 }
 

@@ -33,14 +33,13 @@ k_life_tileK(TileArgs A, const uint8_t *__restrict__ in, uint8_t *__restrict__ o
 {
     using LDS = TileLds<Pat>;
     __shared__ uint32_t s_buf[3][LDS::WORDS];
-    __shared__ uint32_t s_ex[2];  // ring cells present (their tile exists)
     __shared__ __align__(16) uint32_t s_ring[kRingTab];
     uint32_t *const buf[3] = {s_buf[0], s_buf[1], s_buf[2]};
     const uint32_t G = gridDim.x;
     for (uint64_t round = 0; round * G < A.ntiles; ++round) {
         const uint64_t t = round * G + xcd_remap(blockIdx.x, G);
         if (t >= A.ntiles) break;  // uniform across the workgroup
-        tile_bodyK<Pat, K, NT>(A, in, out, t, buf, s_ex, s_ring);
+        tile_bodyK<Pat, K, NT>(A, in, out, t, buf, s_ring);
     }
 }
 
@@ -120,7 +119,7 @@ sqz_status prepare(FractalHost &F)
 
     // rings 2..kMaxSteps (several steps per launch): breadth-first from ring 1
     // over member cells outside the tile (ring d = graph distance d from the
-    // tile); each must fit one LDS word and all rings the 64 lanes of wave 0.
+    // tile); each must fit one LDS word and all rings kMaxRing lanes.
     std::vector<Slot> ring = slots;  // rings in order, ring 1 first
     std::vector<uint32_t> start = {0, (uint32_t)slots.size()};
     auto find = [&](int64_t qx, int64_t qy) {
@@ -145,7 +144,8 @@ sqz_status prepare(FractalHost &F)
                     if (j >= 0 && find(qx, qy) < 0) ring.push_back(Slot{tdx, tdy, j, qx, qy});
                 }
         start.push_back((uint32_t)ring.size());
-        if (T->nthalo == 0 || start[d] - start[d - 1] > 32 || start[d] > (uint32_t)kMaxRing) break;
+        // (ring cells must also lie in adjacent tiles: d < side)
+        if (T->nthalo == 0 || start[d] - start[d - 1] > 32 || start[d] > (uint32_t)kMaxRing || d >= side) break;
         ksteps = (uint32_t)d;  // rings 1..d fit: d steps per launch
     }
     T->ksteps = ksteps;
@@ -291,7 +291,10 @@ sqz_status launch(const FractalHost &F, const uint8_t *in, uint8_t *out, int ste
     case 1: hipLaunchKernelGGL((k_life_tile<Pat, NT>), dim3((unsigned)grid), dim3(NT), 0, st, A, in, out); break;
     case 2: hipLaunchKernelGGL((k_life_tileK<Pat, 2, NT>), dim3((unsigned)grid), dim3(NT), 0, st, A, in, out); break;
     case 3: hipLaunchKernelGGL((k_life_tileK<Pat, 3, NT>), dim3((unsigned)grid), dim3(NT), 0, st, A, in, out); break;
-    default: hipLaunchKernelGGL((k_life_tileK<Pat, 4, NT>), dim3((unsigned)grid), dim3(NT), 0, st, A, in, out); break;
+    case 4: hipLaunchKernelGGL((k_life_tileK<Pat, 4, NT>), dim3((unsigned)grid), dim3(NT), 0, st, A, in, out); break;
+    case 5: hipLaunchKernelGGL((k_life_tileK<Pat, 5, NT>), dim3((unsigned)grid), dim3(NT), 0, st, A, in, out); break;
+    case 6: hipLaunchKernelGGL((k_life_tileK<Pat, 6, NT>), dim3((unsigned)grid), dim3(NT), 0, st, A, in, out); break;
+    default: hipLaunchKernelGGL((k_life_tileK<Pat, 7, NT>), dim3((unsigned)grid), dim3(NT), 0, st, A, in, out); break;
     }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? SQZ_OK : hip_error(e, "compact step (tile) launch");

@@ -77,9 +77,9 @@ constexpr int cpow(int b, int e)
 }
 
 constexpr int kMaxHalo = 16;      // halo cells per block
-constexpr int kMaxSteps = 4;      // Life steps per launch of the multi-step tiled kernel
+constexpr int kMaxSteps = 7;      // Life steps per launch of the multi-step tiled kernel
 constexpr int kMaxTileHalo = 32;  // halo cells per tile (one LDS word of bits)
-constexpr int kMaxRing = 64;      // ring cells of all rings (one wave)
+constexpr int kMaxRing = 128;     // ring cells of all rings (two waves)
 constexpr int kRingTab = kMaxRing * 9;  // LDS words of a tile's ring tables: 8 sources per cell, then homes
 constexpr int kBlock = 256;
 
@@ -597,27 +597,27 @@ __device__ __forceinline__ void tile_body(const TileArgs &A, const uint8_t *__re
 }
 
 // One tile, K steps (temporal blocking).  The states of the ring cells are
-// loaded with the tile; in round j (computing t+j) the tile's blocks and the
-// cells of rings 1..K-j are advanced together, each ring cell by one lane of
-// wave 0 that reads its eight neighbours at t+j-1 (tile bits or ring bits,
-// through the tile-invariant source table, copied to LDS with the tile).
-// Three LDS buffers rotate: round j reads buf[(j-1)%3], writes buf[j%3] and
-// clears the ring words of buf[(j+1)%3]; buf[2] first holds the packed bytes.
-// s_ex: two words, bit c = ring slot c's tile exists.  s_ring: kRingTab words,
-// 16-byte aligned.
+// loaded with the tile, one lane per ring cell; in round j (computing t+j)
+// the tile's blocks and the cells of rings 1..K-j are advanced together, ring
+// cell c by lane c, which reads its eight neighbours at t+j-1 (tile bits or
+// ring bits, through the tile-invariant source table, copied to LDS with the
+// tile).  A ring cell whose tile does not exist stays zero.  Three LDS
+// buffers rotate: round j reads buf[(j-1)%3], writes buf[j%3] and clears the
+// ring words of buf[(j+1)%3]; buf[2] first holds the packed bytes.  s_ring:
+// kRingTab words, 16-byte aligned.
 template <class Pat, int K, int NT = kBlock>
 __device__ __forceinline__ void tile_bodyK(const TileArgs &A, const uint8_t *__restrict__ in,
                                            uint8_t *__restrict__ out, uint64_t t, uint32_t *const buf[3],
-                                           uint32_t *s_ex, uint32_t *s_ring)
+                                           uint32_t *s_ring)
 {
     using LDS = TileLds<Pat>;
+    static_assert(kMaxRing <= NT, "one lane per ring cell");
     const uint32_t tid = threadIdx.x;
     const uint64_t S0 = t * A.tile;
     const uint64_t A0 = S0 & ~31ull;
     const uint32_t o = (uint32_t)(S0 - A0);
     const uint32_t W = (o + A.tile + 31) / 32;
 
-    // ring slots (at most 64: wave 0)
     uint64_t gi = kHole64;
     uint32_t home = 0;
     if (tid < A.tstride) {
@@ -633,21 +633,16 @@ __device__ __forceinline__ void tile_bodyK(const TileArgs &A, const uint8_t *__r
         buf[1][LDS::ZERO + tid] = 0;
         buf[2][LDS::ZERO + tid] = 0;
     }
+    const bool here = gi != kHole64;  // ring cell tid exists
     uint32_t v = 0;
-    if (tid < 64) {
-        v = gi != kHole64 ? (in[gi] & 1u) : 0u;
+    if (tid < kMaxRing) {
+        v = here ? (in[gi] & 1u) : 0u;
         s_ring[kMaxRing * 8 + tid] = home;
-        const uint64_t x = __ballot(gi != kHole64);
-        if (tid == 0) {
-            s_ex[0] = (uint32_t)x;
-            s_ex[1] = (uint32_t)(x >> 32);
-        }
     }
     __syncthreads();
     tile_convert<Pat, NT>(A, o, buf[2], buf[0]);
     if (v) atomicOr(lds_word(buf[0], home), 1u << (home & 31));
     __syncthreads();
-    const uint64_t present = (uint64_t)s_ex[1] << 32 | s_ex[0];
 #pragma unroll
     for (int j = 1; j <= K; ++j) {
         const uint32_t *src = buf[(j - 1) % 3];
@@ -656,14 +651,14 @@ __device__ __forceinline__ void tile_bodyK(const TileArgs &A, const uint8_t *__r
         if (j < K) {
             uint32_t *clr = buf[(j + 1) % 3];
             if (tid < LDS::WORDS - LDS::VIRT) clr[LDS::VIRT + tid] = 0;
-            if (tid < A.ring_start[K - j]) {  // wave 0
+            if (tid < A.ring_start[K - j]) {  // waves 0 and 1
                 const uint4 e0 = *reinterpret_cast<const uint4 *>(s_ring + tid * 8);
                 const uint4 e1 = *reinterpret_cast<const uint4 *>(s_ring + tid * 8 + 4);
                 const uint32_t cnt = lds_bit(src, e0.x) + lds_bit(src, e0.y) + lds_bit(src, e0.z) +
                                      lds_bit(src, e0.w) + lds_bit(src, e1.x) + lds_bit(src, e1.y) +
                                      lds_bit(src, e1.z) + lds_bit(src, e1.w);
                 const uint32_t h = s_ring[kMaxRing * 8 + tid];
-                const uint32_t self = lds_bit(src, h), here = (uint32_t)(present >> tid) & 1u;
+                const uint32_t self = lds_bit(src, h);
                 if (here & ((cnt == 3) | (self & (cnt == 2)))) atomicOr(lds_word(dst, h), 1u << (h & 31));
             }
         }
