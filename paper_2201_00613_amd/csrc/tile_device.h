@@ -46,7 +46,7 @@ namespace sqz {
 #ifndef SQZ_NT_LOAD
 #define SQZ_NT_LOAD 0
 #endif
-#ifndef SQZ_NT_STORE
+#ifndef SQZ_NT_STORE  // 1: nontemporal stores in every tiled kernel, 0: in the multi-step kernels only
 #define SQZ_NT_STORE 0
 #endif
 
@@ -332,14 +332,15 @@ __device__ __forceinline__ uint4 load16(const uint8_t *p)
     return *reinterpret_cast<const uint4 *>(p);
 #endif
 }
+template <bool NTS>
 __device__ __forceinline__ void store16(uint8_t *p, uint4 v)
 {
-#if SQZ_NT_STORE
-    u32x4 w = {v.x, v.y, v.z, v.w};
-    __builtin_nontemporal_store(w, reinterpret_cast<u32x4 *>(p));
-#else
-    *reinterpret_cast<uint4 *>(p) = v;
-#endif
+    if constexpr (NTS || SQZ_NT_STORE) {
+        u32x4 w = {v.x, v.y, v.z, v.w};
+        __builtin_nontemporal_store(w, reinterpret_cast<u32x4 *>(p));
+    } else {
+        *reinterpret_cast<uint4 *>(p) = v;
+    }
 }
 
 template <int Layer, int Shift, uint32_t Mask, int NL>
@@ -518,10 +519,10 @@ __device__ __forceinline__ void tile_convert(const TileArgs &A, uint32_t o, cons
 }
 
 // Phase D: join block words back into 32-cell words, unpack and store whole
-// 32-byte words; the (at most two) edge words of the tile go out byte by
-// byte, one byte per lane of wave 0.  A whole word reads at most the blocks
+// 32-byte words (NTS: nontemporal); the (at most two) edge words of the tile
+// go out byte by byte, one byte per lane of wave 0.  A whole word reads at most the blocks
 // b0 .. b0+2 <= nblocks + 1; bits of blocks past the tile fall beyond bit 31.
-template <class Pat, int NT>
+template <class Pat, int NT, bool NTS = false>
 __device__ __forceinline__ void tile_store(const TileArgs &A, uint8_t *__restrict__ out, uint64_t A0, uint32_t o,
                                            uint32_t W, const uint32_t *blk)
 {
@@ -544,8 +545,8 @@ __device__ __forceinline__ void tile_store(const TileArgs &A, uint8_t *__restric
             b.y = spread4((v >> 20) & 15);
             b.z = spread4((v >> 24) & 15);
             b.w = spread4(v >> 28);
-            store16(out + g, a);
-            store16(out + g + 16, b);
+            store16<NTS>(out + g, a);
+            store16<NTS>(out + g + 16, b);
         }
     }
     if (tid < 64) {
@@ -664,7 +665,7 @@ __device__ __forceinline__ void tile_bodyK(const TileArgs &A, const uint8_t *__r
         }
         __syncthreads();
     }
-    tile_store<Pat, NT>(A, out, A0, o, W, buf[K % 3]);
+    tile_store<Pat, NT, true>(A, out, A0, o, W, buf[K % 3]);  // streaming: read next by another launch
     __syncthreads();
 }
 
