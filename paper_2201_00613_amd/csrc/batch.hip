@@ -104,7 +104,7 @@ __device__ __forceinline__ void bitsliced_unit(const BatchInst &I, const uint8_t
 
 // K Life steps of every instance (K > 1: every instance has multi-step tiles).
 template <int K>
-__global__ void __launch_bounds__(256) k_batch_life(BatchArgs B, const uint8_t *__restrict__ in,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_batch_life(BatchArgs B, const uint8_t *__restrict__ in,
                                                     uint8_t *__restrict__ out)
 {
     extern __shared__ __align__(16) unsigned char smem[];
