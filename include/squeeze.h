@@ -61,7 +61,9 @@ typedef enum sqz_status {
 typedef enum sqz_layout { SQZ_LAYOUT_COMPACT = 0, SQZ_LAYOUT_EXPANDED = 1 } sqz_layout;
 
 /* Implementation of the compact stencil.
- *   SQZ_IMPL_AUTO: the tiled kernel when one exists for the replica pattern, else CELL.
+ *   SQZ_IMPL_AUTO: TILE when the pattern has a bit-sliced tiled kernel and the
+ *                  buffers are 16-byte aligned, else BITS when it has bit-row
+ *                  tiles and the buffers are 8-byte aligned, else XTILE, else CELL.
  *   SQZ_IMPL_CELL: thread-level Squeeze: one lambda and eight nu per cell
  *                  (Section "Exploring Compact Fractal Space").
  *   SQZ_IMPL_TILE: block-level Squeeze (Section "Moving from Thread-level to
@@ -71,13 +73,21 @@ typedef enum sqz_layout { SQZ_LAYOUT_COMPACT = 0, SQZ_LAYOUT_EXPANDED = 1 } sqz_
 /*   SQZ_IMPL_XTILE: block-level Squeeze with the level-M subtree expanded on chip
  *                  (any replica pattern; SQZ_ERR_UNSUPPORTED when no level fits).
  *   SQZ_IMPL_CELL_MFMA: CELL with both maps evaluated on the matrix cores
- *                  (SQZ_MAP_MFMA below).  A comparison variant, never chosen by AUTO. */
+ *                  (SQZ_MAP_MFMA below).  A comparison variant, never chosen by AUTO.
+ *   SQZ_IMPL_BITS: block-level Squeeze with the level-M subtree (M <= 5) and a
+ *                  six-cell border from the adjacent subtrees expanded on chip
+ *                  as bit rows, Life on 32 positions per word (patterns with
+ *                  s = 3 and at most 8 replicas that have a kernel: the
+ *                  Sierpinski carpet; levels >= 2).  Buffers 8-byte aligned
+ *                  (SQZ_ERR_INVALID otherwise); SQZ_ERR_UNSUPPORTED for other
+ *                  patterns.  Up to 6 steps per launch in sqz_compact_run. */
 typedef enum sqz_impl {
     SQZ_IMPL_AUTO = 0,
     SQZ_IMPL_CELL = 1,
     SQZ_IMPL_TILE = 2,
     SQZ_IMPL_XTILE = 3,
-    SQZ_IMPL_CELL_MFMA = 4
+    SQZ_IMPL_CELL_MFMA = 4,
+    SQZ_IMPL_BITS = 5
 } sqz_impl;
 
 /* Evaluation of lambda and nu.
@@ -138,7 +148,7 @@ typedef struct sqz_info {
     int32_t run_steps_per_launch; /* Life steps per launch in sqz_compact_run with 16-byte aligned
                                      buffers: up to 7 with multi-step tiled kernels (temporal
                                      blocking), else 1 */
-    int32_t reserved;
+    int32_t bits_level;  /* level M of the bit-row tiles of SQZ_IMPL_BITS (0 if none) */
 } sqz_info;
 
 /*

@@ -9,12 +9,14 @@ from __future__ import annotations
 
 import ctypes
 
-from ._lib import (BF16, F32, HOLE, IMPL_AUTO, IMPL_CELL, IMPL_CELL_MFMA, IMPL_TILE, IMPL_XTILE, LAYOUT_COMPACT,
-                   LAYOUT_EXPANDED, MAP_MFMA, MAP_SCALAR, MASS_WORK_DOUBLES, ROUND_NEAREST_EVEN, ROUND_STOCHASTIC, Diffusion, Info, SqueezeError, check, lib)
+from ._lib import (BF16, F32, HOLE, IMPL_AUTO, IMPL_BITS, IMPL_CELL, IMPL_CELL_MFMA, IMPL_TILE, IMPL_XTILE,
+                   LAYOUT_COMPACT, LAYOUT_EXPANDED, MAP_MFMA, MAP_SCALAR, MASS_WORK_DOUBLES, ROUND_NEAREST_EVEN,
+                   ROUND_STOCHASTIC, Diffusion, Info, SqueezeError, check, lib)
 
 __all__ = ["Fractal", "SqueezeError", "HOLE", "descriptor_check", "IMPLS"]
 
-IMPLS = {"auto": IMPL_AUTO, "cell": IMPL_CELL, "tile": IMPL_TILE, "xtile": IMPL_XTILE, "cell_mfma": IMPL_CELL_MFMA}
+IMPLS = {"auto": IMPL_AUTO, "cell": IMPL_CELL, "tile": IMPL_TILE, "xtile": IMPL_XTILE, "cell_mfma": IMPL_CELL_MFMA,
+         "bits": IMPL_BITS}
 MAP_IMPLS = {"scalar": MAP_SCALAR, "mfma": MAP_MFMA}
 DTYPES = {"f32": F32, "bf16": BF16}
 ROUNDINGS = {"nearest": ROUND_NEAREST_EVEN, "stochastic": ROUND_STOCHASTIC}
@@ -74,6 +76,7 @@ class Fractal:
         self.tile_level = info.tile_level
         self.xtile_level = info.xtile_level
         self.run_steps_per_launch = info.run_steps_per_launch
+        self.bits_level = info.bits_level
         self.offsets = [tuple(map(int, xy)) for xy in offsets]
 
     def close(self):

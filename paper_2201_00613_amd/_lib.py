@@ -11,7 +11,7 @@ LIB_PATH = os.path.join(_HERE, "libsqueeze.so")
 OK, ERR_INVALID, ERR_RANGE, ERR_NOMEM, ERR_HIP, ERR_UNSUPPORTED = range(6)
 HOLE = (1 << 64) - 1
 LAYOUT_COMPACT, LAYOUT_EXPANDED = 0, 1
-IMPL_AUTO, IMPL_CELL, IMPL_TILE, IMPL_XTILE, IMPL_CELL_MFMA = 0, 1, 2, 3, 4
+IMPL_AUTO, IMPL_CELL, IMPL_TILE, IMPL_XTILE, IMPL_CELL_MFMA, IMPL_BITS = 0, 1, 2, 3, 4, 5
 MAP_SCALAR, MAP_MFMA = 0, 1
 F32, BF16 = 0, 1
 ROUND_NEAREST_EVEN, ROUND_STOCHASTIC = 0, 1
@@ -30,7 +30,7 @@ class Info(ctypes.Structure):
         ("tile_level", ctypes.c_int32), ("n", ctypes.c_int64), ("cells", ctypes.c_uint64),
         ("compact_w", ctypes.c_uint64), ("compact_h", ctypes.c_uint64),
         ("has_tile", ctypes.c_int32), ("xtile_level", ctypes.c_int32),
-        ("run_steps_per_launch", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("run_steps_per_launch", ctypes.c_int32), ("bits_level", ctypes.c_int32),
     ]
 
 

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libsqueeze.so")
-SOURCES = ["api.hip", "maps.hip", "mfma_maps.hip", "blocks.hip", "bb.hip", "life_tile.hip", "xtile.hip", "batch.hip"]
+SOURCES = ["api.hip", "maps.hip", "mfma_maps.hip", "blocks.hip", "bb.hip", "life_tile.hip", "xtile.hip", "bitbox.hip", "batch.hip"]
 ARCH = os.environ.get("SQZ_OFFLOAD_ARCH", "gfx950")
 
 

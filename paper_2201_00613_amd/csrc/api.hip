@@ -320,11 +320,15 @@ sqz_status sqz_fractal_create(int32_t s, int32_t k, const int32_t *offsets_xy, i
     f->h.tile_kind = tile_kind_for(f->h);
     f->h.tile = nullptr;
     f->h.xtile = nullptr;
+    f->h.bitbox = nullptr;
     f->h.mfma = mfma_prepare(f->h);  // null when the pattern does not fit int8 digits
     if (f->h.tile_kind) st = tile_prepare(f->h);
     if (st == SQZ_OK) st = xtile_prepare(f->h);
+    if (st == SQZ_OK) st = bitbox_prepare(f->h);
     if (st != SQZ_OK) {
         tile_release(f->h);
+        xtile_release(f->h);
+        bitbox_release(f->h);
         mfma_release(f->h);
         (void)hipFree(f->h.d_tables);
         delete f;
@@ -339,6 +343,7 @@ void sqz_fractal_destroy(sqz_fractal *f)
     if (!f) return;
     tile_release(f->h);
     xtile_release(f->h);
+    bitbox_release(f->h);
     mfma_release(f->h);
     if (f->h.d_tables) (void)hipFree(f->h.d_tables);
     delete f;
@@ -351,9 +356,12 @@ sqz_status sqz_fractal_info(const sqz_fractal *f, sqz_info *out)
     out->has_tile = f->h.tile_kind != 0;
     out->tile_level = tile_level_of(f->h);
     out->xtile_level = xtile_level_of(f->h);
+    out->bits_level = bitbox_level_of(f->h);
     {
-        const int kt = tile_steps_per_launch(f->h), kx = xtile_steps_per_launch(f->h);
-        out->run_steps_per_launch = f->h.tile_kind ? (kt > 1 ? kt : 1) : (kx > 1 ? kx : 1);
+        const int kt = tile_steps_per_launch(f->h), kb = bitbox_steps_per_launch(f->h),
+                  kx = xtile_steps_per_launch(f->h);
+        const int k = f->h.tile_kind ? kt : (f->h.bitbox ? kb : kx);
+        out->run_steps_per_launch = k > 1 ? k : 1;
     }
     return SQZ_OK;
 }
@@ -453,12 +461,17 @@ sqz_status sqz_compact_step_impl(const sqz_fractal *f, sqz_impl impl, const uint
     if (overlap(d_in, d_out, f->h.N)) return set_error(SQZ_ERR_INVALID, "d_in and d_out overlap");
     hipStream_t s = (hipStream_t)stream;
     const bool aligned = !(((uintptr_t)d_in | (uintptr_t)d_out) & 15);
+    const bool aligned8 = !(((uintptr_t)d_in | (uintptr_t)d_out) & 7);
     switch (impl) {
     case SQZ_IMPL_AUTO:
-        // the bit-sliced tiled kernel moves 16-byte words; unaligned buffers skip it
+        // the bit-sliced tiled kernel moves 16-byte words, the bit-row tiles 8-byte
+        // words; unaligned buffers skip them
         if (f->h.tile_kind && aligned) return launch_life_tile(f->h, d_in, d_out, s);
+        if (f->h.bitbox && aligned8) return launch_life_bitbox(f->h, d_in, d_out, 1, s);
         if (f->h.xtile) return launch_life_xtile(f->h, d_in, d_out, s);
         return launch_life_cell(f->h.P, d_in, d_out, s);
+    case SQZ_IMPL_BITS:
+        return launch_life_bitbox(f->h, d_in, d_out, 1, s);
     case SQZ_IMPL_CELL:
         return launch_life_cell(f->h.P, d_in, d_out, s);
     case SQZ_IMPL_TILE:
@@ -488,16 +501,22 @@ sqz_status sqz_compact_run(const sqz_fractal *f, uint8_t *d_a, uint8_t *d_b, int
     if (!d_a || !d_b) return set_error(SQZ_ERR_INVALID, "NULL buffer");
     if (overlap(d_a, d_b, f->h.N)) return set_error(SQZ_ERR_INVALID, "d_a and d_b overlap");
     const bool aligned = !(((uintptr_t)d_a | (uintptr_t)d_b) & 15);
-    const bool tiled = f->h.tile_kind && aligned;
-    const int K = tiled ? tile_steps_per_launch(f->h) : xtile_steps_per_launch(f->h);
+    const bool aligned8 = !(((uintptr_t)d_a | (uintptr_t)d_b) & 7);
+    const bool tiled = f->h.tile_kind && aligned, bits = !tiled && f->h.bitbox && aligned8;
+    const int K = tiled ? tile_steps_per_launch(f->h)
+                        : (bits ? bitbox_steps_per_launch(f->h) : xtile_steps_per_launch(f->h));
     if (K >= 2) {
         const std::vector<int> plan = plan_launches(steps, K);
         const hipStream_t s = (hipStream_t)stream;
         for (size_t i = 0; i < plan.size() && st == SQZ_OK; ++i) {
             const uint8_t *in = (i & 1) ? d_b : d_a;
             uint8_t *out = (i & 1) ? d_a : d_b;
-            st = tiled ? launch_life_tile_steps(f->h, in, out, plan[i], s)
-                       : launch_life_xtile_steps(f->h, in, out, plan[i], s);
+            if (tiled)
+                st = launch_life_tile_steps(f->h, in, out, plan[i], s);
+            else if (bits)
+                st = launch_life_bitbox(f->h, in, out, plan[i], s);
+            else
+                st = launch_life_xtile_steps(f->h, in, out, plan[i], s);
         }
         return st;
     }

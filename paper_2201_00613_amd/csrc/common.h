@@ -163,6 +163,7 @@ __device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t i)
 struct TileConfig;   // defined in life_tile.hip
 struct XTileConfig;  // defined in xtile.hip
 struct MfmaParams;   // defined in mfma_maps.hip
+struct BitboxConfig; // defined in bitbox.hip
 
 struct FractalHost {
     int32_t s, k, r;
@@ -178,6 +179,7 @@ struct FractalHost {
     TileConfig *tile;
     XTileConfig *xtile;           // expanded-tile kernels (any pattern), null if none
     MfmaParams *mfma;             // matrix-core map variants, null if unsupported (k > 127)
+    BitboxConfig *bitbox;         // bit-row expanded tiles (dense s = 3 patterns), null if none
 };
 
 // Launch sizes for `steps` steps with at most K per launch (temporal
@@ -255,6 +257,13 @@ sqz_status launch_mass(const FractalHost &F, int dtype, const void *u, double of
 sqz_status launch_bf16_convert(const FractalHost &F, int encode, const float *u, float offset, uint16_t *b,
                                hipStream_t st);
 int mass_grid();
+
+// Bit-row expanded tiles (bitbox.hip)
+sqz_status bitbox_prepare(FractalHost &F);
+void bitbox_release(FractalHost &F);
+int bitbox_steps_per_launch(const FractalHost &F);  // 0: none
+int32_t bitbox_level_of(const FractalHost &F);
+sqz_status launch_life_bitbox(const FractalHost &F, const uint8_t *in, uint8_t *out, int steps, hipStream_t st);
 
 // Batched Life (batch.hip)
 struct BatchHost;
