@@ -1,20 +1,26 @@
 // Batched Life: many independent fractals of mixed replica pattern and level
-// advanced together, one persistent launch per step.
+// advanced together.
 //
-// Every instance owns a 256-byte aligned range of one state buffer.  Its work
-// is a list of units: level-M tiles for the bit-sliced (triangle, Vicsek) and
-// expanded-tile (any pattern) paths, runs of 4096 cells for the thread-level
-// path (instances too small to tile).  The units of all instances form one
-// sequence; workgroup b takes the units whose first cell falls in the b-th
-// equal share of all cells, so the split is balanced by cells and each
-// workgroup walks adjacent tiles of one or two instances.  The tile bodies are
-// the same device functions the single-fractal kernels use, with LDS carved
-// from one dynamic buffer; the expanded-tile tables are reloaded only when a
-// workgroup moves to an instance with a different tile configuration.
+// Every instance owns a 256-byte aligned range of one state buffer.
+// Instances with a tiled kernel form groups by pattern (bit-sliced tiles of
+// the triangle, its mirror image and the Vicsek cross; bit-row tiles of the
+// carpet): a group is one launch with one workgroup per tile of any of its
+// instances, the same device functions as the single-fractal kernels, and
+// its own number of steps per launch.  The remaining instances (expanded
+// tiles of any pattern, runs of 4096 cells of the thread-level path for
+// instances too small to tile) share one persistent launch: their units form
+// one sequence, and workgroup b takes the units whose first cost unit falls
+// in the b-th equal share of the total cost, so each workgroup walks
+// adjacent tiles of one or two instances; the expanded-tile tables are
+// reloaded only when a workgroup moves to an instance with a different tile
+// configuration.  Instances are independent, so every group follows its own
+// launch plan; each plan has the parity of the step count, so all results
+// land in the same buffer.
 //
 // Runs of several steps are captured once into a hipGraph (kernel nodes only)
-// and replayed; an autotuner times candidate grid sizes on the caller's
-// buffers and keeps the fastest, cached per batch composition.
+// and replayed; an autotuner times candidate grid sizes of the persistent
+// launch on the caller's buffers and keeps the fastest, cached per batch
+// composition.
 #include <string.h>
 
 #include <algorithm>
@@ -23,6 +29,7 @@
 #include <string>
 #include <vector>
 
+#include "bitbox_device.h"
 #include "tile_device.h"
 #include "xtile_device.h"
 
@@ -30,7 +37,7 @@ struct sqz_fractal;  // api.hip
 
 namespace sqz {
 
-enum BatchKind : uint32_t { kBTri = 1, kBTriPaper = 2, kBVicsek = 3, kBX68 = 4, kBX84 = 5, kBXAny = 6, kBCell = 7 };
+enum BatchKind : uint32_t { kBTri = 1, kBTriPaper = 2, kBVicsek = 3, kBX68 = 4, kBX84 = 5, kBXAny = 6, kBCell = 7, kBBits = 8 };
 
 constexpr uint32_t kCellUnit = 4096;
 
@@ -81,28 +88,8 @@ __device__ __forceinline__ void life_cell_unit(const MapParams &P, const uint8_t
     }
 }
 
-// LDS word offset of the ring tables in the multi-step layout (16-byte aligned)
-template <class Pat>
-__host__ __device__ constexpr int ring_tab_offset()
-{
-    return (3 * TileLds<Pat>::WORDS + 3) / 4 * 4;
-}
-
-template <class Pat, int K>
-__device__ __forceinline__ void bitsliced_unit(const BatchInst &I, const uint8_t *in, uint8_t *out, uint64_t t,
-                                               unsigned char *smem)
-{
-    using LDS = TileLds<Pat>;
-    uint32_t *s_in = reinterpret_cast<uint32_t *>(smem);
-    if constexpr (K == 1) {
-        tile_body<Pat>(I.tile, in, out, t, s_in, s_in + LDS::WORDS);
-    } else {
-        uint32_t *const buf[3] = {s_in, s_in + LDS::WORDS, s_in + 2 * LDS::WORDS};
-        tile_bodyK<Pat, K>(I.tile, in, out, t, buf, s_in + ring_tab_offset<Pat>());
-    }
-}
-
-// K Life steps of every instance (K > 1: every instance has multi-step tiles).
+// K Life steps of every instance of the persistent launch (K > 1: every such
+// instance has multi-step expanded tiles).
 template <int K>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_batch_life(BatchArgs B, const uint8_t *__restrict__ in,
                                                     uint8_t *__restrict__ out)
@@ -139,21 +126,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
         uint8_t *oo = out + I.base;
         __syncthreads();  // the previous unit's LDS reads are done
         switch (I.kind) {
-        case kBTri:
-            loaded = -1;
-            bitsliced_unit<PatTriangle, K>(I, ii, oo, j, smem);
-            ++j;
-            break;
-        case kBTriPaper:
-            loaded = -1;
-            bitsliced_unit<PatTrianglePaper, K>(I, ii, oo, j, smem);
-            ++j;
-            break;
-        case kBVicsek:
-            loaded = -1;
-            bitsliced_unit<PatVicsek, K>(I, ii, oo, j, smem);
-            ++j;
-            break;
         case kBX68:
         case kBX84:
         case kBXAny: {
@@ -200,12 +172,77 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     }
 }
 
+// One group: instances of one tiled pattern, one workgroup per tile.
+struct GroupArgs {
+    const void *args;        // per instance: TileArgs or BitboxArgs
+    const uint64_t *base;    // byte offset of each instance
+    const uint64_t *tstart;  // ninst + 1 prefix sums of tile counts
+    uint32_t ninst;
+};
+
+__device__ __forceinline__ uint32_t group_instance(const GroupArgs &G, uint64_t b)
+{
+    uint32_t a = 0, e = G.ninst;
+    while (e - a > 1) {
+        const uint32_t m = (a + e) / 2;
+        if (G.tstart[m] <= b)
+            a = m;
+        else
+            e = m;
+    }
+    return a;
+}
+
+template <class Pat, int K>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8)))
+k_batch_tile(GroupArgs G, const uint8_t *__restrict__ in, uint8_t *__restrict__ out)
+{
+    using LDS = TileLds<Pat>;
+    __shared__ uint32_t s_buf[3][LDS::WORDS];
+    __shared__ __align__(16) uint32_t s_ring[kRingTab];
+    const uint64_t b = xcd_remap(blockIdx.x, gridDim.x);
+    const uint32_t i = group_instance(G, b);
+    const TileArgs &A = reinterpret_cast<const TileArgs *>(G.args)[i];
+    const uint64_t t = b - G.tstart[i], base = G.base[i];
+    if constexpr (K == 1) {
+        tile_body<Pat>(A, in + base, out + base, t, s_buf[0], s_buf[1]);
+    } else {
+        uint32_t *const buf[3] = {s_buf[0], s_buf[1], s_buf[2]};
+        tile_bodyK<Pat, K>(A, in + base, out + base, t, buf, s_ring);
+    }
+}
+
+template <class Pat, int K>
+__global__ void __launch_bounds__(kBxThreads) __attribute__((amdgpu_waves_per_eu(6)))
+k_batch_bitbox(GroupArgs G, const uint8_t *__restrict__ in, uint8_t *__restrict__ out)
+{
+    __shared__ uint32_t s_buf[2][kBxBuf];
+    __shared__ uint64_t s_nb[9];
+    __shared__ uint32_t s_ex;
+    const uint64_t b = blockIdx.x;
+    const uint32_t i = group_instance(G, b);
+    const BitboxArgs &A = reinterpret_cast<const BitboxArgs *>(G.args)[i];
+    const uint64_t base = G.base[i];
+    bitbox_tile<Pat, K>(A, in + base, out + base, b - G.tstart[i], s_buf, s_nb, &s_ex);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
+struct BatchGroup {
+    uint32_t kind;  // kBTri, kBTriPaper, kBVicsek or kBBits
+    int K;          // steps per launch
+    std::vector<uint32_t> members;
+    uint64_t ntiles;
+    void *d_args;
+    uint64_t *d_base, *d_tstart;
+};
+
 struct BatchHost {
+    std::vector<BatchGroup> groups;
+    bool has_rest;  // instances for the persistent launch
     int device;
     int cus;
     std::vector<BatchInst> inst;
@@ -234,6 +271,7 @@ const FractalHost &fractal_host_of(const sqz_fractal *f);  // api.hip
 
 static uint32_t kind_of(const FractalHost &F)
 {
+    if (F.bitbox) return kBBits;
     if (F.tile_kind == 1) return kBTri;
     if (F.tile_kind == 2) return kBTriPaper;
     if (F.tile_kind == 3) return kBVicsek;
@@ -241,23 +279,11 @@ static uint32_t kind_of(const FractalHost &F)
     return kBCell;
 }
 
-template <class Pat>
-static size_t tile_lds(bool multi)
-{
-    return multi ? (size_t)(ring_tab_offset<Pat>() + kRingTab) * 4 : (size_t)(2 * TileLds<Pat>::WORDS) * 4;
-}
+static bool grouped(uint32_t kind) { return kind == kBTri || kind == kBTriPaper || kind == kBVicsek || kind == kBBits; }
 
-static size_t tile_lds_of(const FractalHost &F, bool multi)
-{
-    switch (F.tile_kind) {
-    case 1: return tile_lds<PatTriangle>(multi);
-    case 2: return tile_lds<PatTrianglePaper>(multi);
-    default: return tile_lds<PatVicsek>(multi);
-    }
-}
-
-// Cost of a cell per path (for the static split): bit-sliced 2, expanded tile
-// xt_weight (tuned), thread-level 32.  Uploads the instances and prefix sums.
+// Cost of a cell per path of the persistent launch (for its static split):
+// expanded tile xt_weight (tuned), thread-level 32; grouped instances have no
+// units there.  Uploads the instances and prefix sums.
 static hipError_t upload_costs(BatchHost *H)
 {
     const size_t n = H->inst.size();
@@ -266,7 +292,7 @@ static hipError_t upload_costs(BatchHost *H)
     for (size_t i = 0; i < n; ++i) {
         BatchInst &I = H->inst[i];
         const uint32_t k = I.kind;
-        const uint64_t w = (k == kBTri || k == kBTriPaper || k == kBVicsek) ? 2 : (k == kBCell ? 32 : H->xt_weight);
+        const uint64_t w = k == kBCell ? 32 : H->xt_weight;
         I.cost_start = c;
         I.unit_cost = I.unit_cells * w;
         cs[i] = c;
@@ -311,13 +337,18 @@ sqz_status batch_create(const sqz_fractal *const *fr, int32_t count, BatchHost *
         I.cells = F.N;
         I.cell_start = cstart;
         I.P = F.P;
-        if (I.kind == kBTri || I.kind == kBTriPaper || I.kind == kBVicsek) {
-            I.tile = tile_args(F);
-            I.units = I.tile.ntiles;
-            I.unit_cells = I.tile.tile;
-            lds = std::max(lds, tile_lds_of(F, false));
-            ldsk = std::max(ldsk, tile_lds_of(F, true));
-            kmin = std::min(kmin, tile_steps_per_launch(F));
+        if (grouped(I.kind)) {
+            BatchGroup *G = nullptr;
+            for (BatchGroup &g : H->groups)
+                if (g.kind == I.kind) G = &g;
+            if (!G) {
+                H->groups.push_back(BatchGroup{I.kind, kMaxSteps, {}, 0, nullptr, nullptr, nullptr});
+                G = &H->groups.back();
+            }
+            G->members.push_back((uint32_t)i);
+            G->K = std::min(G->K, I.kind == kBBits ? bitbox_steps_per_launch(F) : tile_steps_per_launch(F));
+            I.units = 0;  // not in the persistent launch
+            I.unit_cells = 1;
         } else if (I.kind != kBCell) {
             const XTileConfig *X = F.xtile;
             I.x = X->base;
@@ -348,10 +379,12 @@ sqz_status batch_create(const sqz_fractal *const *fr, int32_t count, BatchHost *
                 }
             I.units = X->ntiles;
             I.unit_cells = X->KM;
+            H->has_rest = true;
         } else {
             I.units = (F.N + kCellUnit - 1) / kCellUnit;
             I.unit_cells = kCellUnit;
             kmin = 1;
+            H->has_rest = true;
         }
         snprintf(buf, sizeof buf, "%d:%d:%d;", (int)I.kind, F.s, F.r);
         H->key += buf;
@@ -366,13 +399,45 @@ sqz_status batch_create(const sqz_fractal *const *fr, int32_t count, BatchHost *
     H->total_cells = cstart;
     H->total_bytes = off;
     H->lds = std::max<size_t>(lds, 16);
-    H->K = count > 0 && kmin >= 2 ? std::min(kmin, 3) : 1;
+    H->K = H->has_rest && kmin >= 2 ? std::min(kmin, 3) : 1;
     H->ldsk = std::max<size_t>(ldsk, 16);
     H->d_inst = nullptr;
     H->d_cost_start = nullptr;
     H->cap = nullptr;
     H->gexec = nullptr;
     e = hipMalloc(&H->d_inst, sizeof(BatchInst) * count);
+    // groups: per-instance kernel arguments, bases and tile prefix sums
+    for (size_t g = 0; g < H->groups.size() && e == hipSuccess; ++g) {
+        BatchGroup &G = H->groups[g];
+        const size_t m = G.members.size();
+        const bool bits = G.kind == kBBits;
+        std::vector<TileArgs> ta(bits ? 0 : m);
+        std::vector<BitboxArgs> ba(bits ? m : 0);
+        std::vector<uint64_t> base(m), ts(m + 1);
+        uint64_t tiles = 0;
+        for (size_t q = 0; q < m; ++q) {
+            const FractalHost &F = fractal_host_of(fr[G.members[q]]);
+            ts[q] = tiles;
+            base[q] = H->offsets[G.members[q]];
+            if (bits) {
+                ba[q] = bitbox_args(F);
+                tiles += ba[q].ntiles;
+            } else {
+                ta[q] = tile_args(F);
+                tiles += ta[q].ntiles;
+            }
+        }
+        ts[m] = tiles;
+        G.ntiles = tiles;
+        const size_t asz = bits ? sizeof(BitboxArgs) * m : sizeof(TileArgs) * m;
+        e = hipMalloc(&G.d_args, asz);
+        if (e == hipSuccess) e = hipMemcpy(G.d_args, bits ? (const void *)ba.data() : (const void *)ta.data(), asz,
+                                           hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMalloc(&G.d_base, sizeof(uint64_t) * m);
+        if (e == hipSuccess) e = hipMemcpy(G.d_base, base.data(), sizeof(uint64_t) * m, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMalloc(&G.d_tstart, sizeof(uint64_t) * (m + 1));
+        if (e == hipSuccess) e = hipMemcpy(G.d_tstart, ts.data(), sizeof(uint64_t) * (m + 1), hipMemcpyHostToDevice);
+    }
     if (e == hipSuccess) e = hipMalloc(&H->d_cost_start, sizeof(uint64_t) * (count + 1));
     H->xt_weight = 4;
     {
@@ -391,10 +456,7 @@ sqz_status batch_create(const sqz_fractal *const *fr, int32_t count, BatchHost *
         }
     }
     if (e != hipSuccess) {
-        if (H->d_inst) (void)hipFree(H->d_inst);
-        if (H->d_cost_start) (void)hipFree(H->d_cost_start);
-        if (H->cap) (void)hipStreamDestroy(H->cap);
-        delete H;
+        batch_destroy(H);
         return hip_error(e, "batch setup");
     }
     H->max_wg_per_cu = per_cu < 1 ? 1u : (unsigned)per_cu;
@@ -415,6 +477,11 @@ void batch_destroy(BatchHost *H)
     if (H->cap) (void)hipStreamDestroy(H->cap);
     (void)hipFree(H->d_inst);
     (void)hipFree(H->d_cost_start);
+    for (BatchGroup &G : H->groups) {
+        (void)hipFree(G.d_args);
+        (void)hipFree(G.d_base);
+        (void)hipFree(G.d_tstart);
+    }
     delete H;
 }
 
@@ -438,9 +505,72 @@ static sqz_status launch_batch(const BatchHost *H, unsigned wg_per_cu, const uin
     return e == hipSuccess ? SQZ_OK : hip_error(e, "batch launch");
 }
 
+template <class Pat>
+static void launch_tile_group(const GroupArgs &A, unsigned grid, const uint8_t *in, uint8_t *out, int steps,
+                              hipStream_t st)
+{
+    switch (steps) {
+    case 1: hipLaunchKernelGGL((k_batch_tile<Pat, 1>), dim3(grid), dim3(kBlock), 0, st, A, in, out); break;
+    case 2: hipLaunchKernelGGL((k_batch_tile<Pat, 2>), dim3(grid), dim3(kBlock), 0, st, A, in, out); break;
+    case 3: hipLaunchKernelGGL((k_batch_tile<Pat, 3>), dim3(grid), dim3(kBlock), 0, st, A, in, out); break;
+    case 4: hipLaunchKernelGGL((k_batch_tile<Pat, 4>), dim3(grid), dim3(kBlock), 0, st, A, in, out); break;
+    case 5: hipLaunchKernelGGL((k_batch_tile<Pat, 5>), dim3(grid), dim3(kBlock), 0, st, A, in, out); break;
+    case 6: hipLaunchKernelGGL((k_batch_tile<Pat, 6>), dim3(grid), dim3(kBlock), 0, st, A, in, out); break;
+    default: hipLaunchKernelGGL((k_batch_tile<Pat, 7>), dim3(grid), dim3(kBlock), 0, st, A, in, out); break;
+    }
+}
+
+static void launch_bits_group(const GroupArgs &A, unsigned grid, const uint8_t *in, uint8_t *out, int steps,
+                              hipStream_t st)
+{
+    const dim3 g(grid), b(kBxThreads);
+    switch (steps) {
+    case 1: hipLaunchKernelGGL((k_batch_bitbox<PatCarpet, 1>), g, b, 0, st, A, in, out); break;
+    case 2: hipLaunchKernelGGL((k_batch_bitbox<PatCarpet, 2>), g, b, 0, st, A, in, out); break;
+    case 3: hipLaunchKernelGGL((k_batch_bitbox<PatCarpet, 3>), g, b, 0, st, A, in, out); break;
+    case 4: hipLaunchKernelGGL((k_batch_bitbox<PatCarpet, 4>), g, b, 0, st, A, in, out); break;
+    case 5: hipLaunchKernelGGL((k_batch_bitbox<PatCarpet, 5>), g, b, 0, st, A, in, out); break;
+    default: hipLaunchKernelGGL((k_batch_bitbox<PatCarpet, 6>), g, b, 0, st, A, in, out); break;
+    }
+}
+
+// One launch of `steps` (1..G.K) steps for every instance of group G.
+static sqz_status launch_group(const BatchGroup &G, const uint8_t *in, uint8_t *out, int steps, hipStream_t st)
+{
+    const GroupArgs A{G.d_args, G.d_base, G.d_tstart, (uint32_t)G.members.size()};
+    const unsigned grid = (unsigned)G.ntiles;
+    switch (G.kind) {
+    case kBTri: launch_tile_group<PatTriangle>(A, grid, in, out, steps, st); break;
+    case kBTriPaper: launch_tile_group<PatTrianglePaper>(A, grid, in, out, steps, st); break;
+    case kBVicsek: launch_tile_group<PatVicsek>(A, grid, in, out, steps, st); break;
+    default: launch_bits_group(A, grid, in, out, steps, st); break;
+    }
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SQZ_OK : hip_error(e, "batch group launch");
+}
+
+// All launches of `steps` steps: every group and the persistent launch follow
+// their own plan (each with the parity of `steps`).
+static sqz_status launch_all(const BatchHost *H, const uint8_t *a, const uint8_t *b, int32_t steps, hipStream_t st)
+{
+    sqz_status s2 = SQZ_OK;
+    uint8_t *const A = const_cast<uint8_t *>(a), *const B = const_cast<uint8_t *>(b);
+    for (size_t g = 0; g < H->groups.size() && s2 == SQZ_OK; ++g) {
+        const std::vector<int> plan = plan_launches(steps, H->groups[g].K);
+        for (size_t i = 0; i < plan.size() && s2 == SQZ_OK; ++i)
+            s2 = launch_group(H->groups[g], (i & 1) ? B : A, (i & 1) ? A : B, plan[i], st);
+    }
+    if (H->has_rest) {
+        const std::vector<int> plan = plan_launches(steps, H->K);
+        for (size_t i = 0; i < plan.size() && s2 == SQZ_OK; ++i)
+            s2 = launch_batch(H, H->wg_per_cu, (i & 1) ? B : A, (i & 1) ? A : B, plan[i], st);
+    }
+    return s2;
+}
+
 sqz_status batch_step(const BatchHost *H, const uint8_t *in, uint8_t *out, hipStream_t st)
 {
-    return launch_batch(H, H->wg_per_cu, in, out, 1, st);
+    return launch_all(H, in, out, 1, st);
 }
 
 sqz_status batch_run(BatchHost *H, uint8_t *a, uint8_t *b, int32_t steps, hipStream_t st)
@@ -454,10 +584,7 @@ sqz_status batch_run(BatchHost *H, uint8_t *a, uint8_t *b, int32_t steps, hipStr
         }
         hipError_t e = hipStreamBeginCapture(H->cap, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_error(e, "hipStreamBeginCapture");
-        sqz_status s2 = SQZ_OK;
-        const std::vector<int> plan = plan_launches(steps, H->K);
-        for (size_t i = 0; i < plan.size() && s2 == SQZ_OK; ++i)
-            s2 = launch_batch(H, H->wg_per_cu, (i & 1) ? b : a, (i & 1) ? a : b, plan[i], H->cap);
+        const sqz_status s2 = launch_all(H, a, b, steps, H->cap);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(H->cap, &g);
         if (s2 != SQZ_OK) {
@@ -481,6 +608,10 @@ sqz_status batch_run(BatchHost *H, uint8_t *a, uint8_t *b, int32_t steps, hipStr
 
 sqz_status batch_autotune(BatchHost *H, uint8_t *a, uint8_t *b, hipStream_t st, unsigned *best_out)
 {
+    if (!H->has_rest) {  // every instance is in a group: nothing to tune
+        if (best_out) *best_out = H->wg_per_cu;
+        return SQZ_OK;
+    }
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return set_error(SQZ_ERR_HIP, "hipEventCreate failed");
@@ -542,7 +673,12 @@ uint64_t batch_total_bytes(const BatchHost *H) { return H->total_bytes; }
 uint64_t batch_offset(const BatchHost *H, int32_t i) { return H->offsets[i]; }
 int32_t batch_count(const BatchHost *H) { return (int32_t)H->inst.size(); }
 unsigned batch_wg_per_cu(const BatchHost *H) { return H->wg_per_cu; }
-int batch_steps_per_launch(const BatchHost *H) { return H->K; }
+int batch_steps_per_launch(const BatchHost *H)
+{
+    int k = H->has_rest ? H->K : kMaxSteps;
+    for (const BatchGroup &G : H->groups) k = std::min(k, G.K);
+    return k < 1 ? 1 : k;
+}
 uint64_t batch_total_cells(const BatchHost *H) { return H->total_cells; }
 
 }  // namespace sqz

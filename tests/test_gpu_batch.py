@@ -48,15 +48,17 @@ def test_small_mixed_batch_matches_oracle():
 
 
 def test_multi_step_runs_equal_eager_steps():
-    """Every instance has multi-step tiles (single-tile ones included), so runs take
-    three steps per launch; any step count equals that many one-step launches."""
+    """Every instance is in a group of a multi-step kernel (single-tile ones
+    included): triangle and Vicsek tiles take seven steps per launch, carpet bit
+    rows six, so the batch reports six; any step count equals that many one-step
+    launches."""
     torch = torch_or_skip()
     spec = [("triangle", 9), ("carpet", 5), ("vicsek", 6), ("carpet", 2), ("triangle", 12), ("vicsek", 3),
             ("triangle_paper", 10), ("carpet", 6)]
     fr, B = build(spec)
-    assert B.steps_per_launch == 3
+    assert B.steps_per_launch == 6
     seeds = [31 * i + 1 for i in range(len(fr))]
-    for steps in (1, 2, 3, 4, 5, 7, 9):
+    for steps in (1, 2, 3, 4, 5, 6, 7, 9, 13, 14):
         a, b = B.fill_bernoulli(seeds, 0.5), B.empty_state()
         res = B.run(a, b, steps)
         assert res is (a if steps % 2 == 0 else b)
@@ -107,6 +109,29 @@ def test_graph_replays_equal_eager_steps():
     g.copy_(g2)
     h.zero_()
     assert torch.equal(B.run(g, h, 6), want)
+
+
+def test_mixed_groups_and_persistent_launch():
+    """Groups (tiles, bit rows) and instances of the persistent launch (expanded
+    tiles of another pattern, thread-level cells) in one batch: runs of several
+    lengths equal the instances' own single-fractal runs."""
+    torch = torch_or_skip()
+    import paper_2201_00613_amd as sqz
+
+    wide = (4, ((0, 0), (1, 0), (3, 0), (0, 1), (2, 1), (3, 1), (1, 2), (2, 2), (0, 3), (3, 3)))
+    import fractals as FR
+
+    fr = [sqz.Fractal(*FR.ALL["triangle"], 11), sqz.Fractal(*wide, 5), sqz.Fractal(*FR.ALL["carpet"], 1),
+          sqz.Fractal(*FR.ALL["carpet"], 6), sqz.Fractal(*FR.ALL["vicsek"], 7), sqz.Fractal(*FR.ALL["triangle"], 2)]
+    B = sqz.Batch(fr)
+    seeds = [3, 4, 5, 6, 7, 8]
+    for steps in (1, 4, 7, 10):
+        a = B.fill_bernoulli(seeds, 0.5)
+        res = B.run(a, B.empty_state(), steps)
+        for i, F in enumerate(fr):
+            x = F.fill_bernoulli(seeds[i], 0.5)
+            y = F.compact_run(x, torch.empty_like(x), steps)
+            assert torch.equal(B.instance(res, i), y), (i, steps)
 
 
 def test_autotune_keeps_results():
