@@ -132,7 +132,47 @@ def cpu_baseline(r: int, seed: int, p: float, min_sec: float, max_steps: int) ->
         steps += 1
     sec = time.perf_counter() - t0
     return {"value": O.N * steps / sec, "unit": "cell-updates/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{steps} full B3/S23 step(s) of the level-{r} triangle ({O.N} cells each), {sec:.1f} s"}
+            "sample": f"{steps} full B3/S23 step(s) of the level-{r} triangle ({O.N} cells each), {sec:.1f} s",
+            "cpu_model": cpu_model(), "single_core": single_core_baseline(r, seed, p)}
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+SINGLE_CORE = '''
+import sys, time
+sys.path.insert(0, {root!r})
+import oracle
+O = oracle.Fractal({s}, {offs!r}, {r})
+state = O.fill_compact({seed}, {p})
+t0 = time.perf_counter()
+O.life_compact(state, 0, {cells})
+print(time.perf_counter() - t0, oracle.num_threads())
+'''
+
+
+def single_core_baseline(r: int, seed: int, p: float, cells: int = 1 << 21) -> dict:
+    """The oracle on one host thread (a child process with OMP_NUM_THREADS=1): one step
+    of the first `cells` compact cells of the same workload."""
+    import subprocess
+
+    code = SINGLE_CORE.format(root=ROOT, s=TRIANGLE[0], offs=[list(o) for o in TRIANGLE[1]], r=r, seed=seed, p=p,
+                              cells=cells)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        res = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+        sec, threads = res.stdout.split()
+        return {"value": cells / float(sec), "unit": "cell-updates/s", "cores": int(threads),
+                "sample": f"one B3/S23 step of compact cells [0, {cells}) of the level-{r} triangle, {float(sec):.2f} s"}
+    except (subprocess.SubprocessError, ValueError) as e:
+        return {"value": None, "error": str(e)[:200]}
 
 
 def maps_leg(torch, F, seed, p, steps: int) -> dict:
