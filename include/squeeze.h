@@ -145,9 +145,10 @@ typedef struct sqz_info {
     uint64_t compact_h;  /* height, k^floor(r/2) (Section "Compacting NBB Fractals") */
     int32_t has_tile;    /* 1 if SQZ_IMPL_TILE is available for this pattern */
     int32_t xtile_level; /* level of the expanded tiles of SQZ_IMPL_XTILE (0 if none) */
-    int32_t run_steps_per_launch; /* Life steps per launch in sqz_compact_run with 16-byte aligned
-                                     buffers: up to 7 with multi-step tiled kernels (temporal
-                                     blocking), else 1 */
+    int32_t run_steps_per_launch; /* Life steps per launch in sqz_compact_run with aligned buffers:
+                                     up to 10 with multi-step tiled kernels (temporal blocking;
+                                     16-byte alignment), 6 with bit-row tiles (8-byte), 3 with
+                                     multi-step expanded tiles, else 1 */
     int32_t bits_level;  /* level M of the bit-row tiles of SQZ_IMPL_BITS (0 if none) */
 } sqz_info;
 

@@ -516,7 +516,10 @@ static void launch_tile_group(const GroupArgs &A, unsigned grid, const uint8_t *
     case 4: hipLaunchKernelGGL((k_batch_tile<Pat, 4>), dim3(grid), dim3(kBlock), 0, st, A, in, out); break;
     case 5: hipLaunchKernelGGL((k_batch_tile<Pat, 5>), dim3(grid), dim3(kBlock), 0, st, A, in, out); break;
     case 6: hipLaunchKernelGGL((k_batch_tile<Pat, 6>), dim3(grid), dim3(kBlock), 0, st, A, in, out); break;
-    default: hipLaunchKernelGGL((k_batch_tile<Pat, 7>), dim3(grid), dim3(kBlock), 0, st, A, in, out); break;
+    case 7: hipLaunchKernelGGL((k_batch_tile<Pat, 7>), dim3(grid), dim3(kBlock), 0, st, A, in, out); break;
+    case 8: hipLaunchKernelGGL((k_batch_tile<Pat, 8>), dim3(grid), dim3(kBlock), 0, st, A, in, out); break;
+    case 9: hipLaunchKernelGGL((k_batch_tile<Pat, 9>), dim3(grid), dim3(kBlock), 0, st, A, in, out); break;
+    default: hipLaunchKernelGGL((k_batch_tile<Pat, 10>), dim3(grid), dim3(kBlock), 0, st, A, in, out); break;
     }
 }
 

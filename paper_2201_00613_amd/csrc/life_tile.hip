@@ -119,7 +119,7 @@ sqz_status prepare(FractalHost &F)
 
     // rings 2..kMaxSteps (several steps per launch): breadth-first from ring 1
     // over member cells outside the tile (ring d = graph distance d from the
-    // tile); each must fit one LDS word and all rings kMaxRing lanes.
+    // tile); all rings must fit kMaxRing lanes.
     std::vector<Slot> ring = slots;  // rings in order, ring 1 first
     std::vector<uint32_t> start = {0, (uint32_t)slots.size()};
     auto find = [&](int64_t qx, int64_t qy) {
@@ -145,7 +145,7 @@ sqz_status prepare(FractalHost &F)
                 }
         start.push_back((uint32_t)ring.size());
         // (ring cells must also lie in adjacent tiles: d < side)
-        if (T->nthalo == 0 || start[d] - start[d - 1] > 32 || start[d] > (uint32_t)kMaxRing || d >= side) break;
+        if (T->nthalo == 0 || start[d] > (uint32_t)kMaxRing || d >= side) break;
         ksteps = (uint32_t)d;  // rings 1..d fit: d steps per launch
     }
     T->ksteps = ksteps;
@@ -178,7 +178,8 @@ sqz_status prepare(FractalHost &F)
             const int64_t g = virt_of(floor_div(s.px, box), floor_div(s.py, box));
             return entry(LDS::VIRT + (uint32_t)g, (uint32_t)(s.idx % PL.nc));
         }
-        return entry(LDS::RING2 + d - 2, (uint32_t)i - T->ring_start[d - 1]);
+        const uint32_t k = (uint32_t)i - T->nthalo;  // rings 2.. packed in order
+        return entry(LDS::RING2 + k / 32, k % 32);
     };
     std::vector<uint32_t> home(T->tstride ? T->tstride : 1, zero_entry);
     for (uint32_t i = 0; i < T->tstride; ++i) home[i] = ring_entry(i);
@@ -294,7 +295,10 @@ sqz_status launch(const FractalHost &F, const uint8_t *in, uint8_t *out, int ste
     case 4: hipLaunchKernelGGL((k_life_tileK<Pat, 4, NT>), dim3((unsigned)grid), dim3(NT), 0, st, A, in, out); break;
     case 5: hipLaunchKernelGGL((k_life_tileK<Pat, 5, NT>), dim3((unsigned)grid), dim3(NT), 0, st, A, in, out); break;
     case 6: hipLaunchKernelGGL((k_life_tileK<Pat, 6, NT>), dim3((unsigned)grid), dim3(NT), 0, st, A, in, out); break;
-    default: hipLaunchKernelGGL((k_life_tileK<Pat, 7, NT>), dim3((unsigned)grid), dim3(NT), 0, st, A, in, out); break;
+    case 7: hipLaunchKernelGGL((k_life_tileK<Pat, 7, NT>), dim3((unsigned)grid), dim3(NT), 0, st, A, in, out); break;
+    case 8: hipLaunchKernelGGL((k_life_tileK<Pat, 8, NT>), dim3((unsigned)grid), dim3(NT), 0, st, A, in, out); break;
+    case 9: hipLaunchKernelGGL((k_life_tileK<Pat, 9, NT>), dim3((unsigned)grid), dim3(NT), 0, st, A, in, out); break;
+    default: hipLaunchKernelGGL((k_life_tileK<Pat, 10, NT>), dim3((unsigned)grid), dim3(NT), 0, st, A, in, out); break;
     }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? SQZ_OK : hip_error(e, "compact step (tile) launch");

@@ -77,9 +77,9 @@ constexpr int cpow(int b, int e)
 }
 
 constexpr int kMaxHalo = 16;      // halo cells per block
-constexpr int kMaxSteps = 7;      // Life steps per launch of the multi-step tiled kernel
+constexpr int kMaxSteps = 10;     // Life steps per launch of the multi-step tiled kernel
 constexpr int kMaxTileHalo = 32;  // halo cells per tile (one LDS word of bits)
-constexpr int kMaxRing = 128;     // ring cells of all rings (two waves)
+constexpr int kMaxRing = 256;     // ring cells of all rings (one lane each)
 constexpr int kRingTab = kMaxRing * 9;  // LDS words of a tile's ring tables: 8 sources per cell, then homes
 constexpr int kBlock = 256;
 
@@ -281,7 +281,7 @@ inline TileArgs tile_args(const FractalHost &F)
 // of the block, bits from K^J up zero): blocks [0, NBMAX), two words that
 // stay zero (absent neighbours), one word per adjacent block of another tile
 // that holds ring-1 cells (each at its bit within that block), then the bits
-// of rings 2..kMaxSteps, one word per ring.  Ring d holds the cells of other
+// of rings 2..kMaxSteps, packed in ring order.  Ring d holds the cells of other
 // tiles at graph distance d from the tile (each neighbour of a ring-d cell is
 // in ring d-1, d or d+1, or in the tile for d = 1).  The layout does not
 // depend on where the tile starts within a 32-byte word, so every table that
@@ -296,7 +296,7 @@ struct TileLds {
     static constexpr int ZERO = NBMAX;
     static constexpr int VIRT = ZERO + 2;
     static constexpr int RING2 = VIRT + kMaxTileHalo;
-    static constexpr int WORDS = RING2 + kMaxSteps - 1;
+    static constexpr int WORDS = RING2 + (kMaxRing + 31) / 32;
     static constexpr int STAGE = (TMAX + 31 + 31) / 32 + 1;
     static constexpr int NGRP = PlanOf<Pat>::value.ngrp > 0 ? PlanOf<Pat>::value.ngrp : 1;
     static_assert(STAGE <= NBMAX, "packed tile overlaps the special words");
@@ -652,7 +652,7 @@ __device__ __forceinline__ void tile_bodyK(const TileArgs &A, const uint8_t *__r
         if (j < K) {
             uint32_t *clr = buf[(j + 1) % 3];
             if (tid < LDS::WORDS - LDS::VIRT) clr[LDS::VIRT + tid] = 0;
-            if (tid < A.ring_start[K - j]) {  // waves 0 and 1
+            if (tid < A.ring_start[K - j]) {
                 const uint4 e0 = *reinterpret_cast<const uint4 *>(s_ring + tid * 8);
                 const uint4 e1 = *reinterpret_cast<const uint4 *>(s_ring + tid * 8 + 4);
                 const uint32_t cnt = lds_bit(src, e0.x) + lds_bit(src, e0.y) + lds_bit(src, e0.z) +
