@@ -401,7 +401,9 @@ def main() -> int:
                    "tile_level": F.tile_level, "steps_per_launch": args.steps / launches,
                    "note": "2 x 43 MB working set is Infinity-Cache resident"},
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gbs / HBM_PEAK_GBS, "traffic": None},
+                     "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                     # 2 B per cell-update over the step time: the bytes one-step launches would move
+                     "step_equivalent_gbs": BYTES_PER_UPDATE * F.cells * args.steps / sec / 1e9},
     }
     if args.impl == "auto" and F.run_steps_per_launch >= 2:
         s1 = compact_run(torch, F, seed, p, args.steps, args.warmup, "tile")
