@@ -320,8 +320,11 @@ SQZ_API sqz_status sqz_bf16_decode(const sqz_fractal *f, const uint16_t *d_b, fl
 
 /*
  * Batched Life: `count` independent fractals (handles may repeat and may mix
- * replica patterns and levels) advanced together, one persistent launch per
- * step (the batched form of the method's data-parallel step).  The handles
+ * replica patterns and levels) advanced together (the batched form of the
+ * method's data-parallel step).  Instances with a tiled kernel run either as
+ * one launch per pattern group or as one persistent launch over all of them
+ * (sqz_batch_set_tiled_launch; sqz_batch_autotune times both); the others
+ * (expanded tiles, thread level) share one persistent launch.  The handles
  * must outlive the batch and live on the current device.  Instance i owns
  * bytes [offsets[i], offsets[i] + cells_i) of one state buffer of
  * offsets[count] bytes (sqz_batch_layout); the gaps are padding.  A batch is
@@ -340,21 +343,37 @@ SQZ_API sqz_status sqz_batch_layout(const sqz_batch *b, uint64_t *offsets, uint6
 SQZ_API sqz_status sqz_batch_fill_bernoulli(const sqz_batch *b, const uint64_t *seeds, double p, uint8_t *d_state,
                                             void *stream);
 
-/* One step of every instance: one kernel launch.  Buffers 16-byte aligned, non-overlapping. */
+/* One step of every instance.  Buffers 16-byte aligned, non-overlapping. */
 SQZ_API sqz_status sqz_batch_step(const sqz_batch *b, const uint8_t *d_in, uint8_t *d_out, void *stream);
 
-/* `steps` steps ping-ponging from d_a (result in d_a if steps is even, else d_b).  Each launch takes
- * up to sqz_batch_steps_per_launch steps (multi-step tiles, when every instance has them; the
- * launch count keeps the parity of `steps`).  For steps >= 2 the launches are captured once into a
- * hipGraph (cached for the same buffers and step count) and replayed. */
+/* `steps` steps ping-ponging from d_a (result in d_a if steps is even, else d_b).  Each launch form
+ * follows its own plan of launches of up to its steps per launch (multi-step tiles), with the
+ * parity of `steps`.  For steps >= 2 all launches are captured once into a hipGraph (cached for
+ * the same buffers and step count) and replayed. */
 SQZ_API sqz_status sqz_batch_run(sqz_batch *b, uint8_t *d_a, uint8_t *d_b, int32_t steps, void *stream);
 
-/* Most steps one launch of sqz_batch_run takes (1 when some instance has no multi-step tiles). */
+/* Steps every instance advances per launch of sqz_batch_run at least: the smallest steps per
+ * launch over the launch forms in use (1 when some instance has no multi-step tiles). */
 SQZ_API sqz_status sqz_batch_steps_per_launch(const sqz_batch *b, int32_t *steps);
 
-/* Time candidate grid sizes (workgroups per compute unit) on the given buffers (their contents are
- * advanced by a few steps) and keep the fastest for this batch and for later batches of the same
- * composition in this process.  *wg_per_cu (may be NULL) receives the choice. */
+/* Launch form of the instances with a tiled kernel (triangle, its mirror image, Vicsek cross:
+ * bit-sliced tiles; carpet: bit rows):
+ *   persistent = 0: one launch per pattern group, one workgroup per tile (the default);
+ *   persistent = 1: one persistent launch over all of them, wg_per_cu workgroups per compute unit,
+ *                   each taking an equal share of the tiles' cells.
+ * steps_per_launch: 0 keeps the current value, else 1 .. the most the instances allow (for
+ * groups, capped at each group's most).  wg_per_cu: 0 keeps the current value, else 1 .. the
+ * most that are resident.  Other values: SQZ_ERR_INVALID.  Results do not depend on the form. */
+SQZ_API sqz_status sqz_batch_set_tiled_launch(sqz_batch *b, int32_t persistent, int32_t steps_per_launch,
+                                              int32_t wg_per_cu);
+
+/* Time candidate launch shapes on the given buffers (their contents are advanced by a few steps)
+ * and keep the fastest for this batch and for later batches of the same composition in this
+ * process: for the tiled instances, steps per launch of each pattern group against one
+ * persistent launch (steps per launch x workgroups per compute unit); for the others, workgroups
+ * per compute unit and the expanded-tile cost weight.  *wg_per_cu (may be NULL) receives the
+ * workgroups per compute unit of the persistent launch timed for the tiled instances (of the
+ * other launch when there are none). */
 SQZ_API sqz_status sqz_batch_autotune(sqz_batch *b, uint8_t *d_a, uint8_t *d_b, void *stream, int32_t *wg_per_cu);
 
 /* Static text for a status code. */

@@ -368,4 +368,16 @@ class Batch:
         w = ctypes.c_int32()
         with dev:
             check(lib().sqz_batch_autotune(self._h, _ptr(a), _ptr(b), st, ctypes.byref(w)))
+        self._refresh_steps()
         return int(w.value)
+
+    def set_tiled_launch(self, persistent: bool, steps_per_launch: int = 0, wg_per_cu: int = 0):
+        """Launch form of the instances with a tiled kernel: one launch per pattern group
+        (persistent=False) or one persistent launch over all of them (sqz_batch_set_tiled_launch)."""
+        check(lib().sqz_batch_set_tiled_launch(self._h, int(persistent), steps_per_launch, wg_per_cu))
+        self._refresh_steps()
+
+    def _refresh_steps(self):
+        k = ctypes.c_int32()
+        check(lib().sqz_batch_steps_per_launch(self._h, ctypes.byref(k)))
+        self.steps_per_launch = int(k.value)

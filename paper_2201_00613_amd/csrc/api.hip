@@ -776,6 +776,12 @@ sqz_status sqz_batch_run(sqz_batch *b, uint8_t *d_a, uint8_t *d_b, int32_t steps
     return batch_run(b->h, d_a, d_b, steps, (hipStream_t)stream);
 }
 
+sqz_status sqz_batch_set_tiled_launch(sqz_batch *b, int32_t persistent, int32_t steps_per_launch, int32_t wg_per_cu)
+{
+    if (!b) return set_error(SQZ_ERR_INVALID, "batch is NULL");
+    return batch_set_tiled(b->h, persistent, steps_per_launch, wg_per_cu);
+}
+
 sqz_status sqz_batch_autotune(sqz_batch *b, uint8_t *d_a, uint8_t *d_b, void *stream, int32_t *wg_per_cu)
 {
     sqz_status st = check_batch_buffers(b, d_a, d_b);

@@ -2,24 +2,24 @@
 // advanced together.
 //
 // Every instance owns a 256-byte aligned range of one state buffer.
-// Instances with a tiled kernel form groups by pattern (bit-sliced tiles of
-// the triangle, its mirror image and the Vicsek cross; bit-row tiles of the
-// carpet): a group is one launch with one workgroup per tile of any of its
-// instances, the same device functions as the single-fractal kernels, and
-// its own number of steps per launch.  The remaining instances (expanded
-// tiles of any pattern, runs of 4096 cells of the thread-level path for
-// instances too small to tile) share one persistent launch: their units form
-// one sequence, and workgroup b takes the units whose first cost unit falls
-// in the b-th equal share of the total cost, so each workgroup walks
-// adjacent tiles of one or two instances; the expanded-tile tables are
-// reloaded only when a workgroup moves to an instance with a different tile
-// configuration.  Instances are independent, so every group follows its own
-// launch plan; each plan has the parity of the step count, so all results
-// land in the same buffer.
+// Instances with a tiled kernel (bit-sliced tiles of the triangle, its mirror
+// image and the Vicsek cross; bit rows of the carpet) run in one of two
+// forms: one launch per pattern group, with one workgroup per tile of any of
+// the group's instances and the group's own steps per launch; or one
+// persistent launch over all of them, in which workgroup b takes the tiles
+// whose first cell falls in the b-th equal share of their cells.  The tile
+// bodies are the single-fractal kernels' device functions.  The remaining
+// instances (expanded tiles of any pattern, runs of 4096 cells of the
+// thread-level path for instances too small to tile) share one persistent
+// launch balanced the same way by a per-path cost; the expanded-tile tables
+// are reloaded only when a workgroup moves to an instance with a different
+// tile configuration.  Instances are independent, so every launch form
+// follows its own plan of launches; each plan has the parity of the step
+// count, so all results land in the same buffer.
 //
 // Runs of several steps are captured once into a hipGraph (kernel nodes only)
-// and replayed; an autotuner times candidate grid sizes of the persistent
-// launch on the caller's buffers and keeps the fastest, cached per batch
+// and replayed; an autotuner times the launch forms, steps per launch and
+// grid sizes on the caller's buffers and keeps the fastest, cached per batch
 // composition.
 #include <string.h>
 
@@ -226,6 +226,111 @@ k_batch_bitbox(GroupArgs G, const uint8_t *__restrict__ in, uint8_t *__restrict_
     bitbox_tile<Pat, K>(A, in + base, out + base, b - G.tstart[i], s_buf, s_nb, &s_ex);
 }
 
+// Instance of the persistent tiled launch (patterns with a tiled kernel).
+struct TiledInst {
+    uint32_t kind;        // kBTri, kBTriPaper, kBVicsek or kBBits
+    uint32_t pad;
+    uint64_t base;        // byte offset of the instance in the state buffer
+    uint64_t units;       // tiles
+    uint64_t unit_cells;  // cells per tile
+    uint64_t cost_start;  // first cost unit (cell) of the instance
+    TileArgs t;
+    BitboxArgs x;
+};
+
+struct TiledArgs {
+    const TiledInst *inst;
+    const uint64_t *cost_start;  // ninst + 1 entries
+    uint32_t ninst;
+    uint64_t total_cost;
+};
+
+// LDS of a tile body: the bit-sliced layout (three state buffers, the ring
+// tables 16-byte aligned) or the bit-row layout (two row buffers, nine
+// bases, one flag word), whichever the kind uses; sizes in bytes.
+template <class Pat>
+__host__ __device__ constexpr size_t tiled_ring_offset()
+{
+    return (3 * (size_t)TileLds<Pat>::WORDS + 3) / 4 * 4;  // words
+}
+template <class Pat>
+__host__ __device__ constexpr size_t tiled_lds_bytes()
+{
+    return (tiled_ring_offset<Pat>() + kRingTab) * 4;
+}
+constexpr size_t kBitsLds = 2 * (size_t)kBxBuf * 4 + 9 * 8 + 16;
+
+template <class Pat, int K>
+__device__ __forceinline__ void tiled_unit(const TileArgs &A, const uint8_t *in, uint8_t *out, uint64_t t,
+                                           unsigned char *smem)
+{
+    using LDS = TileLds<Pat>;
+    uint32_t *w = reinterpret_cast<uint32_t *>(smem);
+    if constexpr (K == 1) {
+        tile_body<Pat>(A, in, out, t, w, w + LDS::WORDS);
+    } else {
+        uint32_t *const buf[3] = {w, w + LDS::WORDS, w + 2 * LDS::WORDS};
+        tile_bodyK<Pat, K>(A, in, out, t, buf, w + tiled_ring_offset<Pat>());
+    }
+}
+
+template <int K>
+__device__ __forceinline__ void bits_unit(const BitboxArgs &A, const uint8_t *in, uint8_t *out, uint64_t t,
+                                          unsigned char *smem)
+{
+    if constexpr (K <= kBxMaxSteps) {
+        uint32_t(*s_buf)[kBxBuf] = reinterpret_cast<uint32_t(*)[kBxBuf]>(smem);
+        uint64_t *s_nb = reinterpret_cast<uint64_t *>(smem + ((2 * (size_t)kBxBuf * 4 + 7) & ~(size_t)7));
+        bitbox_tile<PatCarpet, K>(A, in, out, t, s_buf, s_nb, reinterpret_cast<uint32_t *>(s_nb + 9));
+    }
+}
+
+// K Life steps of every instance with a tiled kernel, one persistent launch:
+// the tiles of all such instances form one sequence weighted by cells;
+// workgroup b takes the tiles whose first cell falls in the b-th equal share
+// and runs each with its pattern's tile body (bit-sliced tiles of the
+// triangle, its mirror image and the Vicsek cross; bit rows of the carpet).
+template <int K>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6)))
+k_batch_tiles(TiledArgs B, const uint8_t *__restrict__ in, uint8_t *__restrict__ out)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint64_t lo = B.total_cost * blockIdx.x / gridDim.x;
+    const uint64_t hi = B.total_cost * (blockIdx.x + 1) / gridDim.x;
+    uint32_t a = 0, e = B.ninst;
+    while (e - a > 1) {
+        const uint32_t m = (a + e) / 2;
+        if (B.cost_start[m] <= lo)
+            a = m;
+        else
+            e = m;
+    }
+    uint32_t i = a;
+    uint64_t j = 0;
+    {
+        const TiledInst &I = B.inst[i];
+        j = (lo - I.cost_start + I.unit_cells - 1) / I.unit_cells;
+    }
+    while (i < B.ninst) {
+        const TiledInst &I = B.inst[i];
+        if (j >= I.units) {
+            ++i;
+            j = 0;
+            continue;
+        }
+        if (I.cost_start + j * I.unit_cells >= hi) break;
+        const uint8_t *ii = in + I.base;
+        uint8_t *oo = out + I.base;
+        switch (I.kind) {
+        case kBTri: tiled_unit<PatTriangle, K>(I.t, ii, oo, j, smem); break;
+        case kBTriPaper: tiled_unit<PatTrianglePaper, K>(I.t, ii, oo, j, smem); break;
+        case kBVicsek: tiled_unit<PatVicsek, K>(I.t, ii, oo, j, smem); break;
+        default: bits_unit<K>(I.x, ii, oo, j, smem); break;
+        }
+        ++j;  // every tile body ends with a barrier: LDS is free for the next tile
+    }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -233,7 +338,7 @@ k_batch_bitbox(GroupArgs G, const uint8_t *__restrict__ in, uint8_t *__restrict_
 // ---------------------------------------------------------------------------
 struct BatchGroup {
     uint32_t kind;  // kBTri, kBTriPaper, kBVicsek or kBBits
-    int K;          // steps per launch
+    int K, K_max;   // steps per launch: chosen, most allowed
     std::vector<uint32_t> members;
     uint64_t ntiles;
     void *d_args;
@@ -241,8 +346,18 @@ struct BatchGroup {
 };
 
 struct BatchHost {
+    // instances with a tiled kernel run either as one launch per pattern group
+    // or as one persistent launch over all of them (the autotuner picks)
     std::vector<BatchGroup> groups;
-    bool has_rest;  // instances for the persistent launch
+    bool persistent_tiles;
+    std::vector<TiledInst> tiled;
+    TiledInst *d_tiled;
+    uint64_t *d_tcost;
+    uint64_t tcost_total;
+    size_t tlds;
+    int Kt_max, Kt;             // steps per launch: most allowed, chosen
+    unsigned twg, twg_max;      // workgroups per CU: chosen, most resident
+    bool has_rest;  // instances for the persistent expanded-tile / thread-level launch
     int device;
     int cus;
     std::vector<BatchInst> inst;
@@ -265,7 +380,13 @@ struct BatchHost {
 };
 
 static std::mutex g_tune_mu;
-static std::map<std::string, std::pair<unsigned, unsigned>> g_tune_cache;  // key -> (wg per CU, xt weight)
+struct TuneResult {
+    unsigned wg, xt_weight, twg;
+    int Kt;
+    bool persistent_tiles;
+    std::vector<int> group_K;
+};
+static std::map<std::string, TuneResult> g_tune_cache;  // batch composition -> tuned launch shapes
 
 const FractalHost &fractal_host_of(const sqz_fractal *f);  // api.hip
 
@@ -318,6 +439,7 @@ sqz_status batch_create(const sqz_fractal *const *fr, int32_t count, BatchHost *
     }
     hipDeviceProp_t prop;
     H->cus = hipGetDeviceProperties(&prop, H->device) == hipSuccess ? prop.multiProcessorCount : 256;
+    H->Kt_max = kMaxSteps;
     std::map<std::string, uint32_t> xcfg_ids;
     std::vector<uint64_t> cell_start(count + 1);
     uint64_t off = 0, cstart = 0;
@@ -338,16 +460,38 @@ sqz_status batch_create(const sqz_fractal *const *fr, int32_t count, BatchHost *
         I.cell_start = cstart;
         I.P = F.P;
         if (grouped(I.kind)) {
+            TiledInst T;
+            memset(&T, 0, sizeof T);
+            T.kind = I.kind;
+            T.base = off;
+            if (I.kind == kBBits) {
+                T.x = bitbox_args(F);
+                T.units = T.x.ntiles;
+                T.unit_cells = T.x.tile;
+                H->Kt_max = std::min(H->Kt_max, bitbox_steps_per_launch(F));
+                H->tlds = std::max(H->tlds, kBitsLds);
+            } else {
+                T.t = tile_args(F);
+                T.units = T.t.ntiles;
+                T.unit_cells = T.t.tile;
+                H->Kt_max = std::min(H->Kt_max, tile_steps_per_launch(F));
+                H->tlds = std::max(H->tlds, I.kind == kBVicsek ? tiled_lds_bytes<PatVicsek>()
+                                                                : tiled_lds_bytes<PatTriangle>());
+            }
+            T.cost_start = H->tcost_total;
+            H->tcost_total += T.units * T.unit_cells;
+            H->tiled.push_back(T);
             BatchGroup *G = nullptr;
             for (BatchGroup &g : H->groups)
                 if (g.kind == I.kind) G = &g;
             if (!G) {
-                H->groups.push_back(BatchGroup{I.kind, kMaxSteps, {}, 0, nullptr, nullptr, nullptr});
+                H->groups.push_back(BatchGroup{I.kind, kMaxSteps, kMaxSteps, {}, 0, nullptr, nullptr, nullptr});
                 G = &H->groups.back();
             }
             G->members.push_back((uint32_t)i);
-            G->K = std::min(G->K, I.kind == kBBits ? bitbox_steps_per_launch(F) : tile_steps_per_launch(F));
-            I.units = 0;  // not in the persistent launch
+            G->K_max = std::min(G->K_max, I.kind == kBBits ? bitbox_steps_per_launch(F) : tile_steps_per_launch(F));
+            G->K = G->K_max;
+            I.units = 0;  // not in the expanded-tile / thread-level launch
             I.unit_cells = 1;
         } else if (I.kind != kBCell) {
             const XTileConfig *X = F.xtile;
@@ -406,6 +550,24 @@ sqz_status batch_create(const sqz_fractal *const *fr, int32_t count, BatchHost *
     H->cap = nullptr;
     H->gexec = nullptr;
     e = hipMalloc(&H->d_inst, sizeof(BatchInst) * count);
+    if (e == hipSuccess) e = hipMalloc(&H->d_cost_start, sizeof(uint64_t) * (count + 1));
+    // the persistent tiled launch: instances and cost prefix sums
+    if (e == hipSuccess && !H->tiled.empty()) {
+        const size_t m = H->tiled.size();
+        std::vector<uint64_t> cs(m + 1);
+        for (size_t q = 0; q < m; ++q) cs[q] = H->tiled[q].cost_start;
+        cs[m] = H->tcost_total;
+        e = hipMalloc(&H->d_tiled, sizeof(TiledInst) * m);
+        if (e == hipSuccess) e = hipMemcpy(H->d_tiled, H->tiled.data(), sizeof(TiledInst) * m, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMalloc(&H->d_tcost, sizeof(uint64_t) * (m + 1));
+        if (e == hipSuccess) e = hipMemcpy(H->d_tcost, cs.data(), sizeof(uint64_t) * (m + 1), hipMemcpyHostToDevice);
+        H->Kt = H->Kt_max;
+        int per_cu = 0;
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_tiles<2>, 256, H->tlds);
+        H->twg_max = per_cu < 1 ? 1u : (unsigned)per_cu;
+        H->twg = H->twg_max;
+    }
     // groups: per-instance kernel arguments, bases and tile prefix sums
     for (size_t g = 0; g < H->groups.size() && e == hipSuccess; ++g) {
         BatchGroup &G = H->groups[g];
@@ -443,7 +605,16 @@ sqz_status batch_create(const sqz_fractal *const *fr, int32_t count, BatchHost *
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(H->key);
-        if (it != g_tune_cache.end()) H->xt_weight = it->second.second;
+        if (it != g_tune_cache.end()) {
+            H->xt_weight = it->second.xt_weight;
+            if (!H->tiled.empty()) {
+                H->twg = std::min(it->second.twg, H->twg_max);
+                H->Kt = std::min(it->second.Kt, H->Kt_max);
+                H->persistent_tiles = it->second.persistent_tiles;
+                for (size_t g = 0; g < H->groups.size() && g < it->second.group_K.size(); ++g)
+                    H->groups[g].K = std::min(it->second.group_K[g], H->groups[g].K_max);
+            }
+        }
     }
     if (e == hipSuccess) e = upload_costs(H);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&H->cap, hipStreamNonBlocking);
@@ -464,7 +635,7 @@ sqz_status batch_create(const sqz_fractal *const *fr, int32_t count, BatchHost *
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(H->key);
-        if (it != g_tune_cache.end()) H->wg_per_cu = std::min(it->second.first, H->max_wg_per_cu);
+        if (it != g_tune_cache.end()) H->wg_per_cu = std::min(it->second.wg, H->max_wg_per_cu);
     }
     *out = H;
     return SQZ_OK;
@@ -477,6 +648,8 @@ void batch_destroy(BatchHost *H)
     if (H->cap) (void)hipStreamDestroy(H->cap);
     (void)hipFree(H->d_inst);
     (void)hipFree(H->d_cost_start);
+    (void)hipFree(H->d_tiled);
+    (void)hipFree(H->d_tcost);
     for (BatchGroup &G : H->groups) {
         (void)hipFree(G.d_args);
         (void)hipFree(G.d_base);
@@ -552,16 +725,52 @@ static sqz_status launch_group(const BatchGroup &G, const uint8_t *in, uint8_t *
     return e == hipSuccess ? SQZ_OK : hip_error(e, "batch group launch");
 }
 
-// All launches of `steps` steps: every group and the persistent launch follow
-// their own plan (each with the parity of `steps`).
+// One launch of `steps` (1..H->Kt_max) steps for every tiled instance.
+static sqz_status launch_tiled(const BatchHost *H, unsigned wg_per_cu, const uint8_t *in, uint8_t *out, int steps,
+                               hipStream_t st)
+{
+    TiledArgs A;
+    A.inst = H->d_tiled;
+    A.cost_start = H->d_tcost;
+    A.ninst = (uint32_t)H->tiled.size();
+    A.total_cost = H->tcost_total;
+    uint64_t grid = (uint64_t)H->cus * wg_per_cu;
+    if (grid < 1) grid = 1;
+    const dim3 g((unsigned)grid), b(256);
+    const size_t L = H->tlds;
+    switch (steps) {
+    case 1: hipLaunchKernelGGL(k_batch_tiles<1>, g, b, L, st, A, in, out); break;
+    case 2: hipLaunchKernelGGL(k_batch_tiles<2>, g, b, L, st, A, in, out); break;
+    case 3: hipLaunchKernelGGL(k_batch_tiles<3>, g, b, L, st, A, in, out); break;
+    case 4: hipLaunchKernelGGL(k_batch_tiles<4>, g, b, L, st, A, in, out); break;
+    case 5: hipLaunchKernelGGL(k_batch_tiles<5>, g, b, L, st, A, in, out); break;
+    case 6: hipLaunchKernelGGL(k_batch_tiles<6>, g, b, L, st, A, in, out); break;
+    case 7: hipLaunchKernelGGL(k_batch_tiles<7>, g, b, L, st, A, in, out); break;
+    case 8: hipLaunchKernelGGL(k_batch_tiles<8>, g, b, L, st, A, in, out); break;
+    case 9: hipLaunchKernelGGL(k_batch_tiles<9>, g, b, L, st, A, in, out); break;
+    default: hipLaunchKernelGGL(k_batch_tiles<10>, g, b, L, st, A, in, out); break;
+    }
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SQZ_OK : hip_error(e, "batch tiled launch");
+}
+
+// All launches of `steps` steps: the tiled launch and the expanded-tile /
+// thread-level launch follow their own plans (each with the parity of
+// `steps`, so every result lands in the same buffer).
 static sqz_status launch_all(const BatchHost *H, const uint8_t *a, const uint8_t *b, int32_t steps, hipStream_t st)
 {
     sqz_status s2 = SQZ_OK;
     uint8_t *const A = const_cast<uint8_t *>(a), *const B = const_cast<uint8_t *>(b);
-    for (size_t g = 0; g < H->groups.size() && s2 == SQZ_OK; ++g) {
-        const std::vector<int> plan = plan_launches(steps, H->groups[g].K);
+    if (!H->tiled.empty() && H->persistent_tiles) {
+        const std::vector<int> plan = plan_launches(steps, H->Kt);
         for (size_t i = 0; i < plan.size() && s2 == SQZ_OK; ++i)
-            s2 = launch_group(H->groups[g], (i & 1) ? B : A, (i & 1) ? A : B, plan[i], st);
+            s2 = launch_tiled(H, H->twg, (i & 1) ? B : A, (i & 1) ? A : B, plan[i], st);
+    } else {
+        for (size_t g = 0; g < H->groups.size() && s2 == SQZ_OK; ++g) {
+            const std::vector<int> plan = plan_launches(steps, H->groups[g].K);
+            for (size_t i = 0; i < plan.size() && s2 == SQZ_OK; ++i)
+                s2 = launch_group(H->groups[g], (i & 1) ? B : A, (i & 1) ? A : B, plan[i], st);
+        }
     }
     if (H->has_rest) {
         const std::vector<int> plan = plan_launches(steps, H->K);
@@ -609,66 +818,144 @@ sqz_status batch_run(BatchHost *H, uint8_t *a, uint8_t *b, int32_t steps, hipStr
     return e == hipSuccess ? SQZ_OK : hip_error(e, "hipGraphLaunch");
 }
 
+// Milliseconds of `launches` of the given shape on the caller's buffers.
+template <class F>
+static sqz_status time_launches(hipStream_t st, hipEvent_t e0, hipEvent_t e1, F &&launch_i, int launches, float *ms)
+{
+    sqz_status st2 = launch_i(0);  // warm-up
+    if (st2 != SQZ_OK) return st2;
+    (void)hipEventRecord(e0, st);
+    for (int i = 0; i < launches && st2 == SQZ_OK; ++i) st2 = launch_i(i);
+    (void)hipEventRecord(e1, st);
+    if (hipEventSynchronize(e1) != hipSuccess) return set_error(SQZ_ERR_HIP, "autotune synchronisation failed");
+    (void)hipEventElapsedTime(ms, e0, e1);
+    return st2;
+}
+
 sqz_status batch_autotune(BatchHost *H, uint8_t *a, uint8_t *b, hipStream_t st, unsigned *best_out)
 {
-    if (!H->has_rest) {  // every instance is in a group: nothing to tune
-        if (best_out) *best_out = H->wg_per_cu;
-        return SQZ_OK;
-    }
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return set_error(SQZ_ERR_HIP, "hipEventCreate failed");
-    bool has_xt = false;
-    for (const BatchInst &I : H->inst) has_xt |= I.kind >= kBX68 && I.kind <= kBXAny;
-    const unsigned weights[] = {2, 3, 4, 6, 8};
-    unsigned best = H->wg_per_cu, best_w = H->xt_weight;
-    float best_ms = 1e30f;
     sqz_status st2 = SQZ_OK;
-    for (unsigned wi = 0; wi < (has_xt ? 5u : 1u) && st2 == SQZ_OK; ++wi) {
-        if (has_xt) {
-            H->xt_weight = weights[wi];
-            hipError_t e = upload_costs(H);
-            if (e != hipSuccess) {
-                st2 = hip_error(e, "batch cost upload");
-                break;
+    // (1) the tiled instances, each candidate timed per step over four
+    // launches of its steps per launch: one launch per pattern group (steps
+    // per launch per group), against one persistent launch (workgroups per CU
+    // x steps per launch)
+    if (!H->tiled.empty()) {
+        const int ks[] = {1, 2, 3, 4, 5, 6, 8, 10};
+        float grouped_ms = 0.0f;
+        for (BatchGroup &G : H->groups) {
+            float best_ms = 1e30f;
+            int bk = G.K;
+            for (int K : ks) {
+                if (K > G.K_max || (K == 1 && G.K_max > 1) || st2 != SQZ_OK) continue;
+                float ms = 0.0f;
+                st2 = time_launches(st, e0, e1, [&](int i) {
+                    return launch_group(G, (i & 1) ? b : a, (i & 1) ? a : b, K, st);
+                }, 4, &ms);
+                ms /= 4.0f * K;
+                if (st2 == SQZ_OK && ms < best_ms) {
+                    best_ms = ms;
+                    bk = K;
+                }
+            }
+            G.K = bk;
+            grouped_ms += best_ms;
+        }
+        const unsigned ws[] = {2, 3, 4, 5, 6, 8};
+        float best_ms = 1e30f;
+        unsigned bw = H->twg;
+        int bk = H->Kt;
+        for (int K : ks) {
+            if (K > H->Kt_max || (K == 1 && H->Kt_max > 1)) continue;
+            for (unsigned w : ws) {
+                if (w > H->twg_max || st2 != SQZ_OK) continue;
+                float ms = 0.0f;
+                st2 = time_launches(st, e0, e1, [&](int i) {
+                    return launch_tiled(H, w, (i & 1) ? b : a, (i & 1) ? a : b, K, st);
+                }, 4, &ms);
+                ms /= 4.0f * K;
+                if (st2 == SQZ_OK && ms < best_ms) {
+                    best_ms = ms;
+                    bw = w;
+                    bk = K;
+                }
             }
         }
-        for (unsigned w = 1; w <= H->max_wg_per_cu && st2 == SQZ_OK; w = (w < 4 ? w + 1 : w * 2)) {
-            st2 = launch_batch(H, w, a, b, H->K, st);  // warm-up
-            if (st2 != SQZ_OK) break;
-            (void)hipEventRecord(e0, st);
-            for (int i = 0; i < 4 && st2 == SQZ_OK; ++i)
-                st2 = launch_batch(H, w, (i & 1) ? b : a, (i & 1) ? a : b, H->K, st);
-            (void)hipEventRecord(e1, st);
-            if (hipEventSynchronize(e1) != hipSuccess) {
-                st2 = set_error(SQZ_ERR_HIP, "autotune synchronisation failed");
-                break;
+        H->twg = bw;
+        H->Kt = bk;
+        H->persistent_tiles = best_ms < grouped_ms;
+    }
+    // (2) the expanded-tile / thread-level launch: workgroups per CU x the
+    // expanded-tile cost weight
+    if (H->has_rest && st2 == SQZ_OK) {
+        bool has_xt = false;
+        for (const BatchInst &I : H->inst) has_xt |= I.kind >= kBX68 && I.kind <= kBXAny;
+        const unsigned weights[] = {2, 3, 4, 6, 8};
+        unsigned best = H->wg_per_cu, best_w = H->xt_weight;
+        float best_ms = 1e30f;
+        for (unsigned wi = 0; wi < (has_xt ? 5u : 1u) && st2 == SQZ_OK; ++wi) {
+            if (has_xt) {
+                H->xt_weight = weights[wi];
+                hipError_t e = upload_costs(H);
+                if (e != hipSuccess) {
+                    st2 = hip_error(e, "batch cost upload");
+                    break;
+                }
             }
-            float ms = 0.0f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            if (ms < best_ms) {
-                best_ms = ms;
-                best = w;
-                best_w = H->xt_weight;
+            for (unsigned w = 1; w <= H->max_wg_per_cu && st2 == SQZ_OK; w = (w < 4 ? w + 1 : w * 2)) {
+                float ms = 0.0f;
+                st2 = time_launches(st, e0, e1, [&](int i) {
+                    return launch_batch(H, w, (i & 1) ? b : a, (i & 1) ? a : b, H->K, st);
+                }, 4, &ms);
+                if (st2 == SQZ_OK && ms < best_ms) {
+                    best_ms = ms;
+                    best = w;
+                    best_w = H->xt_weight;
+                }
             }
         }
+        H->xt_weight = best_w;
+        hipError_t e = upload_costs(H);
+        if (st2 == SQZ_OK && e != hipSuccess) st2 = hip_error(e, "batch cost upload");
+        H->wg_per_cu = best;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    H->xt_weight = best_w;
-    hipError_t e = upload_costs(H);
-    if (st2 == SQZ_OK && e != hipSuccess) st2 = hip_error(e, "batch cost upload");
     if (st2 != SQZ_OK) return st2;
-    H->wg_per_cu = best;
     if (H->gexec) {
         (void)hipGraphExecDestroy(H->gexec);
         H->gexec = nullptr;
     }
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune_cache[H->key] = std::make_pair(best, best_w);
+        std::vector<int> gk;
+        for (const BatchGroup &G : H->groups) gk.push_back(G.K);
+        g_tune_cache[H->key] = TuneResult{H->wg_per_cu, H->xt_weight, H->twg, H->Kt, H->persistent_tiles, gk};
     }
-    if (best_out) *best_out = best;
+    if (best_out) *best_out = H->tiled.empty() ? H->wg_per_cu : H->twg;
+    return SQZ_OK;
+}
+
+sqz_status batch_set_tiled(BatchHost *H, int32_t persistent, int32_t steps_per_launch, int32_t wg_per_cu)
+{
+    if (persistent != 0 && persistent != 1) return set_error(SQZ_ERR_INVALID, "persistent must be 0 or 1");
+    if (steps_per_launch < 0 || (steps_per_launch > 0 && (H->tiled.empty() || steps_per_launch > H->Kt_max)))
+        return set_error(SQZ_ERR_INVALID, "steps_per_launch %d outside 0..%d", steps_per_launch,
+                         H->tiled.empty() ? 0 : H->Kt_max);
+    if (wg_per_cu < 0 || (wg_per_cu > 0 && (H->tiled.empty() || (unsigned)wg_per_cu > H->twg_max)))
+        return set_error(SQZ_ERR_INVALID, "wg_per_cu %d outside 0..%u", wg_per_cu, H->tiled.empty() ? 0u : H->twg_max);
+    H->persistent_tiles = persistent == 1;
+    if (steps_per_launch > 0) {
+        H->Kt = steps_per_launch;
+        for (BatchGroup &G : H->groups) G.K = std::min(steps_per_launch, G.K_max);
+    }
+    if (wg_per_cu > 0) H->twg = (unsigned)wg_per_cu;
+    if (H->gexec) {
+        (void)hipGraphExecDestroy(H->gexec);
+        H->gexec = nullptr;
+    }
     return SQZ_OK;
 }
 
@@ -679,7 +966,10 @@ unsigned batch_wg_per_cu(const BatchHost *H) { return H->wg_per_cu; }
 int batch_steps_per_launch(const BatchHost *H)
 {
     int k = H->has_rest ? H->K : kMaxSteps;
-    for (const BatchGroup &G : H->groups) k = std::min(k, G.K);
+    if (!H->tiled.empty() && H->persistent_tiles)
+        k = std::min(k, H->Kt);
+    else
+        for (const BatchGroup &G : H->groups) k = std::min(k, G.K);
     return k < 1 ? 1 : k;
 }
 uint64_t batch_total_cells(const BatchHost *H) { return H->total_cells; }

@@ -272,6 +272,7 @@ void batch_destroy(BatchHost *H);
 sqz_status batch_step(const BatchHost *H, const uint8_t *in, uint8_t *out, hipStream_t st);
 sqz_status batch_run(BatchHost *H, uint8_t *a, uint8_t *b, int32_t steps, hipStream_t st);
 sqz_status batch_autotune(BatchHost *H, uint8_t *a, uint8_t *b, hipStream_t st, unsigned *best_out);
+sqz_status batch_set_tiled(BatchHost *H, int32_t persistent, int32_t steps_per_launch, int32_t wg_per_cu);
 uint64_t batch_total_bytes(const BatchHost *H);
 uint64_t batch_offset(const BatchHost *H, int32_t i);
 int32_t batch_count(const BatchHost *H);

@@ -134,6 +134,41 @@ def test_mixed_groups_and_persistent_launch():
             assert torch.equal(B.instance(res, i), y), (i, steps)
 
 
+@pytest.mark.parametrize("steps_per_launch,wg", [(0, 0), (3, 2), (6, 4), (1, 1)])
+def test_persistent_tiled_launch_equals_groups(steps_per_launch, wg):
+    """The tiled instances as one persistent launch (any steps per launch and grid)
+    give the same states as the per-group launches, next to instances of the other
+    persistent launch."""
+    torch = torch_or_skip()
+    spec = [("triangle", 9), ("carpet", 5), ("vicsek", 6), ("carpet", 2), ("triangle", 12), ("vicsek", 3),
+            ("triangle_paper", 10), ("carpet", 6), ("triangle", 1), ("carpet", 0)]
+    fr, B = build(spec)
+    seeds = [17 * i + 5 for i in range(len(fr))]
+    for steps in (1, 5, 12):
+        a = B.fill_bernoulli(seeds, 0.5)
+        want = B.run(a, B.empty_state(), steps).clone()
+        B.set_tiled_launch(True, steps_per_launch, wg)
+        if steps_per_launch:
+            assert B.steps_per_launch <= steps_per_launch
+        x = B.fill_bernoulli(seeds, 0.5)
+        got = B.run(x, B.empty_state(), steps)
+        assert torch.equal(got, want), steps
+        B.set_tiled_launch(False)
+
+
+def test_tiled_launch_arguments():
+    torch_or_skip()
+    import paper_2201_00613_amd as sqz
+
+    fr, B = build([("triangle", 9), ("carpet", 5)])
+    for bad in ((2, 0, 0), (1, -1, 0), (1, 11, 0), (1, 0, -1), (1, 0, 1000)):
+        with pytest.raises(sqz.SqueezeError) as e:
+            B.set_tiled_launch(*bad)
+        assert e.value.status == 1
+    B.set_tiled_launch(True, 6, 2)
+    assert B.steps_per_launch == 6
+
+
 def test_autotune_keeps_results():
     torch = torch_or_skip()
     spec = [("triangle", 13), ("carpet", 6), ("vicsek", 8)]
