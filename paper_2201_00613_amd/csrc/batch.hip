@@ -516,7 +516,7 @@ sqz_status batch_create(const sqz_fractal *const *fr, int32_t count, BatchHost *
                 if ((H->inst[p].kind == I.kind) && H->inst[p].xcfg == I.xcfg && H->inst[p].kind != kBCell &&
                     H->inst[p].kind >= kBX68) {
                     I.x.lam = H->inst[p].x.lam;
-                    I.x.mem_in = H->inst[p].x.mem_in;
+                    I.x.ent = H->inst[p].x.ent;
                     I.x.rpos = H->inst[p].x.rpos;
                     I.x.rinfo = H->inst[p].x.rinfo;
                     break;

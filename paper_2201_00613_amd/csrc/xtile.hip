@@ -12,7 +12,8 @@ namespace sqz {
 namespace {
 
 template <class Op, int PT>
-__global__ void __launch_bounds__(kXBlock) k_xtile(XArgs A, const typename Op::G *__restrict__ in,
+__global__ void __launch_bounds__(kXBlock) __attribute__((amdgpu_waves_per_eu(Op::kWaves)))
+k_xtile(XArgs A, const typename Op::G *__restrict__ in,
                                                    typename Op::G *__restrict__ out, XOp op)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -221,20 +222,40 @@ sqz_status xtile_prepare(FractalHost &F)
     X->R = (uint32_t)ring.size();
     const uint32_t P = X->P, KM = X->KM, R = X->R;
 
-    // tables: lambda positions, interior membership, ring positions, ring info
+    // tables: lambda positions, cell entries (diffusion), ring positions, ring info
     std::vector<uint16_t> lam(KM);
-    std::vector<uint8_t> mem((size_t)P * P, 0);
+    std::vector<uint32_t> ent(KM);
+    const int64_t side = (int64_t)X->B;
     for (uint32_t c = 0; c < KM; ++c) {
         int64_t x, y;
         host_lambda(F, M, c, x, y);
         lam[c] = (uint16_t)((y + 1) * P + (x + 1));
-        mem[lam[c]] = 1;
+        // member neighbours inside the tile, and per adjacent tile the member
+        // cells of that tile (its own copy of the level-M pattern) it touches
+        uint32_t inner = 0, cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                if (dx == 0 && dy == 0) continue;
+                const int64_t qx = x + dx, qy = y + dy;
+                const int tdx = qx < 0 ? -1 : (qx >= side ? 1 : 0), tdy = qy < 0 ? -1 : (qy >= side ? 1 : 0);
+                const bool member = host_nu(F, M, qx - tdx * side, qy - tdy * side) >= 0;
+                if (!member) continue;
+                if (tdx == 0 && tdy == 0) {
+                    ++inner;
+                } else {
+                    const int d = (tdy + 1) * 3 + (tdx + 1);
+                    ++cnt[d < 4 ? d : d - 1];
+                }
+            }
+        uint32_t e = lam[c] | inner << 16;
+        for (int d8 = 0; d8 < 8; ++d8) e |= cnt[d8] << deg_field(d8);  // sides <= 3, corners <= 1
+        ent[c] = e;
     }
-    const size_t o_lam = 0, o_mem = xt_align16(o_lam + KM * 2), o_rpos = xt_align16(o_mem + (size_t)P * P),
+    const size_t o_lam = 0, o_ent = xt_align16(o_lam + KM * 2), o_rpos = xt_align16(o_ent + (size_t)KM * 4),
                  o_rinfo = xt_align16(o_rpos + (size_t)R * 2), total = xt_align16(o_rinfo + (size_t)R * 4 + 4);
     std::vector<uint8_t> blob(total, 0);
     memcpy(blob.data() + o_lam, lam.data(), KM * 2);
-    memcpy(blob.data() + o_mem, mem.data(), (size_t)P * P);
+    memcpy(blob.data() + o_ent, ent.data(), (size_t)KM * 4);
     for (uint32_t j = 0; j < R; ++j) {
         memcpy(blob.data() + o_rpos + 2 * j, &ring[j].pos, 2);
         memcpy(blob.data() + o_rinfo + 4 * j, &ring[j].info, 4);
@@ -259,13 +280,14 @@ sqz_status xtile_prepare(FractalHost &F)
     X->base.B = X->B;
     X->base.R = R;
     X->base.lam = (const uint16_t *)(b + o_lam);
-    X->base.mem_in = b + o_mem;
+    X->base.ent = (const uint32_t *)(b + o_ent);
     X->base.rpos = (const uint16_t *)(b + o_rpos);
     X->base.rinfo = (const uint32_t *)(b + o_rinfo);
     X->lds_life = xt_layout(P, KM, R, 1, false, true, nullptr);
     X->lds_diff = xt_layout(P, KM, R, 4, true, false, nullptr);
     X->grid_life = occupancy_grid<XLife, 0>(X->lds_life, X->ntiles, F.device);
     X->grid_diff = occupancy_grid<XDiffF32, 0>(X->lds_diff, X->ntiles, F.device);
+    X->grid_diff16 = occupancy_grid<XDiffBF16, 0>(X->lds_diff, X->ntiles, F.device);
     st = xtile_prepare_multi(F, X);
     if (st != SQZ_OK) {
         (void)hipFree(X->d_tab);
@@ -407,7 +429,7 @@ static sqz_status launch_x(const FractalHost &F, const void *in, void *out, cons
     const bool life = !Op::kMem;
     const size_t lds = xt_layout(X->P, X->KM, X->R, sizeof(typename Op::L), Op::kMem, Op::kSwar, &A);
     A.vec = ((X->KM * sizeof(typename Op::G)) % 16 == 0 && !(((uintptr_t)in | (uintptr_t)out) & 15)) ? 1u : 0u;
-    const unsigned grid = life ? X->grid_life : X->grid_diff;
+    const unsigned grid = life ? X->grid_life : (sizeof(typename Op::G) == 4 ? X->grid_diff : X->grid_diff16);
     using G = typename Op::G;
     const G *i = (const G *)in;
     G *o = (G *)out;

@@ -43,6 +43,7 @@ struct XArgs {
     uint32_t ring_start[4];
     const uint16_t *lam;
     const uint8_t *mem_in;
+    const uint32_t *ent;  // per cell: lambda position | member-neighbour fields << 16 (diffusion)
     const uint16_t *rpos;
     const uint32_t *rinfo;
     MapParams Pc;
@@ -54,12 +55,16 @@ struct XOp {
     uint64_t seed, step;
 };
 
+// kWaves: the one-step kernel's minimum waves per SIMD (register budget; the
+// diffusion kernels keep every lane's sixteen cell entries in registers, and
+// the measured best is four waves for binary32, five for bfloat16 storage).
 struct XLife {
     using G = uint8_t;
     using L = uint8_t;
     static constexpr bool kMem = false;
     static constexpr bool kSwar = true;  // row-wise SIMD-within-a-register update
     static constexpr int kVec = 16;
+    static constexpr int kWaves = 1;
 };
 struct XDiffF32 {
     using G = float;
@@ -67,6 +72,7 @@ struct XDiffF32 {
     static constexpr bool kMem = true;
     static constexpr bool kSwar = false;
     static constexpr int kVec = 4;
+    static constexpr int kWaves = 4;
 };
 struct XDiffBF16 {
     using G = uint16_t;  // bfloat16 bits of delta
@@ -74,6 +80,7 @@ struct XDiffBF16 {
     static constexpr bool kMem = true;
     static constexpr bool kSwar = false;
     static constexpr int kVec = 8;
+    static constexpr int kWaves = 5;
 };
 
 __device__ __forceinline__ uint8_t to_lds(uint8_t v) { return v; }
@@ -104,6 +111,18 @@ __device__ __forceinline__ uint16_t to_bf16(float u, uint32_t rounding, uint32_t
     return (uint16_t)(b >> 16);
 }
 
+// u' = u + a (S - deg u) in binary32 (S summed in a fixed order), stored as
+// binary32 or as bfloat16 bits.
+template <class Op>
+__device__ __forceinline__ typename Op::G diff_finish(float S, float c, uint32_t deg, const XOp &op, uint64_t gcell)
+{
+    const float u = fmaf(op.coef, fmaf(-(float)deg, c, S), c);
+    if constexpr (sizeof(typename Op::G) == 4)
+        return u;
+    else
+        return to_bf16(u, op.rounding, op.rounding == SQZ_ROUND_STOCHASTIC ? rand16(op.seed, op.step, gcell) : 0u);
+}
+
 template <class Op>
 __device__ __forceinline__ typename Op::G cell_update(const typename Op::L *s_val, const uint8_t *s_mem, uint32_t p,
                                                       uint32_t P, const XOp &op, uint64_t gcell)
@@ -119,12 +138,50 @@ __device__ __forceinline__ typename Op::G cell_update(const typename Op::L *s_va
         const uint8_t *m = s_mem + (p - P - 1);
         const uint32_t deg = (uint32_t)m[0] + m[1] + m[2] + m[P] + m[P + 2] + m[2 * P] + m[2 * P + 1] + m[2 * P + 2];
         const float S = ((((((n0 + n1) + n2) + n3) + n4) + n5) + n6) + n7;
-        const float u = fmaf(op.coef, fmaf(-(float)deg, c, S), c);
-        if constexpr (sizeof(typename Op::G) == 4)
-            return u;
-        else
-            return to_bf16(u, op.rounding, op.rounding == SQZ_ROUND_STOCHASTIC ? rand16(op.seed, op.step, gcell) : 0u);
+        return diff_finish<Op>(S, c, deg, op, gcell);
     }
+}
+
+// Member-neighbour count of a tile cell without a membership array.  The
+// cell's entry holds its lambda position in bits 0..15, the number of its
+// member neighbours inside the tile in bits 16..19, and for each adjacent tile
+// the number of that tile's member cells it touches: two bits for the four
+// side tiles (up to three cells), one bit for the four corner tiles.  Which
+// adjacent tiles exist varies per tile; lo / hi select the fields of those
+// present, with weights 1 and 2.
+struct DegMask {
+    uint32_t lo, hi;
+};
+// field of adjacent tile d8 (d8 = index of (dx, dy) in row-major order of the
+// 3 x 3 neighbourhood without its centre)
+__host__ __device__ constexpr int deg_field(int d8)
+{
+    return d8 == 1 ? 20 : d8 == 3 ? 22 : d8 == 4 ? 24 : d8 == 6 ? 26 : d8 == 0 ? 28 : d8 == 2 ? 29 : d8 == 5 ? 30 : 31;
+}
+__host__ __device__ constexpr bool deg_side(int d8) { return d8 == 1 || d8 == 3 || d8 == 4 || d8 == 6; }
+
+__device__ __forceinline__ DegMask deg_mask(const uint64_t *nbase)
+{
+    DegMask m{0u, 0u};
+#pragma unroll
+    for (int d = 0; d < 8; ++d)
+        if (nbase[d] != kHole64) {
+            m.lo |= 1u << deg_field(d);
+            if (deg_side(d)) m.hi |= 2u << deg_field(d);
+        }
+    return m;
+}
+
+template <class Op>
+__device__ __forceinline__ typename Op::G diff_update(const float *s_val, uint32_t e, uint32_t P, DegMask dm,
+                                                      const XOp &op, uint64_t gcell)
+{
+    const float *b = s_val + ((e & 0xFFFFu) - P - 1);
+    const float n0 = b[0], n1 = b[1], n2 = b[2], n3 = b[P], c = b[P + 1], n4 = b[P + 2];
+    const float n5 = b[2 * P], n6 = b[2 * P + 1], n7 = b[2 * P + 2];
+    const uint32_t deg = ((e >> 16) & 15u) + __popc(e & dm.lo) + 2u * __popc(e & dm.hi);
+    const float S = ((((((n0 + n1) + n2) + n3) + n4) + n5) + n6) + n7;
+    return diff_finish<Op>(S, c, deg, op, gcell);
 }
 
 // LDS carve-up of the expanded tile (offsets in XArgs).
@@ -132,12 +189,11 @@ template <class Op>
 struct XLds {
     typename Op::L *val;
     uint8_t *res;  // row-update results (Life)
-    uint8_t *mem;
     uint16_t *lam, *rpos;
     uint32_t *rinfo;
     uint64_t *nbase;
     __device__ XLds(unsigned char *smem, const XArgs &A)
-        : val(reinterpret_cast<typename Op::L *>(smem + A.off_val)), res(smem + A.off_res), mem(smem + A.off_mem),
+        : val(reinterpret_cast<typename Op::L *>(smem + A.off_val)), res(smem + A.off_res),
           lam(reinterpret_cast<uint16_t *>(smem + A.off_lam)), rpos(reinterpret_cast<uint16_t *>(smem + A.off_rpos)),
           rinfo(reinterpret_cast<uint32_t *>(smem + A.off_rinfo)), nbase(reinterpret_cast<uint64_t *>(smem + A.off_nbase))
     {
@@ -151,7 +207,6 @@ __device__ __forceinline__ void xtile_setup(const XArgs &A, const XLds<Op> &S)
     const uint32_t tid = threadIdx.x, PP = A.P * A.P;
     for (uint32_t i = tid; i < PP; i += kXBlock) {
         S.val[i] = (typename Op::L)0;
-        if constexpr (Op::kMem) S.mem[i] = A.mem_in[i];
     }
     if constexpr (Op::kSwar) {  // the 16 bytes on either side of the box: row updates read them
         uint32_t *before = reinterpret_cast<uint32_t *>(S.val) - 4;
@@ -159,11 +214,23 @@ __device__ __forceinline__ void xtile_setup(const XArgs &A, const XLds<Op> &S)
         if (tid < 4) before[tid] = 0;
         else if (tid < 8) after[tid - 4] = 0;
     }
-    for (uint32_t i = tid; i < A.KM; i += kXBlock) S.lam[i] = A.lam[i];
+    if constexpr (!Op::kMem)
+        for (uint32_t i = tid; i < A.KM; i += kXBlock) S.lam[i] = A.lam[i];
     for (uint32_t i = tid; i < A.R; i += kXBlock) {
         S.rpos[i] = A.rpos[i];
         S.rinfo[i] = A.rinfo[i];
     }
+}
+
+// Box position of tile cell l: the LDS lambda table (Life) or the cell's
+// entry (diffusion).
+template <class Op>
+__device__ __forceinline__ uint32_t xt_pos(const XArgs &A, const XLds<Op> &S, uint32_t l)
+{
+    if constexpr (Op::kMem)
+        return A.ent[l] & 0xFFFFu;
+    else
+        return S.lam[l];
 }
 
 // One tile t: scatter, ring, update.  Starts with a barrier (tables ready and
@@ -197,10 +264,10 @@ __device__ __forceinline__ void xtile_body(const XArgs &A, const typename Op::G 
             const uint4 q = *reinterpret_cast<const uint4 *>(src + (size_t)v * VEC);
             const G *e = reinterpret_cast<const G *>(&q);
 #pragma unroll
-            for (int i = 0; i < VEC; ++i) S.val[S.lam[v * VEC + i]] = to_lds(e[i]);
+            for (int i = 0; i < VEC; ++i) S.val[xt_pos<Op>(A, S, v * VEC + i)] = to_lds(e[i]);
         }
     } else {
-        for (uint32_t l = tid; l < KM; l += kXBlock) S.val[S.lam[l]] = to_lds(src[l]);
+        for (uint32_t l = tid; l < KM; l += kXBlock) S.val[xt_pos<Op>(A, S, l)] = to_lds(src[l]);
     }
     __syncthreads();
     // the ring: cells of adjacent tiles that touch this one
@@ -210,23 +277,25 @@ __device__ __forceinline__ void xtile_body(const XArgs &A, const typename Op::G 
         L v = (L)0;
         if (nb != kHole64) v = to_lds(in[nb + (info & 0xFFFFu)]);
         S.val[S.rpos[j]] = v;
-        if constexpr (Op::kMem) S.mem[S.rpos[j]] = nb != kHole64;
     }
     __syncthreads();
     // update every cell, results in compact order
     G *dst = out + t * KM;
     const uint64_t gbase = t * KM;
-    if (A.vec) {
+    if constexpr (Op::kMem) {
+        const DegMask dm = deg_mask(S.nbase);
+        for (uint32_t l = tid; l < KM; l += kXBlock) dst[l] = diff_update<Op>(S.val, A.ent[l], P, dm, op, gbase + l);
+    } else if (A.vec) {
         for (uint32_t v = tid; v < KM / VEC; v += kXBlock) {
             uint4 q;
             G *e = reinterpret_cast<G *>(&q);
 #pragma unroll
             for (int i = 0; i < VEC; ++i)
-                e[i] = cell_update<Op>(S.val, S.mem, S.lam[v * VEC + i], P, op, gbase + v * VEC + i);
+                e[i] = cell_update<Op>(S.val, nullptr, S.lam[v * VEC + i], P, op, gbase + v * VEC + i);
             *reinterpret_cast<uint4 *>(dst + (size_t)v * VEC) = q;
         }
     } else {
-        for (uint32_t l = tid; l < KM; l += kXBlock) dst[l] = cell_update<Op>(S.val, S.mem, S.lam[l], P, op, gbase + l);
+        for (uint32_t l = tid; l < KM; l += kXBlock) dst[l] = cell_update<Op>(S.val, nullptr, S.lam[l], P, op, gbase + l);
     }
 }
 
@@ -266,7 +335,15 @@ __device__ __forceinline__ void xtile_run(const XArgs &A, const typename Op::G *
     if (t0 >= t1) return;
     G cur[KPL];
     L rv[RPL];
-    bool rm[RPL];
+    // diffusion: the entries of this lane's cells, the same for every tile
+    uint32_t ent[Op::kMem ? KPL : 1];
+    if constexpr (Op::kMem) {
+#pragma unroll
+        for (int k = 0; k < KPL; ++k) {
+            const uint32_t l = (uint32_t)k * 256 + tid;
+            ent[k] = (FULL || l < KM) ? A.ent[l] : 0u;
+        }
+    }
     __syncthreads();  // tables and the previous work's LDS reads are done
     xtile_bases(A, t0, S.nbase + 8 * (t0 & 1));
     __syncthreads();
@@ -283,14 +360,10 @@ __device__ __forceinline__ void xtile_run(const XArgs &A, const typename Op::G *
         for (int k = 0; k < RPL; ++k) {
             const uint32_t j = (uint32_t)k * 256 + tid;
             rv[k] = (L)0;
-            rm[k] = false;
             if (j < R) {
                 const uint32_t info = S.rinfo[j];
                 const uint64_t b = nb[info >> 16];
-                if (b != kHole64) {
-                    rv[k] = to_lds(in[b + (info & 0xFFFFu)]);
-                    rm[k] = true;
-                }
+                if (b != kHole64) rv[k] = to_lds(in[b + (info & 0xFFFFu)]);
             }
         }
     }
@@ -299,15 +372,17 @@ __device__ __forceinline__ void xtile_run(const XArgs &A, const typename Op::G *
 #pragma unroll
         for (int k = 0; k < KPL; ++k) {
             const uint32_t l = (uint32_t)k * 256 + tid;
-            if (FULL || l < KM) S.val[S.lam[l]] = to_lds(cur[k]);
+            if (FULL || l < KM) {
+                if constexpr (Op::kMem)
+                    S.val[ent[k] & 0xFFFFu] = to_lds(cur[k]);
+                else
+                    S.val[S.lam[l]] = to_lds(cur[k]);
+            }
         }
 #pragma unroll
         for (int k = 0; k < RPL; ++k) {
             const uint32_t j = (uint32_t)k * 256 + tid;
-            if (j < R) {
-                S.val[S.rpos[j]] = rv[k];
-                if constexpr (Op::kMem) S.mem[S.rpos[j]] = rm[k];
-            }
+            if (j < R) S.val[S.rpos[j]] = rv[k];
         }
         const bool more = t + 1 < t1;
         if (more) xtile_bases(A, t + 1, S.nbase + 8 * ((t + 1) & 1));
@@ -324,14 +399,10 @@ __device__ __forceinline__ void xtile_run(const XArgs &A, const typename Op::G *
             for (int k = 0; k < RPL; ++k) {
                 const uint32_t j = (uint32_t)k * 256 + tid;
                 rv[k] = (L)0;
-                rm[k] = false;
                 if (j < R) {
                     const uint32_t info = S.rinfo[j];
                     const uint64_t b = nb[info >> 16];
-                    if (b != kHole64) {
-                        rv[k] = to_lds(in[b + (info & 0xFFFFu)]);
-                        rm[k] = true;
-                    }
+                    if (b != kHole64) rv[k] = to_lds(in[b + (info & 0xFFFFu)]);
                 }
             }
         }
@@ -363,10 +434,11 @@ __device__ __forceinline__ void xtile_run(const XArgs &A, const typename Op::G *
                 if (FULL || l < KM) dst[l] = S.res[S.lam[l]];
             }
         } else {
-#pragma unroll 4
+            const DegMask dm = deg_mask(S.nbase + 8 * (t & 1));
+#pragma unroll
             for (int k = 0; k < KPL; ++k) {
                 const uint32_t l = (uint32_t)k * 256 + tid;
-                if (FULL || l < KM) dst[l] = cell_update<Op>(S.val, S.mem, S.lam[l], P, op, gbase + l);
+                if (FULL || l < KM) dst[l] = diff_update<Op>(S.val, ent[k], P, dm, op, gbase + l);
             }
         }
     }
@@ -380,7 +452,7 @@ struct XTileConfig {
     void *d_tab;
     XArgs base;  // tables; LDS offsets are filled per operation
     size_t lds_life, lds_diff;
-    unsigned grid_life, grid_diff;
+    unsigned grid_life, grid_diff, grid_diff16;  // persistent grids (diff16: bfloat16 storage)
     void *d_coarse;
     // multi-step form (K steps per launch; K = 0: none)
     uint32_t K;
@@ -390,19 +462,19 @@ struct XTileConfig {
     unsigned gridk_life, gridk_diff;
 };
 
-// LDS layout: values, membership bytes (diffusion), lambda table, ring tables, 8 bases.
+// LDS layout: values, row results (Life), lambda table (Life), ring tables,
+// 2 x 8 bases.  Diffusion keeps its cell entries in registers or reads them
+// from global memory, so its box needs no membership array.
 inline size_t xt_align16(size_t v) { return (v + 15) & ~(size_t)15; }
-inline size_t xt_layout(uint32_t P, uint32_t KM, uint32_t R, size_t val_bytes, bool mem, bool swar, XArgs *A)
+inline size_t xt_layout(uint32_t P, uint32_t KM, uint32_t R, size_t val_bytes, bool diff, bool swar, XArgs *A)
 {
     const size_t box = (size_t)P * P * val_bytes;
     const size_t off_val = 16;  // padding on both sides: row updates read one word past each end
     size_t off = xt_align16(off_val + box + 16);
     const size_t off_res = off;
     if (swar) off = xt_align16(off + (size_t)P * P);
-    const size_t off_mem = off;
-    if (mem) off = xt_align16(off + (size_t)P * P);
     const size_t off_lam = off;
-    off = xt_align16(off + (size_t)KM * 2);
+    if (!diff) off = xt_align16(off + (size_t)KM * 2);  // diffusion keeps cell entries in registers
     const size_t off_rpos = off;
     off = xt_align16(off + (size_t)R * 2);
     const size_t off_rinfo = off;
@@ -412,7 +484,6 @@ inline size_t xt_layout(uint32_t P, uint32_t KM, uint32_t R, size_t val_bytes, b
     if (A) {
         A->off_val = (uint32_t)off_val;
         A->off_res = (uint32_t)off_res;
-        A->off_mem = (uint32_t)off_mem;
         A->off_lam = (uint32_t)off_lam;
         A->off_rpos = (uint32_t)off_rpos;
         A->off_rinfo = (uint32_t)off_rinfo;
