@@ -24,6 +24,7 @@ METRIC = "compact cell-updates/s vs expanded bounding-box on 1 MI355X; HBM GB/s 
 TRIANGLE = (2, [(0, 0), (1, 0), (0, 1)])
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 BYTES_PER_UPDATE = 2   # one byte read, one byte written per cell per step
+NUM_CUS, CLOCK_HZ = 256, 2.4e9  # MI355X compute units and peak engine clock
 
 
 def log(msg: str) -> None:
@@ -422,6 +423,14 @@ def main() -> int:
         out["roofline"]["traffic"] = rec["traffic_bytes_per_launch"] / (sec / launches) / 1e9
         out["roofline"]["traffic_bytes_per_launch"] = rec["traffic_bytes_per_launch"]
         out["roofline"]["traffic_vs_algorithmic"] = rec["traffic_bytes_per_launch"] / (BYTES_PER_UPDATE * F.cells)
+        K = rec["steps_per_launch"]
+        if "valu_insts_per_launch" in rec and args.steps % K == 0 and launches == args.steps // K:
+            # vector-ALU issue of the same launches: counter-measured instructions per launch over
+            # the live launch time, against the calibrated ceiling for the kernel's instruction mix
+            per_cu_clock = rec["valu_insts_per_launch"] / (sec / launches) / NUM_CUS / CLOCK_HZ
+            out["roofline"]["valu_issue"] = {
+                "achieved": per_cu_clock, "ceiling": rec["valu_ceiling_per_cu_clock"],
+                "unit": "wave-instructions per CU per clock", "frac": per_cu_clock / rec["valu_ceiling_per_cu_clock"]}
     if not args.no_bb:
         bsec = bb_run(torch, F, seed, p, args.bb_steps, 2)
         bb_ups = F.cells * args.bb_steps / bsec

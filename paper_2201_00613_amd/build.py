@@ -34,6 +34,16 @@ def compile_command(out: str, defines=()) -> list[str]:
     ]
 
 
+CALIB_SRC = os.path.join(PKG, "calib", "valu_issue.hip")
+CALIB_BIN = os.path.join(PKG, "calib", "valu_issue")
+
+
+def calib_command(out: str) -> list[str]:
+    """The vector-ALU issue-rate calibration program (a measurement aid, not part of the library)."""
+    return [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-Wall",
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", CALIB_SRC, "-o", out]
+
+
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
     cmd = compile_command(tmp)
@@ -41,6 +51,11 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
+    cmd = calib_command(CALIB_BIN + ".tmp")
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(CALIB_BIN + ".tmp", CALIB_BIN)
     return LIB
 
 
