@@ -259,8 +259,23 @@ def batch_leg(torch, sqz, steps: int) -> dict:
     res = {"instances": len(inst), "cells": B.total_cells, "steps": steps, "ms_per_step": sec * 1e3 / steps,
            "cell_updates_per_s": B.total_cells * steps / sec,
            "algorithmic_gbs_per_step": 2 * B.total_cells * steps / sec / 1e9, "wg_per_cu": wg, "graph": True,
-           "steps_per_launch": B.steps_per_launch,
+           "steps_per_launch": B.steps_per_launch, "tiled_launch": B.tiled_launch,
            "mix": {k: sum(1 for x in inst if x[0] == k) for k in ("triangle", "carpet", "vicsek")}}
+    # the same run with each launch form of the tiled instances (tuned steps per launch and grid)
+    chosen = res["tiled_launch"]
+    res["ms_per_step_by_tiled_form"] = {}
+    for form in ("groups", "persistent", "per_tile"):
+        B.set_tiled_launch(form)
+        a = B.fill_bernoulli(seeds, 0.5, out=a)
+        B.run(a, b, steps)  # capture + warm-up
+        a = B.fill_bernoulli(seeds, 0.5, out=a)
+        torch.cuda.synchronize()
+        e0.record()
+        B.run(a, b, steps)
+        e1.record()
+        torch.cuda.synchronize()
+        res["ms_per_step_by_tiled_form"][form] = e0.elapsed_time(e1) / steps
+    B.set_tiled_launch(chosen["form"])
     del a, b, B, fr, cache
     torch.cuda.empty_cache()
     return res

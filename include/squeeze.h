@@ -321,9 +321,10 @@ SQZ_API sqz_status sqz_bf16_decode(const sqz_fractal *f, const uint16_t *d_b, fl
 /*
  * Batched Life: `count` independent fractals (handles may repeat and may mix
  * replica patterns and levels) advanced together (the batched form of the
- * method's data-parallel step).  Instances with a tiled kernel run either as
- * one launch per pattern group or as one persistent launch over all of them
- * (sqz_batch_set_tiled_launch; sqz_batch_autotune times both); the others
+ * method's data-parallel step).  Instances with a tiled kernel run as one
+ * launch per pattern group or as one launch over all of them, persistent or
+ * with a workgroup per tile (sqz_batch_set_tiled_launch; sqz_batch_autotune
+ * times all three); the others
  * (expanded tiles, thread level) share one persistent launch.  The handles
  * must outlive the batch and live on the current device.  Instance i owns
  * bytes [offsets[i], offsets[i] + cells_i) of one state buffer of
@@ -360,17 +361,25 @@ SQZ_API sqz_status sqz_batch_steps_per_launch(const sqz_batch *b, int32_t *steps
  * bit-sliced tiles; carpet: bit rows):
  *   persistent = 0: one launch per pattern group, one workgroup per tile (the default);
  *   persistent = 1: one persistent launch over all of them, wg_per_cu workgroups per compute unit,
- *                   each taking an equal share of the tiles' cells.
+ *                   each taking an equal share of the tiles' cells;
+ *   persistent = 2: one launch over all of them, one workgroup per tile (wg_per_cu unused).
  * steps_per_launch: 0 keeps the current value, else 1 .. the most the instances allow (for
  * groups, capped at each group's most).  wg_per_cu: 0 keeps the current value, else 1 .. the
  * most that are resident.  Other values: SQZ_ERR_INVALID.  Results do not depend on the form. */
 SQZ_API sqz_status sqz_batch_set_tiled_launch(sqz_batch *b, int32_t persistent, int32_t steps_per_launch,
                                               int32_t wg_per_cu);
 
+/* The launch form in use for the tiled instances (each output may be NULL): *form 0, 1 or 2 as
+ * above (-1: no tiled instances); *steps_per_launch of the single launch (forms 1 and 2);
+ * *wg_per_cu of the persistent launch (form 1, else 0). */
+SQZ_API sqz_status sqz_batch_tiled_launch(const sqz_batch *b, int32_t *form, int32_t *steps_per_launch,
+                                          int32_t *wg_per_cu);
+
 /* Time candidate launch shapes on the given buffers (their contents are advanced by a few steps)
  * and keep the fastest for this batch and for later batches of the same composition in this
- * process: for the tiled instances, steps per launch of each pattern group against one
- * persistent launch (steps per launch x workgroups per compute unit); for the others, workgroups
+ * process: for the tiled instances, steps per launch of each pattern group against one launch
+ * over all of them (steps per launch x one workgroup per tile or persistent workgroups per
+ * compute unit); for the others, workgroups
  * per compute unit and the expanded-tile cost weight.  *wg_per_cu (may be NULL) receives the
  * workgroups per compute unit of the persistent launch timed for the tiled instances (of the
  * other launch when there are none). */

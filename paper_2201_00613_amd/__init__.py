@@ -371,11 +371,25 @@ class Batch:
         self._refresh_steps()
         return int(w.value)
 
-    def set_tiled_launch(self, persistent: bool, steps_per_launch: int = 0, wg_per_cu: int = 0):
-        """Launch form of the instances with a tiled kernel: one launch per pattern group
-        (persistent=False) or one persistent launch over all of them (sqz_batch_set_tiled_launch)."""
-        check(lib().sqz_batch_set_tiled_launch(self._h, int(persistent), steps_per_launch, wg_per_cu))
+    TILED_FORMS = {"groups": 0, "persistent": 1, "per_tile": 2}
+
+    def set_tiled_launch(self, form, steps_per_launch: int = 0, wg_per_cu: int = 0):
+        """Launch form of the instances with a tiled kernel (sqz_batch_set_tiled_launch):
+        "groups" (or False, 0) one launch per pattern group; "persistent" (or True, 1) one
+        persistent launch over all of them; "per_tile" (2) one launch over all of them with a
+        workgroup per tile."""
+        code = self.TILED_FORMS[form] if isinstance(form, str) else int(form)
+        check(lib().sqz_batch_set_tiled_launch(self._h, code, steps_per_launch, wg_per_cu))
         self._refresh_steps()
+
+    @property
+    def tiled_launch(self) -> dict:
+        """The launch form in use for the tiled instances (sqz_batch_tiled_launch):
+        {"form": "groups" | "persistent" | "per_tile" | None, "steps_per_launch", "wg_per_cu"}."""
+        f, k, w = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        check(lib().sqz_batch_tiled_launch(self._h, ctypes.byref(f), ctypes.byref(k), ctypes.byref(w)))
+        names = {v: n for n, v in self.TILED_FORMS.items()}
+        return {"form": names.get(f.value), "steps_per_launch": k.value, "wg_per_cu": w.value}
 
     def _refresh_steps(self):
         k = ctypes.c_int32()

@@ -782,6 +782,17 @@ sqz_status sqz_batch_set_tiled_launch(sqz_batch *b, int32_t persistent, int32_t 
     return batch_set_tiled(b->h, persistent, steps_per_launch, wg_per_cu);
 }
 
+sqz_status sqz_batch_tiled_launch(const sqz_batch *b, int32_t *form, int32_t *steps_per_launch, int32_t *wg_per_cu)
+{
+    if (!b) return set_error(SQZ_ERR_INVALID, "batch is NULL");
+    int32_t f = 0, k = 0, w = 0;
+    batch_tiled_form(b->h, &f, &k, &w);
+    if (form) *form = f;
+    if (steps_per_launch) *steps_per_launch = k;
+    if (wg_per_cu) *wg_per_cu = w;
+    return SQZ_OK;
+}
+
 sqz_status sqz_batch_autotune(sqz_batch *b, uint8_t *d_a, uint8_t *d_b, void *stream, int32_t *wg_per_cu)
 {
     sqz_status st = check_batch_buffers(b, d_a, d_b);

@@ -241,6 +241,7 @@ struct TiledInst {
 struct TiledArgs {
     const TiledInst *inst;
     const uint64_t *cost_start;  // ninst + 1 entries
+    const uint64_t *tile_start;  // ninst + 1 prefix sums of tile counts
     uint32_t ninst;
     uint64_t total_cost;
 };
@@ -285,16 +286,46 @@ __device__ __forceinline__ void bits_unit(const BitboxArgs &A, const uint8_t *in
     }
 }
 
-// K Life steps of every instance with a tiled kernel, one persistent launch:
-// the tiles of all such instances form one sequence weighted by cells;
-// workgroup b takes the tiles whose first cell falls in the b-th equal share
-// and runs each with its pattern's tile body (bit-sliced tiles of the
-// triangle, its mirror image and the Vicsek cross; bit rows of the carpet).
 template <int K>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6)))
+__device__ __forceinline__ void tiled_run(const TiledInst &I, const uint8_t *in, uint8_t *out, uint64_t j,
+                                          unsigned char *smem)
+{
+    const uint8_t *ii = in + I.base;
+    uint8_t *oo = out + I.base;
+    switch (I.kind) {
+    case kBTri: tiled_unit<PatTriangle, K>(I.t, ii, oo, j, smem); break;
+    case kBTriPaper: tiled_unit<PatTrianglePaper, K>(I.t, ii, oo, j, smem); break;
+    case kBVicsek: tiled_unit<PatVicsek, K>(I.t, ii, oo, j, smem); break;
+    default: bits_unit<K>(I.x, ii, oo, j, smem); break;
+    }
+}
+
+// K Life steps of every instance with a tiled kernel in one launch: the tiles
+// of all such instances form one sequence, each run with its pattern's tile
+// body (bit-sliced tiles of the triangle, its mirror image and the Vicsek
+// cross; bit rows of the carpet).  Persistent (PerTile false): the sequence
+// is weighted by cells and workgroup b takes the tiles whose first cell falls
+// in the b-th equal share.  PerTile: one workgroup per tile, dealt to the
+// XCDs in contiguous runs; measured fastest at eight waves per SIMD (a few
+// spilled registers in the bit-row body), the persistent form at six.
+template <int K, bool PerTile>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PerTile ? 8 : 6)))
 k_batch_tiles(TiledArgs B, const uint8_t *__restrict__ in, uint8_t *__restrict__ out)
 {
     extern __shared__ __align__(16) unsigned char smem[];
+    if constexpr (PerTile) {
+        const uint64_t b = xcd_remap(blockIdx.x, gridDim.x);
+        uint32_t a = 0, e = B.ninst;
+        while (e - a > 1) {
+            const uint32_t m = (a + e) / 2;
+            if (B.tile_start[m] <= b)
+                a = m;
+            else
+                e = m;
+        }
+        tiled_run<K>(B.inst[a], in, out, b - B.tile_start[a], smem);
+        return;
+    }
     const uint64_t lo = B.total_cost * blockIdx.x / gridDim.x;
     const uint64_t hi = B.total_cost * (blockIdx.x + 1) / gridDim.x;
     uint32_t a = 0, e = B.ninst;
@@ -319,14 +350,7 @@ k_batch_tiles(TiledArgs B, const uint8_t *__restrict__ in, uint8_t *__restrict__
             continue;
         }
         if (I.cost_start + j * I.unit_cells >= hi) break;
-        const uint8_t *ii = in + I.base;
-        uint8_t *oo = out + I.base;
-        switch (I.kind) {
-        case kBTri: tiled_unit<PatTriangle, K>(I.t, ii, oo, j, smem); break;
-        case kBTriPaper: tiled_unit<PatTrianglePaper, K>(I.t, ii, oo, j, smem); break;
-        case kBVicsek: tiled_unit<PatVicsek, K>(I.t, ii, oo, j, smem); break;
-        default: bits_unit<K>(I.x, ii, oo, j, smem); break;
-        }
+        tiled_run<K>(I, in, out, j, smem);
         ++j;  // every tile body ends with a barrier: LDS is free for the next tile
     }
 }
@@ -346,14 +370,15 @@ struct BatchGroup {
 };
 
 struct BatchHost {
-    // instances with a tiled kernel run either as one launch per pattern group
-    // or as one persistent launch over all of them (the autotuner picks)
+    // instances with a tiled kernel run as one launch per pattern group
+    // (tiled_form 0), one persistent launch over all of them (1) or one launch
+    // over all of them with a workgroup per tile (2); the autotuner picks
     std::vector<BatchGroup> groups;
-    bool persistent_tiles;
+    int tiled_form;
     std::vector<TiledInst> tiled;
     TiledInst *d_tiled;
-    uint64_t *d_tcost;
-    uint64_t tcost_total;
+    uint64_t *d_tcost, *d_ttiles;
+    uint64_t tcost_total, ttiles_total;
     size_t tlds;
     int Kt_max, Kt;             // steps per launch: most allowed, chosen
     unsigned twg, twg_max;      // workgroups per CU: chosen, most resident
@@ -383,7 +408,7 @@ static std::mutex g_tune_mu;
 struct TuneResult {
     unsigned wg, xt_weight, twg;
     int Kt;
-    bool persistent_tiles;
+    int tiled_form;
     std::vector<int> group_K;
 };
 static std::map<std::string, TuneResult> g_tune_cache;  // batch composition -> tuned launch shapes
@@ -555,16 +580,24 @@ sqz_status batch_create(const sqz_fractal *const *fr, int32_t count, BatchHost *
     if (e == hipSuccess && !H->tiled.empty()) {
         const size_t m = H->tiled.size();
         std::vector<uint64_t> cs(m + 1);
-        for (size_t q = 0; q < m; ++q) cs[q] = H->tiled[q].cost_start;
+        std::vector<uint64_t> ts(m + 1);
+        for (size_t q = 0; q < m; ++q) {
+            cs[q] = H->tiled[q].cost_start;
+            ts[q] = H->ttiles_total;
+            H->ttiles_total += H->tiled[q].units;
+        }
         cs[m] = H->tcost_total;
+        ts[m] = H->ttiles_total;
         e = hipMalloc(&H->d_tiled, sizeof(TiledInst) * m);
         if (e == hipSuccess) e = hipMemcpy(H->d_tiled, H->tiled.data(), sizeof(TiledInst) * m, hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMalloc(&H->d_tcost, sizeof(uint64_t) * (m + 1));
         if (e == hipSuccess) e = hipMemcpy(H->d_tcost, cs.data(), sizeof(uint64_t) * (m + 1), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMalloc(&H->d_ttiles, sizeof(uint64_t) * (m + 1));
+        if (e == hipSuccess) e = hipMemcpy(H->d_ttiles, ts.data(), sizeof(uint64_t) * (m + 1), hipMemcpyHostToDevice);
         H->Kt = H->Kt_max;
         int per_cu = 0;
         if (e == hipSuccess)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_tiles<2>, 256, H->tlds);
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_tiles<2, false>, 256, H->tlds);
         H->twg_max = per_cu < 1 ? 1u : (unsigned)per_cu;
         H->twg = H->twg_max;
     }
@@ -610,7 +643,7 @@ sqz_status batch_create(const sqz_fractal *const *fr, int32_t count, BatchHost *
             if (!H->tiled.empty()) {
                 H->twg = std::min(it->second.twg, H->twg_max);
                 H->Kt = std::min(it->second.Kt, H->Kt_max);
-                H->persistent_tiles = it->second.persistent_tiles;
+                H->tiled_form = it->second.tiled_form;
                 for (size_t g = 0; g < H->groups.size() && g < it->second.group_K.size(); ++g)
                     H->groups[g].K = std::min(it->second.group_K[g], H->groups[g].K_max);
             }
@@ -650,6 +683,7 @@ void batch_destroy(BatchHost *H)
     (void)hipFree(H->d_cost_start);
     (void)hipFree(H->d_tiled);
     (void)hipFree(H->d_tcost);
+    (void)hipFree(H->d_ttiles);
     for (BatchGroup &G : H->groups) {
         (void)hipFree(G.d_args);
         (void)hipFree(G.d_base);
@@ -725,31 +759,44 @@ static sqz_status launch_group(const BatchGroup &G, const uint8_t *in, uint8_t *
     return e == hipSuccess ? SQZ_OK : hip_error(e, "batch group launch");
 }
 
-// One launch of `steps` (1..H->Kt_max) steps for every tiled instance.
-static sqz_status launch_tiled(const BatchHost *H, unsigned wg_per_cu, const uint8_t *in, uint8_t *out, int steps,
-                               hipStream_t st)
+template <bool PerTile>
+static void launch_tiles_k(int steps, dim3 g, dim3 b, size_t L, hipStream_t st, const TiledArgs &A, const uint8_t *in,
+                           uint8_t *out)
+{
+    switch (steps) {
+    case 1: hipLaunchKernelGGL((k_batch_tiles<1, PerTile>), g, b, L, st, A, in, out); break;
+    case 2: hipLaunchKernelGGL((k_batch_tiles<2, PerTile>), g, b, L, st, A, in, out); break;
+    case 3: hipLaunchKernelGGL((k_batch_tiles<3, PerTile>), g, b, L, st, A, in, out); break;
+    case 4: hipLaunchKernelGGL((k_batch_tiles<4, PerTile>), g, b, L, st, A, in, out); break;
+    case 5: hipLaunchKernelGGL((k_batch_tiles<5, PerTile>), g, b, L, st, A, in, out); break;
+    case 6: hipLaunchKernelGGL((k_batch_tiles<6, PerTile>), g, b, L, st, A, in, out); break;
+    case 7: hipLaunchKernelGGL((k_batch_tiles<7, PerTile>), g, b, L, st, A, in, out); break;
+    case 8: hipLaunchKernelGGL((k_batch_tiles<8, PerTile>), g, b, L, st, A, in, out); break;
+    case 9: hipLaunchKernelGGL((k_batch_tiles<9, PerTile>), g, b, L, st, A, in, out); break;
+    default: hipLaunchKernelGGL((k_batch_tiles<10, PerTile>), g, b, L, st, A, in, out); break;
+    }
+}
+
+// One launch of `steps` (1..H->Kt_max) steps for every tiled instance: form 1
+// persistent (wg_per_cu workgroups per CU), form 2 one workgroup per tile.
+static sqz_status launch_tiled(const BatchHost *H, int form, unsigned wg_per_cu, const uint8_t *in, uint8_t *out,
+                               int steps, hipStream_t st)
 {
     TiledArgs A;
     A.inst = H->d_tiled;
     A.cost_start = H->d_tcost;
+    A.tile_start = H->d_ttiles;
     A.ninst = (uint32_t)H->tiled.size();
     A.total_cost = H->tcost_total;
-    uint64_t grid = (uint64_t)H->cus * wg_per_cu;
+    uint64_t grid = form == 2 ? H->ttiles_total : (uint64_t)H->cus * wg_per_cu;
     if (grid < 1) grid = 1;
+    if (grid > 0xFFFFFFFFull) return set_error(SQZ_ERR_RANGE, "%llu tiles exceed one launch", (unsigned long long)grid);
     const dim3 g((unsigned)grid), b(256);
     const size_t L = H->tlds;
-    switch (steps) {
-    case 1: hipLaunchKernelGGL(k_batch_tiles<1>, g, b, L, st, A, in, out); break;
-    case 2: hipLaunchKernelGGL(k_batch_tiles<2>, g, b, L, st, A, in, out); break;
-    case 3: hipLaunchKernelGGL(k_batch_tiles<3>, g, b, L, st, A, in, out); break;
-    case 4: hipLaunchKernelGGL(k_batch_tiles<4>, g, b, L, st, A, in, out); break;
-    case 5: hipLaunchKernelGGL(k_batch_tiles<5>, g, b, L, st, A, in, out); break;
-    case 6: hipLaunchKernelGGL(k_batch_tiles<6>, g, b, L, st, A, in, out); break;
-    case 7: hipLaunchKernelGGL(k_batch_tiles<7>, g, b, L, st, A, in, out); break;
-    case 8: hipLaunchKernelGGL(k_batch_tiles<8>, g, b, L, st, A, in, out); break;
-    case 9: hipLaunchKernelGGL(k_batch_tiles<9>, g, b, L, st, A, in, out); break;
-    default: hipLaunchKernelGGL(k_batch_tiles<10>, g, b, L, st, A, in, out); break;
-    }
+    if (form == 2)
+        launch_tiles_k<true>(steps, g, b, L, st, A, in, out);
+    else
+        launch_tiles_k<false>(steps, g, b, L, st, A, in, out);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? SQZ_OK : hip_error(e, "batch tiled launch");
 }
@@ -761,10 +808,10 @@ static sqz_status launch_all(const BatchHost *H, const uint8_t *a, const uint8_t
 {
     sqz_status s2 = SQZ_OK;
     uint8_t *const A = const_cast<uint8_t *>(a), *const B = const_cast<uint8_t *>(b);
-    if (!H->tiled.empty() && H->persistent_tiles) {
+    if (!H->tiled.empty() && H->tiled_form != 0) {
         const std::vector<int> plan = plan_launches(steps, H->Kt);
         for (size_t i = 0; i < plan.size() && s2 == SQZ_OK; ++i)
-            s2 = launch_tiled(H, H->twg, (i & 1) ? B : A, (i & 1) ? A : B, plan[i], st);
+            s2 = launch_tiled(H, H->tiled_form, H->twg, (i & 1) ? B : A, (i & 1) ? A : B, plan[i], st);
     } else {
         for (size_t g = 0; g < H->groups.size() && s2 == SQZ_OK; ++g) {
             const std::vector<int> plan = plan_launches(steps, H->groups[g].K);
@@ -863,29 +910,33 @@ sqz_status batch_autotune(BatchHost *H, uint8_t *a, uint8_t *b, hipStream_t st, 
             G.K = bk;
             grouped_ms += best_ms;
         }
-        const unsigned ws[] = {2, 3, 4, 5, 6, 8};
+        // one launch over all tiled instances: a workgroup per tile (w = 0), or
+        // persistent with w workgroups per CU
+        const unsigned ws[] = {0, 2, 3, 4, 5, 6, 8};
         float best_ms = 1e30f;
         unsigned bw = H->twg;
-        int bk = H->Kt;
+        int bk = H->Kt, bf = 2;
         for (int K : ks) {
             if (K > H->Kt_max || (K == 1 && H->Kt_max > 1)) continue;
             for (unsigned w : ws) {
                 if (w > H->twg_max || st2 != SQZ_OK) continue;
+                const int form = w == 0 ? 2 : 1;
                 float ms = 0.0f;
                 st2 = time_launches(st, e0, e1, [&](int i) {
-                    return launch_tiled(H, w, (i & 1) ? b : a, (i & 1) ? a : b, K, st);
+                    return launch_tiled(H, form, w, (i & 1) ? b : a, (i & 1) ? a : b, K, st);
                 }, 4, &ms);
                 ms /= 4.0f * K;
                 if (st2 == SQZ_OK && ms < best_ms) {
                     best_ms = ms;
-                    bw = w;
+                    bf = form;
+                    if (w) bw = w;
                     bk = K;
                 }
             }
         }
         H->twg = bw;
         H->Kt = bk;
-        H->persistent_tiles = best_ms < grouped_ms;
+        H->tiled_form = best_ms < grouped_ms ? bf : 0;
     }
     // (2) the expanded-tile / thread-level launch: workgroups per CU x the
     // expanded-tile cost weight
@@ -932,7 +983,7 @@ sqz_status batch_autotune(BatchHost *H, uint8_t *a, uint8_t *b, hipStream_t st, 
         std::lock_guard<std::mutex> lk(g_tune_mu);
         std::vector<int> gk;
         for (const BatchGroup &G : H->groups) gk.push_back(G.K);
-        g_tune_cache[H->key] = TuneResult{H->wg_per_cu, H->xt_weight, H->twg, H->Kt, H->persistent_tiles, gk};
+        g_tune_cache[H->key] = TuneResult{H->wg_per_cu, H->xt_weight, H->twg, H->Kt, H->tiled_form, gk};
     }
     if (best_out) *best_out = H->tiled.empty() ? H->wg_per_cu : H->twg;
     return SQZ_OK;
@@ -940,13 +991,13 @@ sqz_status batch_autotune(BatchHost *H, uint8_t *a, uint8_t *b, hipStream_t st, 
 
 sqz_status batch_set_tiled(BatchHost *H, int32_t persistent, int32_t steps_per_launch, int32_t wg_per_cu)
 {
-    if (persistent != 0 && persistent != 1) return set_error(SQZ_ERR_INVALID, "persistent must be 0 or 1");
+    if (persistent < 0 || persistent > 2) return set_error(SQZ_ERR_INVALID, "launch form %d outside 0..2", persistent);
     if (steps_per_launch < 0 || (steps_per_launch > 0 && (H->tiled.empty() || steps_per_launch > H->Kt_max)))
         return set_error(SQZ_ERR_INVALID, "steps_per_launch %d outside 0..%d", steps_per_launch,
                          H->tiled.empty() ? 0 : H->Kt_max);
     if (wg_per_cu < 0 || (wg_per_cu > 0 && (H->tiled.empty() || (unsigned)wg_per_cu > H->twg_max)))
         return set_error(SQZ_ERR_INVALID, "wg_per_cu %d outside 0..%u", wg_per_cu, H->tiled.empty() ? 0u : H->twg_max);
-    H->persistent_tiles = persistent == 1;
+    H->tiled_form = persistent;
     if (steps_per_launch > 0) {
         H->Kt = steps_per_launch;
         for (BatchGroup &G : H->groups) G.K = std::min(steps_per_launch, G.K_max);
@@ -966,12 +1017,18 @@ unsigned batch_wg_per_cu(const BatchHost *H) { return H->wg_per_cu; }
 int batch_steps_per_launch(const BatchHost *H)
 {
     int k = H->has_rest ? H->K : kMaxSteps;
-    if (!H->tiled.empty() && H->persistent_tiles)
+    if (!H->tiled.empty() && H->tiled_form != 0)
         k = std::min(k, H->Kt);
     else
         for (const BatchGroup &G : H->groups) k = std::min(k, G.K);
     return k < 1 ? 1 : k;
 }
 uint64_t batch_total_cells(const BatchHost *H) { return H->total_cells; }
+void batch_tiled_form(const BatchHost *H, int32_t *form, int32_t *steps_per_launch, int32_t *wg_per_cu)
+{
+    *form = H->tiled.empty() ? -1 : H->tiled_form;
+    *steps_per_launch = H->tiled.empty() ? 0 : H->Kt;
+    *wg_per_cu = H->tiled.empty() || H->tiled_form != 1 ? 0 : (int32_t)H->twg;
+}
 
 }  // namespace sqz

@@ -278,6 +278,7 @@ uint64_t batch_offset(const BatchHost *H, int32_t i);
 int32_t batch_count(const BatchHost *H);
 unsigned batch_wg_per_cu(const BatchHost *H);
 int batch_steps_per_launch(const BatchHost *H);
+void batch_tiled_form(const BatchHost *H, int32_t *form, int32_t *steps_per_launch, int32_t *wg_per_cu);
 uint64_t batch_total_cells(const BatchHost *H);
 const FractalHost &fractal_host_of(const sqz_fractal *f);
 sqz_status launch_life_tile(const FractalHost &F, const uint8_t *in, uint8_t *out, hipStream_t st);

@@ -134,11 +134,13 @@ def test_mixed_groups_and_persistent_launch():
             assert torch.equal(B.instance(res, i), y), (i, steps)
 
 
-@pytest.mark.parametrize("steps_per_launch,wg", [(0, 0), (3, 2), (6, 4), (1, 1)])
-def test_persistent_tiled_launch_equals_groups(steps_per_launch, wg):
-    """The tiled instances as one persistent launch (any steps per launch and grid)
-    give the same states as the per-group launches, next to instances of the other
-    persistent launch."""
+@pytest.mark.parametrize("form,steps_per_launch,wg", [("persistent", 0, 0), ("persistent", 3, 2),
+                                                     ("persistent", 6, 4), ("persistent", 1, 1),
+                                                     ("per_tile", 0, 0), ("per_tile", 4, 0), ("per_tile", 1, 0)])
+def test_single_tiled_launch_equals_groups(form, steps_per_launch, wg):
+    """The tiled instances as one launch over all of them (persistent with any grid,
+    or a workgroup per tile; any steps per launch) give the same states as the
+    per-group launches, next to instances of the other persistent launch."""
     torch = torch_or_skip()
     spec = [("triangle", 9), ("carpet", 5), ("vicsek", 6), ("carpet", 2), ("triangle", 12), ("vicsek", 3),
             ("triangle_paper", 10), ("carpet", 6), ("triangle", 1), ("carpet", 0)]
@@ -147,7 +149,7 @@ def test_persistent_tiled_launch_equals_groups(steps_per_launch, wg):
     for steps in (1, 5, 12):
         a = B.fill_bernoulli(seeds, 0.5)
         want = B.run(a, B.empty_state(), steps).clone()
-        B.set_tiled_launch(True, steps_per_launch, wg)
+        B.set_tiled_launch(form, steps_per_launch, wg)
         if steps_per_launch:
             assert B.steps_per_launch <= steps_per_launch
         x = B.fill_bernoulli(seeds, 0.5)
@@ -156,12 +158,28 @@ def test_persistent_tiled_launch_equals_groups(steps_per_launch, wg):
         B.set_tiled_launch(False)
 
 
+def test_tiled_launch_query():
+    torch_or_skip()
+    fr, B = build([("triangle", 9), ("carpet", 5), ("vicsek", 6)])
+    assert B.tiled_launch["form"] == "groups"
+    B.set_tiled_launch("persistent", 3, 2)
+    assert B.tiled_launch == {"form": "persistent", "steps_per_launch": 3, "wg_per_cu": 2}
+    B.set_tiled_launch("per_tile", 5)
+    assert B.tiled_launch == {"form": "per_tile", "steps_per_launch": 5, "wg_per_cu": 0}
+    assert B.steps_per_launch == 5
+    import paper_2201_00613_amd as sqz
+
+    wide = (4, ((0, 0), (1, 0), (3, 0), (0, 1), (2, 1), (3, 1), (1, 2), (2, 2), (0, 3), (3, 3)))
+    C = sqz.Batch([sqz.Fractal(*wide, 3)])  # expanded tiles only: no tiled instance
+    assert C.tiled_launch["form"] is None
+
+
 def test_tiled_launch_arguments():
     torch_or_skip()
     import paper_2201_00613_amd as sqz
 
     fr, B = build([("triangle", 9), ("carpet", 5)])
-    for bad in ((2, 0, 0), (1, -1, 0), (1, 11, 0), (1, 0, -1), (1, 0, 1000)):
+    for bad in ((3, 0, 0), (-1, 0, 0), (1, -1, 0), (1, 11, 0), (1, 0, -1), (1, 0, 1000)):
         with pytest.raises(sqz.SqueezeError) as e:
             B.set_tiled_launch(*bad)
         assert e.value.status == 1
