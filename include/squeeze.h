@@ -74,13 +74,14 @@ typedef enum sqz_layout { SQZ_LAYOUT_COMPACT = 0, SQZ_LAYOUT_EXPANDED = 1 } sqz_
  *                  (any replica pattern; SQZ_ERR_UNSUPPORTED when no level fits).
  *   SQZ_IMPL_CELL_MFMA: CELL with both maps evaluated on the matrix cores
  *                  (SQZ_MAP_MFMA below).  A comparison variant, never chosen by AUTO.
- *   SQZ_IMPL_BITS: block-level Squeeze with the level-M subtree (M <= 5) and a
- *                  six-cell border from the adjacent subtrees expanded on chip
- *                  as bit rows, Life on 32 positions per word (patterns with
- *                  s = 3 and at most 8 replicas that have a kernel: the
- *                  Sierpinski carpet; levels >= 2).  Buffers 8-byte aligned
+ *   SQZ_IMPL_BITS: block-level Squeeze with the level-M subtree (3 <= M <= 5)
+ *                  and a twelve-cell border from the adjacent subtrees expanded
+ *                  on chip as bit rows, Life on 32 positions per word (patterns
+ *                  with s = 3 and at most 8 replicas that have a kernel: the
+ *                  Sierpinski carpet; levels >= 3).  Buffers 8-byte aligned
  *                  (SQZ_ERR_INVALID otherwise); SQZ_ERR_UNSUPPORTED for other
- *                  patterns.  Up to 6 steps per launch in sqz_compact_run. */
+ *                  patterns and levels.  Up to 10 steps per launch in
+ *                  sqz_compact_run. */
 typedef enum sqz_impl {
     SQZ_IMPL_AUTO = 0,
     SQZ_IMPL_CELL = 1,
@@ -147,7 +148,7 @@ typedef struct sqz_info {
     int32_t xtile_level; /* level of the expanded tiles of SQZ_IMPL_XTILE (0 if none) */
     int32_t run_steps_per_launch; /* Life steps per launch in sqz_compact_run with aligned buffers:
                                      up to 10 with multi-step tiled kernels (temporal blocking;
-                                     16-byte alignment), 6 with bit-row tiles (8-byte), 3 with
+                                     16-byte alignment) or bit-row tiles (8-byte), 3 with
                                      multi-step expanded tiles, else 1 */
     int32_t bits_level;  /* level M of the bit-row tiles of SQZ_IMPL_BITS (0 if none) */
 } sqz_info;

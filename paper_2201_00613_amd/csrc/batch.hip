@@ -306,8 +306,8 @@ __device__ __forceinline__ void tiled_run(const TiledInst &I, const uint8_t *in,
 // cross; bit rows of the carpet).  Persistent (PerTile false): the sequence
 // is weighted by cells and workgroup b takes the tiles whose first cell falls
 // in the b-th equal share.  PerTile: one workgroup per tile, dealt to the
-// XCDs in contiguous runs; measured fastest at eight waves per SIMD (a few
-// spilled registers in the bit-row body), the persistent form at six.
+// XCDs in contiguous runs, eight waves per SIMD; the persistent form at six
+// (its tile loop holds more registers).
 template <int K, bool PerTile>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PerTile ? 8 : 6)))
 k_batch_tiles(TiledArgs B, const uint8_t *__restrict__ in, uint8_t *__restrict__ out)
@@ -740,7 +740,11 @@ static void launch_bits_group(const GroupArgs &A, unsigned grid, const uint8_t *
     case 3: hipLaunchKernelGGL((k_batch_bitbox<PatCarpet, 3>), g, b, 0, st, A, in, out); break;
     case 4: hipLaunchKernelGGL((k_batch_bitbox<PatCarpet, 4>), g, b, 0, st, A, in, out); break;
     case 5: hipLaunchKernelGGL((k_batch_bitbox<PatCarpet, 5>), g, b, 0, st, A, in, out); break;
-    default: hipLaunchKernelGGL((k_batch_bitbox<PatCarpet, 6>), g, b, 0, st, A, in, out); break;
+    case 6: hipLaunchKernelGGL((k_batch_bitbox<PatCarpet, 6>), g, b, 0, st, A, in, out); break;
+    case 7: hipLaunchKernelGGL((k_batch_bitbox<PatCarpet, 7>), g, b, 0, st, A, in, out); break;
+    case 8: hipLaunchKernelGGL((k_batch_bitbox<PatCarpet, 8>), g, b, 0, st, A, in, out); break;
+    case 9: hipLaunchKernelGGL((k_batch_bitbox<PatCarpet, 9>), g, b, 0, st, A, in, out); break;
+    default: hipLaunchKernelGGL((k_batch_bitbox<PatCarpet, 10>), g, b, 0, st, A, in, out); break;
     }
 }
 

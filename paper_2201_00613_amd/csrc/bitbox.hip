@@ -9,7 +9,7 @@
 namespace sqz {
 
 template <class Pat, int K>
-__global__ void __launch_bounds__(kBxThreads) __attribute__((amdgpu_waves_per_eu(6)))
+__global__ void __launch_bounds__(kBxThreads) __attribute__((amdgpu_waves_per_eu(8)))
 k_life_bitbox(BitboxArgs A, const uint8_t *__restrict__ in, uint8_t *__restrict__ out)
 {
     __shared__ uint32_t s_buf[2][kBxBuf];
@@ -63,7 +63,7 @@ sqz_status bx_prepare(FractalHost &F)
             if (inner) continue;
             int dir;
             const int64_t lb = outside_block(gx, gy, dir);
-            if (lb >= 0) ring.push_back((uint32_t)(gy * kBxGP + gx) | (uint32_t)dir << 13 | (uint32_t)lb << 17);
+            if (lb >= 0) ring.push_back((uint32_t)(gy * kBxGP + gx) | (uint32_t)dir << 14 | (uint32_t)lb << 18);
         }
     C->nring = (uint32_t)ring.size();
     // membership of every box position (adjacent tiles present)
@@ -119,7 +119,11 @@ sqz_status bx_launch(const FractalHost &F, const uint8_t *in, uint8_t *out, int 
     case 3: hipLaunchKernelGGL((k_life_bitbox<Pat, 3>), grid, block, 0, st, A, in, out); break;
     case 4: hipLaunchKernelGGL((k_life_bitbox<Pat, 4>), grid, block, 0, st, A, in, out); break;
     case 5: hipLaunchKernelGGL((k_life_bitbox<Pat, 5>), grid, block, 0, st, A, in, out); break;
-    default: hipLaunchKernelGGL((k_life_bitbox<Pat, 6>), grid, block, 0, st, A, in, out); break;
+    case 6: hipLaunchKernelGGL((k_life_bitbox<Pat, 6>), grid, block, 0, st, A, in, out); break;
+    case 7: hipLaunchKernelGGL((k_life_bitbox<Pat, 7>), grid, block, 0, st, A, in, out); break;
+    case 8: hipLaunchKernelGGL((k_life_bitbox<Pat, 8>), grid, block, 0, st, A, in, out); break;
+    case 9: hipLaunchKernelGGL((k_life_bitbox<Pat, 9>), grid, block, 0, st, A, in, out); break;
+    default: hipLaunchKernelGGL((k_life_bitbox<Pat, 10>), grid, block, 0, st, A, in, out); break;
     }
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? SQZ_OK : hip_error(e, "compact step (bit rows) launch");
@@ -130,7 +134,8 @@ sqz_status bx_launch(const FractalHost &F, const uint8_t *in, uint8_t *out, int 
 sqz_status bitbox_prepare(FractalHost &F)
 {
     F.bitbox = nullptr;
-    if (F.r >= 2 && bx_matches<PatCarpet>(F)) return bx_prepare<PatCarpet>(F);
+    // tiles of level >= 3: the border (four blocks) must lie in the eight adjacent tiles
+    if (F.r >= 3 && bx_matches<PatCarpet>(F)) return bx_prepare<PatCarpet>(F);
     return SQZ_OK;
 }
 

@@ -8,10 +8,11 @@
 //         3^M x 3^M region of the expanded plane.
 // Block = a level-1 subtree: k <= 8 consecutive compact cells in one 3 x 3
 //         box, held as one byte of bits (bit j = replica j).
-// Box   = the tile's blocks plus a border two blocks (six cells) wide from the
-//         eight adjacent tiles, as bit rows: row y, word w = columns
-//         32w .. 32w+31.  With a six-cell border one launch takes up to six
-//         steps: each step invalidates one more cell along the box edge.
+// Box   = the tile's blocks plus a border four blocks (twelve cells) wide
+//         from the eight adjacent tiles, as bit rows: row y, word w = columns
+//         32w .. 32w+31.  With a twelve-cell border one launch could take up
+//         to twelve steps (each step invalidates one more cell along the box
+//         edge); it takes up to ten, as the bit-sliced tiles do.
 //
 // Per tile: (A) each block's eight bytes are packed to one byte of bits and
 // placed in a block grid (one byte per block position, tile-invariant
@@ -20,7 +21,7 @@
 // twelve consecutive grid bytes: the row's three bits of each block are cut
 // out of four bytes at a time and packed together.  (C) K Life rounds on the
 // row words, bit-sliced with full adders: a lane owns one word column of
-// eight consecutive rows and slides a window over them; new states are
+// ten consecutive rows and slides a window over them; new states are
 // masked by the tile-invariant membership of each position and by whether
 // the adjacent tile it lies in exists.  (D) Each block's byte is read back
 // from three rows and unpacked to eight bytes.
@@ -37,20 +38,35 @@ struct PatCarpet {  // Sierpinski carpet, replicas row by row
     static constexpr int OY[8] = {0, 0, 0, 1, 1, 2, 2, 2};
 };
 
-constexpr int kBxW = 8;                      // row words (256 columns)
-constexpr int kBxP = 9;                      // row pitch in words; word 8 is a zero pad
-constexpr int kBxRows = 256;                 // box rows; rows past the box stay zero
-constexpr int kBxBuf = 1 + (kBxRows + 2) * kBxP;  // a zero word, a zero guard row above and below
-// LDS word of row y (-1 .. kBxRows), word w (-1 .. 8)
+constexpr int kBxBorder = 4;                 // border blocks on each side
+constexpr int kBxBC = 3 * kBxBorder;         // border cells on each side
+constexpr int kBxMMax = 5;                   // tile level: 3^5 + 24 = 267 columns
+// Rows are kBxW words with no pad between them: columns 267 .. 287 are
+// always zero (outside every box, masked by membership), so word 8's right
+// neighbour (word 0 of the next row) and word 0's left neighbour (word 8 of
+// the row before) only ever shift zeros or masked columns into the box.
+constexpr int kBxW = 9;                      // row words (288 columns)
+constexpr int kBxP = kBxW;                   // row pitch in words
+constexpr int kBxSR = 10;                    // rows of one lane's strip
+constexpr int kBxStrips = 27;                // strips: 27 x 10 rows >= 267
+constexpr int kBxLanes = kBxW * kBxStrips;   // lanes with a word column (243)
+constexpr int kBxRows = kBxStrips * kBxSR;   // box rows (270); rows past the box stay zero
+// a zero word, a zero guard row above and below, and a zero word after it (read as the
+// right neighbour of the guard row's last word)
+constexpr int kBxBuf = 2 + (kBxRows + 2) * kBxP;
+// LDS word of row y (-1 .. kBxRows), word w (-1 .. 9; -1 and 9 only at the buffer's ends or as
+// the zero columns of the adjacent row)
 __host__ __device__ constexpr int bx_at(int y, int w) { return 1 + (y + 1) * kBxP + w; }
-constexpr int kBxGP = 96;                    // bytes per block-grid row
-constexpr int kBxGR = 85;                    // block-grid rows: 3^4 + 2 * 2
-constexpr int kBxMMax = 5;                   // tile level: 3^5 + 12 = 255 columns
-constexpr int kBxBorder = 2;                 // border blocks on each side
-constexpr int kBxMaxSteps = 3 * kBxBorder;   // Life steps per launch
+constexpr int kBxGR = 81 + 2 * kBxBorder;    // block-grid rows (and columns): 3^4 + 2 * 4
+constexpr int kBxGP = 100;                   // bytes per block-grid row (a row word reads 16 bytes from byte 84)
+constexpr int kBxMaxSteps = 10;              // Life steps per launch (<= kBxBC)
 constexpr int kBxThreads = 256;
 constexpr int kBxMaxBlocks = 4096;           // k^(M-1) <= 8^4
 static_assert(kBxGR * kBxGP <= kBxBuf * 4, "the block grid lives in the second row buffer");
+static_assert(kBxLanes <= kBxThreads && kBxRows >= 3 * kBxGR && 32 * kBxW > 3 * kBxGR, "box fits the lanes");
+static_assert(2 * kBxBuf * 4 + 9 * 8 + 4 <= 20 * 1024, "eight workgroups per CU");
+static_assert(kBxMaxSteps <= kBxBC, "a step per border cell");
+static_assert(kBxGR * kBxGP < (1 << 14), "ring slots hold the grid byte in 14 bits");
 
 struct BitboxConfig {
     int M;
@@ -60,8 +76,8 @@ struct BitboxConfig {
     uint32_t nring;   // border blocks that can exist
     uint64_t ntiles;  // k^(r-M)
     uint16_t *d_bpos;    // [nblk] grid position of each block: x | y << 7
-    uint32_t *d_ring;    // [nring] grid byte | direction << 13 | block index in that tile << 17
-    uint32_t *d_member;  // [256][8] membership of every box position, adjacent tiles present
+    uint32_t *d_ring;    // [nring] grid byte | direction << 14 | block index in that tile << 18
+    uint32_t *d_member;  // [kBxRows][kBxW] membership of every box position, adjacent tiles present
     MapParams Pc;        // maps at the coarse level r-M
     void *d_coarse;
     unsigned grid;
@@ -193,16 +209,19 @@ __device__ __forceinline__ void bitbox_tile(const BitboxArgs &A, const uint8_t *
 {
     uint32_t &s_ex = *s_ex_p;
     const uint32_t tid = threadIdx.x;
-    const int lw = (int)(tid & 7), ls = (int)(tid >> 3);  // word column, strip of rows 8 ls .. 8 ls + 7
+    // word column and strip of rows kBxSR ls .. kBxSR ls + kBxSR - 1 (lanes past kBxLanes idle in phase C)
+    const bool act = tid < (uint32_t)kBxLanes;
+    const int lw = act ? (int)(tid % kBxW) : 0, ls = act ? (int)(tid / kBxW) : 0;
     uint8_t *const G = reinterpret_cast<uint8_t *>(s_buf[1]);
     const int side = (int)A.side;
-    const uint32_t mL = col_mask(0, 6, lw), mC = col_mask(6, 6 + side, lw), mR = col_mask(6 + side, 12 + side, lw);
+    const uint32_t mL = col_mask(0, kBxBC, lw), mC = col_mask(kBxBC, kBxBC + side, lw),
+                   mR = col_mask(kBxBC + side, 2 * kBxBC + side, lw);
     {
         const uint64_t base = t * A.tile;
         // membership of this lane's words with the adjacent tiles present (tile-invariant table)
-        uint32_t eff[8];
+        uint32_t eff[kBxSR];
 #pragma unroll
-        for (int r = 0; r < 8; ++r) eff[r] = A.member[(8 * ls + r) * kBxW + lw];
+        for (int r = 0; r < kBxSR; ++r) eff[r] = act ? A.member[(kBxSR * ls + r) * kBxW + lw] : 0u;
         if (tid < 64) {
             bool here = false;
             if (tid < 9) {
@@ -234,10 +253,10 @@ __device__ __forceinline__ void bitbox_tile(const BitboxArgs &A, const uint8_t *
         }
         for (uint32_t i = tid; i < A.nring; i += kBxThreads) {
             const uint32_t slot = A.ring[i];
-            const uint64_t nb = s_nb[(slot >> 13) & 15u];
+            const uint64_t nb = s_nb[(slot >> 14) & 15u];
             if (nb != kHole64) {
-                const uint2 d = *reinterpret_cast<const uint2 *>(in + nb + 8ull * (slot >> 17));
-                G[slot & 0x1FFFu] = (uint8_t)pack8(d.x, d.y);
+                const uint2 d = *reinterpret_cast<const uint2 *>(in + nb + 8ull * (slot >> 18));
+                G[slot & 0x3FFFu] = (uint8_t)pack8(d.x, d.y);
             }
         }
         const uint32_t ex = s_ex;
@@ -245,7 +264,7 @@ __device__ __forceinline__ void bitbox_tile(const BitboxArgs &A, const uint8_t *
 
         // (B) row words from the grid: unit (block row R, word w) makes rows 3R .. 3R+2
         for (uint32_t u = tid; u < (uint32_t)(kBxGR * kBxW); u += kBxThreads) {
-            const uint32_t R = u >> 3, w = u & 7;
+            const uint32_t R = u / kBxW, w = u - R * kBxW;
             const uint32_t C0 = 32 * w / 3, dl = 32 * w - 3 * C0, C0a = C0 & ~3u, o = C0 - C0a;
             const uint32_t *g = reinterpret_cast<const uint32_t *>(G + R * kBxGP + C0a);
             const uint32_t g0 = g[0], g1 = g[1], g2 = g[2], g3 = g[3];
@@ -256,29 +275,28 @@ __device__ __forceinline__ void bitbox_tile(const BitboxArgs &A, const uint8_t *
             s_buf[0][bx_at(3 * R + 2, w)] = bx_rowword<Pat, 2>(a, dl);
         }
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            const int y = 8 * ls + r, ry = y < 6 ? 0 : (y < 6 + side ? 1 : 2);
+        for (int r = 0; r < kBxSR; ++r) {
+            const int y = kBxSR * ls + r, ry = y < kBxBC ? 0 : (y < kBxBC + side ? 1 : 2);
             const uint32_t e3 = ex >> (3 * ry);
             eff[r] &= ((e3 & 1u) ? mL : 0u) | ((e3 & 2u) ? mC : 0u) | ((e3 & 4u) ? mR : 0u);
         }
         __syncthreads();
 
-        // (C) K rounds; lane: word lw of rows 8 ls .. 8 ls + 7, sliding over rows 8 ls - 1 .. 8 ls + 8
-#pragma unroll
+        // (C) K rounds; lane: word lw of rows kBxSR ls .. kBxSR ls + kBxSR - 1, sliding over one
+        // row more on either side
+#pragma unroll 1
         for (int j = 1; j <= K; ++j) {
             const uint32_t *src = s_buf[(j - 1) & 1];
             uint32_t *dst = s_buf[j & 1];
-            BxRow up = bx_row(src + bx_at(8 * ls - 1, lw)), mid = bx_row(src + bx_at(8 * ls, lw));
+            if (act) {
+                BxRow up = bx_row(src + bx_at(kBxSR * ls - 1, lw)), mid = bx_row(src + bx_at(kBxSR * ls, lw));
 #pragma unroll
-            for (int r = 0; r < 8; ++r) {
-                const BxRow dn = bx_row(src + bx_at(8 * ls + r + 1, lw));
-                dst[bx_at(8 * ls + r, lw)] = bx_life(up, mid, dn) & eff[r];
-                up = mid;
-                mid = dn;
-            }
-            if (lw == 0) {  // pad words (the block grid may have left bytes there)
-#pragma unroll
-                for (int r = 0; r < 8; ++r) dst[bx_at(8 * ls + r, 8)] = 0u;
+                for (int r = 0; r < kBxSR; ++r) {
+                    const BxRow dn = bx_row(src + bx_at(kBxSR * ls + r + 1, lw));
+                    dst[bx_at(kBxSR * ls + r, lw)] = bx_life(up, mid, dn) & eff[r];
+                    up = mid;
+                    mid = dn;
+                }
             }
             if (tid <= (uint32_t)kBxP) dst[tid] = 0u;  // the zero word and the guard row above row 0
             __syncthreads();

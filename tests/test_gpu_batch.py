@@ -49,16 +49,15 @@ def test_small_mixed_batch_matches_oracle():
 
 def test_multi_step_runs_equal_eager_steps():
     """Every instance is in a group of a multi-step kernel (single-tile ones
-    included): triangle and Vicsek tiles take up to ten steps per launch, carpet
-    bit rows six, so the batch reports six; any step count equals that many
-    one-step launches."""
+    included): triangle and Vicsek tiles and carpet bit rows take up to ten
+    steps per launch; any step count equals that many one-step launches."""
     torch = torch_or_skip()
-    spec = [("triangle", 9), ("carpet", 5), ("vicsek", 6), ("carpet", 2), ("triangle", 12), ("vicsek", 3),
+    spec = [("triangle", 9), ("carpet", 5), ("vicsek", 6), ("carpet", 3), ("triangle", 12), ("vicsek", 3),
             ("triangle_paper", 10), ("carpet", 6)]
     fr, B = build(spec)
-    assert B.steps_per_launch == 6
+    assert B.steps_per_launch == 10
     seeds = [31 * i + 1 for i in range(len(fr))]
-    for steps in (1, 2, 3, 4, 5, 6, 7, 9, 10, 13, 14, 21):
+    for steps in (1, 2, 3, 4, 5, 6, 7, 9, 10, 11, 13, 14, 20, 21, 23):
         a, b = B.fill_bernoulli(seeds, 0.5), B.empty_state()
         res = B.run(a, b, steps)
         assert res is (a if steps % 2 == 0 else b)

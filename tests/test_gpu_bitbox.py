@@ -11,11 +11,19 @@ from gpu_common import gpu_fractal, mismatch, oracle_fractal, to_np, torch_or_sk
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("r", [2, 3, 4, 5, 6])
+def test_no_bit_rows_below_level_3():
+    """A level-2 tile is narrower than the four-block border: such carpets use the
+    expanded tiles."""
+    torch_or_skip()
+    for r in (0, 1, 2):
+        assert gpu_fractal("carpet", r).bits_level == 0
+
+
+@pytest.mark.parametrize("r", [3, 4, 5, 6])
 def test_step_matches_oracle(r):
     torch = torch_or_skip()
     F, O = gpu_fractal("carpet", r), oracle_fractal("carpet", r)
-    assert F.bits_level == min(r, 5) and F.run_steps_per_launch == 6
+    assert F.bits_level == min(r, 5) and F.run_steps_per_launch == 10
     nb = O.neighbour_table()
     for seed, p in ((2201, 0.5), (7, 0.3), (11, 0.8)):
         start = O.fill_compact(seed, p)
@@ -31,7 +39,7 @@ def test_run_equals_single_steps_and_oracle(r):
     F, O = gpu_fractal("carpet", r), oracle_fractal("carpet", r)
     start = O.fill_compact(2201, 0.5)
     nb = O.neighbour_table() if F.cells <= 300_000 else None
-    for steps in range(0, 15):
+    for steps in range(0, 24):
         a = F.fill_bernoulli(2201, 0.5)
         b = torch.zeros_like(a)
         res = F.compact_run(a, b, steps)
@@ -41,11 +49,11 @@ def test_run_equals_single_steps_and_oracle(r):
             F.compact_step(x, y, impl="xtile")
             x, y = y, x
         assert torch.equal(res, x), (r, steps)
-        if nb is not None and steps in (2, 5, 6, 7, 13):
+        if nb is not None and steps in (2, 5, 6, 7, 10, 13, 21):
             mismatch(to_np(res), O.life_steps(start, steps, nb), f"carpet r={r} {steps} steps")
 
 
-@pytest.mark.parametrize("steps", [1, 3, 6, 12])
+@pytest.mark.parametrize("steps", [1, 3, 6, 10, 12, 21])
 def test_all_alive(steps):
     """Every cell alive at t = 0: border cells change in the first step."""
     torch = torch_or_skip()
@@ -56,14 +64,14 @@ def test_all_alive(steps):
 
 
 def test_r9_run_equals_expanded_tiles():
-    """The benchmark level (134,217,728 cells, 4,096 tiles): a 13-step run (launches
-    of 6, 6 and 1) equals 13 one-step expanded-tile launches."""
+    """The benchmark level (134,217,728 cells, 4,096 tiles): a 23-step run (launches
+    of 10, 10 and 3) equals 23 one-step expanded-tile launches."""
     torch = torch_or_skip()
     F = gpu_fractal("carpet", 9)
     a = F.fill_bernoulli(2201, 0.5)
-    r1 = F.compact_run(a.clone(), torch.empty_like(a), 13)
+    r1 = F.compact_run(a.clone(), torch.empty_like(a), 23)
     x, y = a.clone(), torch.empty_like(a)
-    for _ in range(13):
+    for _ in range(23):
         F.compact_step(x, y, impl="xtile")
         x, y = y, x
     assert torch.equal(r1, x)
