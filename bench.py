@@ -293,12 +293,13 @@ def repeat_stats(torch, F, seed, p, steps: int, reps: int) -> dict:
 
 
 def carpet_life_leg(torch, sqz, steps: int) -> dict:
-    """Life on the level-9 Sierpinski carpet (134,217,728 cells; expanded tiles, several
-    steps per launch), Bernoulli(0.5), `steps` steps as one sqz_compact_run call."""
+    """Life on the level-9 Sierpinski carpet (134,217,728 cells; bit-row tiles, up to ten
+    steps per launch), Bernoulli(0.5), `steps` steps as one sqz_compact_run call, after
+    an untimed run of the same steps (a first run in the process is measurably slower)."""
     from paper_2201_00613_amd import workloads as W
 
     F = sqz.Fractal(*W.CARPET, 9)
-    sec = compact_run(torch, F, 2201, 0.5, steps, 3)
+    sec = compact_run(torch, F, 2201, 0.5, steps, steps)
     launches = run_launches(F, steps)
     res = {"fractal": "sierpinski carpet s=3 k=8", "level": 9, "cells": F.cells, "steps": steps,
            "steps_per_launch": F.run_steps_per_launch, "launches": launches, "ms_per_step": sec * 1e3 / steps,
