@@ -1,6 +1,7 @@
 // Bit-sliced block-level Life kernels (device code in tile_device.h) and
 // their host-side preparation: tile halo slots, block-halo tables, per-tile
 // halo indices.
+#include <type_traits>
 #include <vector>
 
 #include "tile_device.h"
@@ -11,6 +12,14 @@ namespace sqz {
 #define SQZ_TILE_NT 256
 #endif
 constexpr int kTileNT = SQZ_TILE_NT;
+
+// Lanes per workgroup of a pattern's tiled kernels: 512 for the level-10
+// tiles of large triangles (2,187 blocks), else kTileNT.
+template <class Pat>
+constexpr int nt_of()
+{
+    return std::is_same<Pat, PatTriangleBig>::value ? 512 : kTileNT;
+}
 
 template <class Pat, int NT>
 __global__ void __launch_bounds__(NT) k_life_tile(TileArgs A, const uint8_t *__restrict__ in,
@@ -287,7 +296,7 @@ sqz_status launch(const FractalHost &F, const uint8_t *in, uint8_t *out, int ste
                          T->ksteps);
     const TileArgs A = tile_args(F);
     const uint64_t grid = T->ntiles < (1ull << 20) ? T->ntiles : (1ull << 20);
-    constexpr int NT = kTileNT;
+    constexpr int NT = nt_of<Pat>();
     switch (steps) {
     case 1: hipLaunchKernelGGL((k_life_tile<Pat, NT>), dim3((unsigned)grid), dim3(NT), 0, st, A, in, out); break;
     case 2: hipLaunchKernelGGL((k_life_tileK<Pat, 2, NT>), dim3((unsigned)grid), dim3(NT), 0, st, A, in, out); break;
@@ -304,12 +313,13 @@ sqz_status launch(const FractalHost &F, const uint8_t *in, uint8_t *out, int ste
     return e == hipSuccess ? SQZ_OK : hip_error(e, "compact step (tile) launch");
 }
 
-enum { kNone = 0, kTriangle = 1, kTrianglePaper = 2, kVicsek = 3 };
+enum { kNone = 0, kTriangle = 1, kTrianglePaper = 2, kVicsek = 3, kTriangleBig = 4 };
 
 }  // namespace
 
 int tile_kind_for(const FractalHost &F)
 {
+    if (matches<PatTriangle>(F) && F.r >= SQZ_TRI_TILE_BIG_FROM) return kTriangleBig;
     if (matches<PatTriangle>(F) && F.r >= PatTriangle::J) return kTriangle;
     if (matches<PatTrianglePaper>(F) && F.r >= PatTrianglePaper::J) return kTrianglePaper;
     if (matches<PatVicsek>(F) && F.r >= PatVicsek::J) return kVicsek;
@@ -320,6 +330,7 @@ sqz_status tile_prepare(FractalHost &F)
 {
     switch (F.tile_kind) {
     case kTriangle: return prepare<PatTriangle>(F);
+    case kTriangleBig: return prepare<PatTriangleBig>(F);
     case kTrianglePaper: return prepare<PatTrianglePaper>(F);
     case kVicsek: return prepare<PatVicsek>(F);
     }
@@ -351,6 +362,7 @@ sqz_status launch_life_tile_steps(const FractalHost &F, const uint8_t *in, uint8
 {
     switch (F.tile_kind) {
     case kTriangle: return launch<PatTriangle>(F, in, out, steps, st);
+    case kTriangleBig: return launch<PatTriangleBig>(F, in, out, steps, st);
     case kTrianglePaper: return launch<PatTrianglePaper>(F, in, out, steps, st);
     case kVicsek: return launch<PatVicsek>(F, in, out, steps, st);
     }

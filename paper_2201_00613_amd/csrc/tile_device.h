@@ -37,8 +37,8 @@ namespace sqz {
 // Replica patterns with a tiled kernel.  Replica j is at (OX[j], OY[j]).
 // ---------------------------------------------------------------------------
 // Build-time knobs (defaults are the tuned values).
-#ifndef SQZ_TRI_TILE_LEVEL  // triangle tile level for large fractals
-#define SQZ_TRI_TILE_LEVEL 9
+#ifndef SQZ_TRI_TILE_LEVEL  // triangle tile level for large fractals (512-lane workgroups)
+#define SQZ_TRI_TILE_LEVEL 10
 #endif
 #ifndef SQZ_TRI_TILE_BIG_FROM  // fractal level from which triangle tiles use SQZ_TRI_TILE_LEVEL (else 8)
 #define SQZ_TRI_TILE_BIG_FROM 16
@@ -52,14 +52,23 @@ namespace sqz {
 
 // Tile level M: MMAX for fractals of level >= MBIG, else MSMALL (more,
 // smaller tiles keep a smaller fractal's launch balanced; from level 16 the
-// larger triangle tile is faster with several steps per launch).
+// larger triangle tile is faster with several steps per launch).  Large
+// triangles are their own pattern type, with level-10 tiles and 512-lane
+// workgroups (all of a level-16 triangle's 729 tiles resident at once), so
+// that the kernels for smaller triangles (and the batch) keep LDS sized for
+// level-8 tiles.
 struct PatTriangle {  // Sierpinski triangle, member iff x & y == 0
-    static constexpr int S = 2, K = 3, J = 3, MMAX = SQZ_TRI_TILE_LEVEL, MSMALL = 8, MBIG = SQZ_TRI_TILE_BIG_FROM;
+    static constexpr int S = 2, K = 3, J = 3, MMAX = 8, MSMALL = 8, MBIG = 0;
+    static constexpr int OX[3] = {0, 1, 0};
+    static constexpr int OY[3] = {0, 0, 1};
+};
+struct PatTriangleBig {  // the same pattern, fractal level >= SQZ_TRI_TILE_BIG_FROM
+    static constexpr int S = 2, K = 3, J = 3, MMAX = SQZ_TRI_TILE_LEVEL, MSMALL = SQZ_TRI_TILE_LEVEL, MBIG = 0;
     static constexpr int OX[3] = {0, 1, 0};
     static constexpr int OY[3] = {0, 0, 1};
 };
 struct PatTrianglePaper {  // the paper's orientation: top, middle, right
-    static constexpr int S = 2, K = 3, J = 3, MMAX = SQZ_TRI_TILE_LEVEL, MSMALL = 8, MBIG = SQZ_TRI_TILE_BIG_FROM;
+    static constexpr int S = 2, K = 3, J = 3, MMAX = 9, MSMALL = 8, MBIG = SQZ_TRI_TILE_BIG_FROM;
     static constexpr int OX[3] = {0, 0, 1};
     static constexpr int OY[3] = {0, 1, 1};
 };
