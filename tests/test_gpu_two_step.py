@@ -59,3 +59,22 @@ def test_r16_run_equals_single_steps():
         F.compact_step(x, y, impl="tile")
         x, y = y, x
     assert torch.equal(r1, x)
+
+
+@pytest.mark.parametrize("r", [15, 16, 17])
+def test_large_triangle_tiles_equal_thread_level(r):
+    """From level 16 the triangle runs level-10 tiles in 512-lane workgroups (below
+    it level-8 tiles): a 13-step run (launches of 10 and 3) equals 13 thread-level
+    steps, which share no code with the tiles."""
+    torch = torch_or_skip()
+    F = gpu_fractal("triangle", r)
+    assert F.tile_level == (10 if r >= 16 else 8) and F.run_steps_per_launch == 10
+    a = F.fill_bernoulli(31, 0.4)
+    r1 = F.compact_run(a.clone(), torch.empty_like(a), 13)
+    x, y = a.clone(), torch.empty_like(a)
+    for _ in range(13):
+        F.compact_step(x, y, impl="cell")
+        x, y = y, x
+    assert torch.equal(r1, x)
+    del a, r1, x, y
+    torch.cuda.empty_cache()
