@@ -355,7 +355,8 @@ def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=20,
+                    help="untimed steps first (20: two launches of the ten-step kernel the timed run uses)")
     ap.add_argument("--level", type=int, default=16)
     ap.add_argument("--impl", default="auto", choices=["auto", "tile", "cell"])
     ap.add_argument("--bb-steps", type=int, default=10)
