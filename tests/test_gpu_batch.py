@@ -249,3 +249,21 @@ def test_batch_argument_errors():
     s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     assert L.sqz_batch_step(B._h, ctypes.c_void_p(big.data_ptr() + 1), ctypes.c_void_p(a.data_ptr()), s) == 1
     assert L.sqz_batch_create(0, None, ctypes.byref(ctypes.c_void_p())) == 1
+
+
+def test_large_triangle_in_a_batch():
+    """A level-16 triangle (level-10 tiles of its own kernel) in a batch runs in the
+    batch's expanded-tile launch; its states equal its own compact_run."""
+    torch = torch_or_skip()
+    spec = [("triangle", 16), ("carpet", 5), ("vicsek", 6), ("triangle", 10)]
+    fr, B = build(spec)
+    seeds = [5, 6, 7, 8]
+    for steps in (1, 7, 12):
+        a = B.fill_bernoulli(seeds, 0.5)
+        res = B.run(a, B.empty_state(), steps)
+        for i, F in enumerate(fr):
+            x = F.fill_bernoulli(seeds[i], 0.5)
+            y = F.compact_run(x, torch.empty_like(x), steps)
+            assert torch.equal(B.instance(res, i), y), (i, steps)
+    del B, fr
+    torch.cuda.empty_cache()
