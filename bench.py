@@ -3,9 +3,11 @@
 Workload (N=1): level-16 Sierpinski triangle, replicas (0,0),(1,0),(0,1),
 43,046,721 compact cells, uint8 states from a Bernoulli(0.5) SplitMix64 start
 (seed 2201), B3/S23 steps ping-ponging between two compact buffers.  One
-"step" is one launch of the compact stencil over every cell.  The same steps
-on the 65536 x 65536 bounding-box grid give the speedup; the level-20 triangle
-(3.49e9 cells, 20 steps, Bernoulli(0.3)) gives the HBM-bound figure.
+"step" is one B3/S23 update of every cell; sqz_compact_run advances up to ten
+steps per kernel launch (temporal blocking), so K timed steps are fewer
+launches.  The same steps on the 65536 x 65536 bounding-box grid give the
+speedup; the level-20 triangle (3.49e9 cells, 20 steps, Bernoulli(0.3)) gives
+the largest workload.
 
 Prints one JSON line.  Inputs are resident in HBM before timing starts.
 """

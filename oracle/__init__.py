@@ -73,6 +73,8 @@ def lib() -> ctypes.CDLL:
             "orc_neighbour_table": (None, [c_int, c_int, i32p, c_int, c_u64, c_u64, i64p]),
             "orc_diffuse_table": (None, [c_i64, i64p, c_dbl, c_int, f64p, f64p]),
             "orc_life_table": (None, [c_i64, i64p, c_int, u8p, u8p]),
+            "orc_life_windows": (None, [c_int, c_int, i32p, c_int, c_u64, c_u32, i64p, c_i64, c_int, c_int, c_int,
+                                        u8p]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -171,6 +173,15 @@ class Fractal:
         out = np.empty(xy.shape[0], dtype=np.uint8)
         lib().orc_light_cone(*self._a(), seed, threshold24(p), _ptr(xy, ctypes.c_int64),
                              xy.shape[0], t, _ptr(out, ctypes.c_uint8))
+        return out
+
+    def life_windows(self, seed: int, p: float, corners, w: int, h: int, t: int) -> np.ndarray:
+        """(count, h, w) states after t steps from fill(seed, p) of the w x h rectangles with
+        the given (x0, y0) corners, indexed [q, y - y0, x - x0]; 0 on holes and outside the box."""
+        corners = np.ascontiguousarray(np.asarray(corners, dtype=np.int64).reshape(-1, 2))
+        out = np.empty((corners.shape[0], h, w), dtype=np.uint8)
+        lib().orc_life_windows(*self._a(), seed, threshold24(p), _ptr(corners, ctypes.c_int64), corners.shape[0],
+                               w, h, t, _ptr(out, ctypes.c_uint8))
         return out
 
     def neighbour_table(self, c0: int = 0, c1: int | None = None) -> np.ndarray:

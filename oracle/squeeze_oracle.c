@@ -329,6 +329,70 @@ void orc_light_cone(int s, int k, const int32_t *offs, int r, uint64_t seed, uin
     }
 }
 
+/*
+ * The light cone for a whole rectangle at once: the states after t steps of
+ * every point of the w x h rectangle with corner (x0, y0) (0 for holes and
+ * for points outside the box).  The rectangle grown by t on every side is
+ * filled from the Bernoulli start and advanced t steps with everything
+ * outside it treated as dead; the error this makes at the grown region's
+ * edge moves inward one cell per step, so the rectangle itself is exact.
+ * out[j*w + i] is point (x0 + i, y0 + j).
+ */
+static void life_window_one(int s, int k, const int32_t *offs, int r, uint64_t seed, uint32_t thresh24,
+                            int64_t x0, int64_t y0, int w, int h, int t, uint8_t *out)
+{
+    int64_t n = ipow(s, r);
+    int W = w + 2 * t, H = h + 2 * t;
+    uint8_t *mem = (uint8_t *)malloc((size_t)W * H);
+    uint8_t *cur = (uint8_t *)malloc((size_t)W * H);
+    uint8_t *nxt = (uint8_t *)malloc((size_t)W * H);
+    for (int j = 0; j < H; ++j)
+        for (int i = 0; i < W; ++i) {
+            int64_t px = x0 - t + i, py = y0 - t + j;
+            int m = orc_nu(s, k, offs, r, px, py) != ORC_HOLE;
+            mem[(size_t)j * W + i] = (uint8_t)m;
+            cur[(size_t)j * W + i] = m ? bernoulli_cell(seed, thresh24, n, px, py) : 0;
+        }
+    for (int step = 0; step < t; ++step) {
+        for (int j = 0; j < H; ++j)
+            for (int i = 0; i < W; ++i) {
+                size_t p = (size_t)j * W + i;
+                if (!mem[p]) {
+                    nxt[p] = 0;
+                    continue;
+                }
+                int cnt = 0;
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        if (!dx && !dy) continue;
+                        int qi = i + dx, qj = j + dy;
+                        if (qi < 0 || qj < 0 || qi >= W || qj >= H) continue;
+                        cnt += cur[(size_t)qj * W + qi];
+                    }
+                nxt[p] = life_rule(cur[p], cnt);
+            }
+        uint8_t *tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+    }
+    for (int j = 0; j < h; ++j)
+        for (int i = 0; i < w; ++i) out[(size_t)j * w + i] = cur[(size_t)(j + t) * W + (i + t)];
+    free(mem);
+    free(cur);
+    free(nxt);
+}
+
+/* count rectangles of w x h points, corners xy0[2q], xy0[2q+1]; out holds
+   count * w * h states, rectangle q at out + q*w*h. */
+void orc_life_windows(int s, int k, const int32_t *offs, int r, uint64_t seed, uint32_t thresh24,
+                      const int64_t *xy0, int64_t count, int w, int h, int t, uint8_t *out)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t q = 0; q < count; ++q)
+        life_window_one(s, k, offs, r, seed, thresh24, xy0[2 * q], xy0[2 * q + 1], w, h, t,
+                        out + (size_t)q * w * h);
+}
+
 /* ------------------------------------------------------------------ */
 /* Explicit diffusion on the fractal, binary64                         */
 /* ------------------------------------------------------------------ */

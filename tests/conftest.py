@@ -14,9 +14,14 @@ def pytest_configure(config):
 
 
 def pytest_collection_modifyitems(config, items):
-    # GPU tests must run on a machine with a HIP device; fail loudly there if the
-    # native library is missing (never fall back to a CPU path).
-    pass
+    # A run that selects GPU tests stops at once, with one message, when the HIP
+    # library has not been built (there is no CPU path to fall back on); every
+    # GPU test would otherwise fail on the same missing file.
+    if any(item.get_closest_marker("gpu") for item in items):
+        lib = os.path.join(ROOT, "paper_2201_00613_amd", "libsqueeze.so")
+        if not os.path.exists(lib):
+            pytest.exit(f"{lib} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')",
+                        returncode=4)
 
 
 @pytest.fixture(scope="session")

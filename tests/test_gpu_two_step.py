@@ -65,7 +65,10 @@ def test_r16_run_equals_single_steps():
 def test_large_triangle_tiles_equal_thread_level(r):
     """From level 16 the triangle runs level-10 tiles in 512-lane workgroups (below
     it level-8 tiles): a 13-step run (launches of 10 and 3) equals 13 thread-level
-    steps, which share no code with the tiles."""
+    steps.  The thread-level kernel computes every cell with one lambda and eight
+    nu; the tiles evaluate no map per cell (the same device maps only locate each
+    tile's ring cells at set-up), so the two paths differ in everything but those
+    maps.  The oracle itself checks the level-10 tiles in test_gpu_headline_parity."""
     torch = torch_or_skip()
     F = gpu_fractal("triangle", r)
     assert F.tile_level == (10 if r >= 16 else 8) and F.run_steps_per_launch == 10

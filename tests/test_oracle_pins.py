@@ -300,6 +300,34 @@ def test_light_cone_matches_full_simulation(oracle_lib, name, r, t):
     assert (F.light_cone(seed, p, xy, t) == full[cs]).all()
 
 
+@pytest.mark.parametrize("name,r,t", [("triangle", 7, 5), ("triangle_paper", 6, 3), ("carpet", 4, 4),
+                                      ("vicsek", 4, 6)])
+def test_life_windows_match_convolution(oracle_lib, name, r, t):
+    """Rectangles of the t-step state (the window form of the light cone) against t
+    steps of a 2-D convolution of the whole masked grid: rectangles inside the box,
+    straddling its edges and corners, partly and wholly outside it, and the whole box."""
+    F = frac(oracle_lib, name, r)
+    seed, p = 7, 0.45
+    member = F.member().astype(np.int64)
+    g = F.fill_expanded(seed, p).astype(np.int64)
+    for _ in range(t):
+        g = life_by_convolution(member, g)
+    n = F.n
+    pad = np.zeros((n + 40, n + 40), np.int64)
+    pad[20:20 + n, 20:20 + n] = g
+    rects = [(0, 0, n, n), (3, 5, 17, 9), (-6, -4, 13, 11), (n - 7, n - 3, 12, 9), (n - 5, -2, 9, 6),
+             (-3, n - 4, 8, 10), (n + 2, n + 1, 5, 4), (n // 3, n // 2, 1, 1), (-8, 4, 6, 5)]
+    for (x0, y0, w, h) in rects:
+        got = F.life_windows(seed, p, [(x0, y0)], w, h, t)[0]
+        want = pad[20 + y0:20 + y0 + h, 20 + x0:20 + x0 + w]
+        assert got.shape == want.shape and (got == want).all(), (name, r, x0, y0, w, h)
+    # several rectangles of one size in one call
+    corners = [(1, 2), (n - 9, 0), (0, n - 9)]
+    got = F.life_windows(seed, p, corners, 9, 9, t)
+    for q, (x0, y0) in enumerate(corners):
+        assert (got[q] == pad[20 + y0:29 + y0, 20 + x0:29 + x0]).all()
+
+
 # ---------------------------------------------------------------------------
 # seeded inputs
 # ---------------------------------------------------------------------------
