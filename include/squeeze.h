@@ -311,11 +311,12 @@ SQZ_API sqz_status sqz_diffuse_run(const sqz_fractal *f, const sqz_diffusion *d,
 SQZ_API sqz_status sqz_mass_f64(const sqz_fractal *f, sqz_dtype dtype, const void *d_u, double offset,
                                 double *d_work, void *stream);
 
-/* bfloat16 storage conversion: d_b[c] = bf16_nearest_even(d_u[c] - offset). */
+/* bfloat16 storage conversion: d_b[c] = bf16_nearest_even(d_u[c] - offset).
+ * d_u: N floats, d_b: N uint16; NULL or overlapping buffers: SQZ_ERR_INVALID. */
 SQZ_API sqz_status sqz_bf16_encode(const sqz_fractal *f, const float *d_u, float offset, uint16_t *d_b,
                                    void *stream);
 
-/* d_u[c] = offset + float(d_b[c]). */
+/* d_u[c] = offset + float(d_b[c]); NULL or overlapping buffers: SQZ_ERR_INVALID. */
 SQZ_API sqz_status sqz_bf16_decode(const sqz_fractal *f, const uint16_t *d_b, float offset, float *d_u,
                                    void *stream);
 

@@ -21,6 +21,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "squeeze_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# A test run may point the loader at another build of the same source (the
+# sanitizer build of tests/test_host_sanitizers.py).
+_LIB_OVERRIDE = os.environ.get("SQZ_ORACLE_LIB")
 
 HOLE = -1
 
@@ -45,7 +48,10 @@ _lib = None
 def lib() -> ctypes.CDLL:
     global _lib
     if _lib is None:
-        path = build() if not os.path.exists(_LIB_PATH) else _LIB_PATH
+        if _LIB_OVERRIDE:
+            path = _LIB_OVERRIDE
+        else:
+            path = build() if not os.path.exists(_LIB_PATH) else _LIB_PATH
         L = ctypes.CDLL(path)
         i32p = ctypes.POINTER(ctypes.c_int32)
         i64p = ctypes.POINTER(ctypes.c_int64)

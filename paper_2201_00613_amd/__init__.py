@@ -256,10 +256,13 @@ class Fractal:
         return a if steps % 2 == 0 else b
 
     def mass_f64(self, u, dtype: str = "f32", offset: float = 0.0, work=None):
-        """Binary64 sum of offset + u on the device; returns a 0-d float64 device tensor."""
+        """Binary64 sum of offset + u on the device; returns a 0-d float64 device tensor
+        (element 0 of `work`, a float64 tensor of MASS_WORK_DOUBLES elements, allocated here
+        if not given)."""
         torch, dev, st = self._ctx()
         self._need(u, self._field_dtype(dtype), self.cells, "u")
         work = torch.empty(MASS_WORK_DOUBLES, dtype=torch.float64, device=self.device) if work is None else work
+        self._need(work, torch.float64, MASS_WORK_DOUBLES, "work")
         with dev:
             check(lib().sqz_mass_f64(self._h, DTYPES[dtype], _ptr(u), offset, _ptr(work), st))
         return work[0]
@@ -268,6 +271,7 @@ class Fractal:
         torch, dev, st = self._ctx()
         self._need(u, torch.float32, self.cells, "u")
         out = torch.empty(self.cells, dtype=torch.uint16, device=self.device) if out is None else out
+        self._need(out, torch.uint16, self.cells, "out")
         with dev:
             check(lib().sqz_bf16_encode(self._h, _ptr(u), offset, _ptr(out), st))
         return out
@@ -276,6 +280,7 @@ class Fractal:
         torch, dev, st = self._ctx()
         self._need(b, torch.uint16, self.cells, "b")
         out = torch.empty(self.cells, dtype=torch.float32, device=self.device) if out is None else out
+        self._need(out, torch.float32, self.cells, "out")
         with dev:
             check(lib().sqz_bf16_decode(self._h, _ptr(b), offset, _ptr(out), st))
         return out

@@ -21,7 +21,7 @@ LIB = os.path.join(PKG, "libsqueeze.so")
 OBJDIR = os.path.join(ROOT, "_build", "obj")
 SOURCES = ["api.hip", "maps.hip", "mfma_maps.hip", "blocks.hip", "bb.hip", "life_tile.hip", "xtile.hip", "bitbox.hip",
            "batch.hip"]
-HOST_SOURCES: list[str] = []
+HOST_SOURCES = ["host_tables.cpp"]
 ARCH = os.environ.get("SQZ_OFFLOAD_ARCH", "gfx950")
 
 

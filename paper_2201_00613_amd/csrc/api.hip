@@ -3,7 +3,6 @@
 #include <hip/hip_runtime.h>
 
 #include <math.h>
-#include <stdarg.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -30,44 +29,9 @@ const FractalHost &fractal_host_of(const sqz_fractal *f) { return f->h; }
 
 namespace sqz {
 
-static thread_local char g_err[512];
-
-sqz_status set_error(sqz_status st, const char *fmt, ...)
-{
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(g_err, sizeof g_err, fmt, ap);
-    va_end(ap);
-    return st;
-}
-
 sqz_status hip_error(hipError_t e, const char *what)
 {
     return set_error(SQZ_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
-}
-
-Div32 make_div32(uint32_t d)
-{
-    Div32 D;
-    D.d = d;
-    uint32_t l = 0;
-    while (l < 32 && (1ull << l) < d) ++l;
-    D.m = (uint32_t)((((unsigned __int128)1 << 32) * (((unsigned __int128)1 << l) - d)) / d + 1);
-    D.sh1 = l < 1 ? l : 1;
-    D.sh2 = l > 0 ? l - 1 : 0;
-    return D;
-}
-
-Div64 make_div64(uint64_t d)
-{
-    Div64 D;
-    D.d = d;
-    uint32_t l = 0;
-    while (l < 64 && ((unsigned __int128)1 << l) < d) ++l;
-    D.m = (uint64_t)((((unsigned __int128)1 << 64) * (((unsigned __int128)1 << l) - d)) / d + 1);
-    D.sh1 = l < 1 ? l : 1;
-    D.sh2 = l > 0 ? l - 1 : 0;
-    return D;
 }
 
 static uint64_t upow(uint64_t b, int e)
@@ -77,194 +41,31 @@ static uint64_t upow(uint64_t b, int e)
     return p;
 }
 
-// Chunk sizes of the map tables: at most 4096 entries per table, lambda
-// offsets packed in 16 bits per axis, nu chunk values below 2^31.
-static int lam_chunk(int s, int k)
-{
-    int c = 1;
-    while (c < 24 && upow(k, c + 1) <= 4096 && upow(s, c + 1) <= 65536) ++c;
-    return c;
-}
-static int nu_chunk(int s, int k)
-{
-    int c = 1;
-    while (c < 24 && upow(s, 2 * (c + 1)) <= 4096 && upow(k, c + 1) < (1ull << 31)) ++c;
-    return c;
-}
-
 sqz_status build_map_params(const FractalHost &F, int level, MapParams &P, void **d_mem)
 {
-    const int s = F.s, k = F.k;
-    memset(&P, 0, sizeof P);
-    P.s = s;
-    P.k = k;
-    P.r = level;
-    P.n = (int32_t)upow(s, level);
-    P.N = upow(k, level);
-    const int CL = lam_chunk(s, k), CN = nu_chunk(s, k);
-    P.nlam = level == 0 ? 0 : (level + CL - 1) / CL;
-    P.nnu = level == 0 ? 0 : (level + CN - 1) / CN;
-    const int TL = level == 0 ? 0 : level - CL * (P.nlam - 1);
-    const int TN = level == 0 ? 0 : level - CN * (P.nnu - 1);
-    P.klam = (uint32_t)upow(k, CL);
-    P.slam = (uint32_t)upow(s, CL);
-    P.snu = (uint32_t)upow(s, CN);
-    P.snu_top = (uint32_t)upow(s, TN);
-    P.knu = upow(k, CN);
-    P.dklam64 = make_div64(P.klam);
-    P.dklam32 = make_div32(P.klam);
-    P.dsnu = make_div32(P.snu);
-
-    // lambda tables: digit chunk -> packed (x | y << 16)
-    auto lam_table = [&](int levels, std::vector<uint32_t> &t) {
-        uint64_t cnt = upow(k, levels);
-        t.resize(cnt);
-        for (uint64_t d = 0; d < cnt; ++d) {
-            uint64_t v = d, sp = 1, x = 0, y = 0;
-            for (int i = 0; i < levels; ++i) {
-                int beta = (int)(v % k);
-                v /= k;
-                x += F.ox[beta] * sp;
-                y += F.oy[beta] * sp;
-                sp *= s;
-            }
-            t[d] = (uint32_t)(x | (y << 16));
-        }
-    };
-    // nu tables: (xc + side*yc) -> base-k replica digits, or hole
-    auto nu_table = [&](int levels, std::vector<uint32_t> &t) {
-        uint64_t side = upow(s, levels);
-        t.resize(side * side);
-        for (uint64_t yc = 0; yc < side; ++yc)
-            for (uint64_t xc = 0; xc < side; ++xc) {
-                uint64_t v = 0, kp = 1, sx = xc, sy = yc;
-                bool hole = false;
-                for (int i = 0; i < levels; ++i) {
-                    int j = F.hnu[(sx % s) + s * (sy % s)];
-                    sx /= s;
-                    sy /= s;
-                    if (j < 0) {
-                        hole = true;
-                        break;
-                    }
-                    v += (uint64_t)j * kp;
-                    kp *= k;
-                }
-                t[xc + side * yc] = hole ? kNuHole32 : (uint32_t)v;
-            }
-    };
-    std::vector<uint32_t> lam_lo, lam_top, nu_lo, nu_top;
-    if (level > 0) {
-        lam_table(CL, lam_lo);
-        lam_table(TL, lam_top);
-        nu_table(CN, nu_lo);
-        nu_table(TN, nu_top);
-    } else {
-        lam_lo.assign(1, 0);
-        lam_top.assign(1, 0);
-        nu_lo.assign(1, 0);
-        nu_top.assign(1, 0);
-    }
-    size_t total = lam_lo.size() + lam_top.size() + nu_lo.size() + nu_top.size();
-    std::vector<uint32_t> all;
-    all.reserve(total);
-    all.insert(all.end(), lam_lo.begin(), lam_lo.end());
-    all.insert(all.end(), lam_top.begin(), lam_top.end());
-    all.insert(all.end(), nu_lo.begin(), nu_lo.end());
-    all.insert(all.end(), nu_top.begin(), nu_top.end());
+    MapTables T;
+    map_tables(F, level, P, T);
+    const size_t total = T.all.size();
     void *mem = nullptr;
     hipError_t e = hipMalloc(&mem, total * sizeof(uint32_t));
     if (e != hipSuccess) return set_error(SQZ_ERR_NOMEM, "hipMalloc of map tables: %s", hipGetErrorString(e));
-    e = hipMemcpy(mem, all.data(), total * sizeof(uint32_t), hipMemcpyHostToDevice);
+    e = hipMemcpy(mem, T.all.data(), total * sizeof(uint32_t), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(mem);
         return hip_error(e, "hipMemcpy of map tables");
     }
     const uint32_t *base = (const uint32_t *)mem;
-    P.lam_lo = base;
-    P.lam_top = P.lam_lo + lam_lo.size();
-    P.nu_lo = P.lam_top + lam_top.size();
-    P.nu_top = P.nu_lo + nu_lo.size();
+    P.lam_lo = base + T.off[0];
+    P.lam_top = base + T.off[1];
+    P.nu_lo = base + T.off[2];
+    P.nu_top = base + T.off[3];
     *d_mem = mem;
     return SQZ_OK;
-}
-
-// Plain host maps of the pattern at a given level (local coordinates), used to
-// build the tiled kernels' tables: lambda as a digit sum, nu as a level scan.
-void host_lambda(const FractalHost &F, int level, uint64_t c, int64_t &x, int64_t &y)
-{
-    int64_t px = 0, py = 0, sp = 1;
-    for (int mu = 1; mu <= level; ++mu) {
-        const int b = (int)(c % (uint64_t)F.k);
-        c /= (uint64_t)F.k;
-        px += F.ox[b] * sp;
-        py += F.oy[b] * sp;
-        sp *= F.s;
-    }
-    x = px;
-    y = py;
-}
-
-int64_t host_nu(const FractalHost &F, int level, int64_t x, int64_t y)
-{
-    int64_t side = 1;
-    for (int i = 0; i < level; ++i) side *= F.s;
-    if (x < 0 || y < 0 || x >= side || y >= side) return -1;
-    int64_t c = 0, kp = 1;
-    for (int mu = 1; mu <= level; ++mu) {
-        const int j = F.hnu[(int)(x % F.s) + F.s * (int)(y % F.s)];
-        if (j < 0) return -1;
-        c += j * kp;
-        kp *= F.k;
-        x /= F.s;
-        y /= F.s;
-    }
-    return c;
 }
 
 }  // namespace sqz
 
 using namespace sqz;
-
-static sqz_status check_descriptor(int32_t s, int32_t k, const int32_t *offs, int32_t r, FractalHost *F)
-{
-    if (s < 2 || s > kMaxS) return set_error(SQZ_ERR_INVALID, "s=%d outside [2, %d]", s, kMaxS);
-    if (k < 1 || k > s * s) return set_error(SQZ_ERR_INVALID, "k=%d outside [1, s*s=%d]", k, s * s);
-    if (!offs) return set_error(SQZ_ERR_INVALID, "offsets_xy is NULL");
-    if (r < 0) return set_error(SQZ_ERR_INVALID, "r=%d is negative", r);
-    int seen[kMaxS * kMaxS];
-    for (int i = 0; i < s * s; ++i) seen[i] = -1;
-    for (int j = 0; j < k; ++j) {
-        int x = offs[2 * j], y = offs[2 * j + 1];
-        if (x < 0 || x >= s || y < 0 || y >= s)
-            return set_error(SQZ_ERR_INVALID, "replica %d offset (%d,%d) outside [0,%d)^2", j, x, y, s);
-        if (seen[x + s * y] >= 0)
-            return set_error(SQZ_ERR_INVALID, "replicas %d and %d share offset (%d,%d)", seen[x + s * y], j, x, y);
-        seen[x + s * y] = j;
-    }
-    // n = s^r < 2^31, N = k^r < 2^62
-    uint64_t n = 1, N = 1;
-    for (int i = 0; i < r; ++i) {
-        n *= (uint64_t)s;
-        if (n >= (1ull << 31)) return set_error(SQZ_ERR_RANGE, "n = %d^%d does not fit in 31 bits", s, r);
-        N *= (uint64_t)k;
-        if (N >= (1ull << 62)) return set_error(SQZ_ERR_RANGE, "N = %d^%d does not fit in 62 bits", k, r);
-    }
-    if (F) {
-        memset(F, 0, sizeof *F);
-        F->s = s;
-        F->k = k;
-        F->r = r;
-        F->n = (int64_t)n;
-        F->N = N;
-        for (int j = 0; j < k; ++j) {
-            F->ox[j] = offs[2 * j];
-            F->oy[j] = offs[2 * j + 1];
-        }
-        for (int i = 0; i < s * s; ++i) F->hnu[i] = seen[i];
-    }
-    return SQZ_OK;
-}
 
 static void fill_info(const FractalHost &F, sqz_info *out)
 {
@@ -681,6 +482,8 @@ sqz_status sqz_bf16_encode(const sqz_fractal *f, const float *d_u, float offset,
     sqz_status st = check_handle(f);
     if (st != SQZ_OK) return st;
     if (!d_u || !d_b) return set_error(SQZ_ERR_INVALID, "NULL buffer");
+    if (ranges_overlap(d_u, f->h.N * sizeof(float), d_b, f->h.N * sizeof(uint16_t)))
+        return set_error(SQZ_ERR_INVALID, "d_u and d_b overlap");
     return launch_bf16_convert(f->h, 1, d_u, offset, d_b, (hipStream_t)stream);
 }
 
@@ -689,6 +492,8 @@ sqz_status sqz_bf16_decode(const sqz_fractal *f, const uint16_t *d_b, float offs
     sqz_status st = check_handle(f);
     if (st != SQZ_OK) return st;
     if (!d_u || !d_b) return set_error(SQZ_ERR_INVALID, "NULL buffer");
+    if (ranges_overlap(d_u, f->h.N * sizeof(float), d_b, f->h.N * sizeof(uint16_t)))
+        return set_error(SQZ_ERR_INVALID, "d_b and d_u overlap");
     return launch_bf16_convert(f->h, 0, d_u, offset, (uint16_t *)d_b, (hipStream_t)stream);
 }
 
@@ -816,6 +621,6 @@ const char *sqz_status_string(sqz_status st)
     return "unknown status";
 }
 
-const char *sqz_last_error(void) { return g_err; }
+const char *sqz_last_error(void) { return last_error_text(); }
 
 }  // extern "C"

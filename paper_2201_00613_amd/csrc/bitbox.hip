@@ -29,8 +29,6 @@ bool bx_matches(const FractalHost &F)
     return true;
 }
 
-int64_t floor_div(int64_t a, int64_t b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
-
 template <class Pat>
 sqz_status bx_prepare(FractalHost &F)
 {
@@ -40,43 +38,19 @@ sqz_status bx_prepare(FractalHost &F)
     C->tile = (uint32_t)cpow(Pat::K, M);
     C->nblk = (uint32_t)cpow(Pat::K, M - 1);
     C->side = (uint32_t)cpow(3, M);
-    const int64_t sb = cpow(3, M - 1), GB = sb + 2 * kBxBorder;
 
-    // grid positions of the tile's blocks
-    std::vector<uint16_t> bpos(C->nblk);
-    for (uint32_t b = 0; b < C->nblk; ++b) {
-        int64_t x, y;
-        host_lambda(F, M - 1, b, x, y);
-        bpos[b] = (uint16_t)((x + kBxBorder) | (y + kBxBorder) << 7);
-    }
-    // border blocks: position in an adjacent tile, if a block of the pattern is there
-    auto outside_block = [&](int64_t gx, int64_t gy, int &dir) -> int64_t {
-        const int64_t bx = gx - kBxBorder, by = gy - kBxBorder;
-        const int64_t tdx = floor_div(bx, sb), tdy = floor_div(by, sb);
-        dir = (int)((tdy + 1) * 3 + (tdx + 1));
-        return host_nu(F, M - 1, bx - tdx * sb, by - tdy * sb);
-    };
-    std::vector<uint32_t> ring;
-    for (int64_t gy = 0; gy < GB; ++gy)
-        for (int64_t gx = 0; gx < GB; ++gx) {
-            const bool inner = gx >= kBxBorder && gy >= kBxBorder && gx < kBxBorder + sb && gy < kBxBorder + sb;
-            if (inner) continue;
-            int dir;
-            const int64_t lb = outside_block(gx, gy, dir);
-            if (lb >= 0) ring.push_back((uint32_t)(gy * kBxGP + gx) | (uint32_t)dir << 14 | (uint32_t)lb << 18);
-        }
-    C->nring = (uint32_t)ring.size();
+    // grid positions of the tile's blocks, border blocks of the adjacent tiles,
     // membership of every box position (adjacent tiles present)
-    std::vector<uint32_t> member((size_t)kBxRows * kBxW, 0);
-    for (int64_t cy = 0; cy < 3 * GB; ++cy)
-        for (int64_t cx = 0; cx < 3 * GB; ++cx) {
-            if (replica_at<Pat>((int)(cx % 3), (int)(cy % 3)) < 0) continue;
-            const int64_t gx = cx / 3, gy = cy / 3;
-            const bool inner = gx >= kBxBorder && gy >= kBxBorder && gx < kBxBorder + sb && gy < kBxBorder + sb;
-            int dir;
-            const int64_t lb = inner ? host_nu(F, M - 1, gx - kBxBorder, gy - kBxBorder) : outside_block(gx, gy, dir);
-            if (lb >= 0) member[(size_t)cy * kBxW + cx / 32] |= 1u << (cx % 32);
-        }
+    BitboxSpec S;
+    S.M = M;
+    S.border = kBxBorder;
+    S.grid_pitch = kBxGP;
+    S.rows = kBxRows;
+    S.words = kBxW;
+    std::vector<uint16_t> bpos;
+    std::vector<uint32_t> ring, member;
+    bitbox_tables(F, S, bpos, ring, member);
+    C->nring = (uint32_t)ring.size();
 
     sqz_status st = build_map_params(F, F.r - M, C->Pc, &C->d_coarse);
     if (st != SQZ_OK) {

@@ -13,33 +13,12 @@
 
 #include <vector>
 
+#include "host_tables.h"
 #include "squeeze.h"
 
 namespace sqz {
 
-constexpr uint32_t kNuHole32 = 0xFFFFFFFFu;
-constexpr uint64_t kHole64 = ~0ull;
-constexpr int kMaxS = 16;
-constexpr int kMaxK = 256;
-
-// ---------------------------------------------------------------------------
-// Division by a run-time invariant integer (Granlund & Montgomery, "Division
-// by invariant integers using multiplication", PLDI 1994, unsigned case):
-// with l = ceil(log2 d) and m = floor(2^W (2^l - d) / d) + 1,
-// q = (t + ((n - t) >> min(l,1))) >> max(l-1,0), t = mulhi(m, n), exact for
-// every W-bit n.
-// ---------------------------------------------------------------------------
-struct Div32 {
-    uint32_t d, m, sh1, sh2;
-};
-struct Div64 {
-    uint64_t d, m;
-    uint32_t sh1, sh2;
-};
-
-Div32 make_div32(uint32_t d);
-Div64 make_div64(uint64_t d);
-
+// Device forms of the invariant division (Div32/Div64 in host_tables.h).
 __device__ __forceinline__ uint32_t divq(uint32_t n, const Div32 &D)
 {
     uint32_t t = __umulhi(D.m, n);
@@ -51,30 +30,7 @@ __device__ __forceinline__ uint64_t divq(uint64_t n, const Div64 &D)
     return (t + ((n - t) >> D.sh1)) >> D.sh2;
 }
 
-// ---------------------------------------------------------------------------
-// Chunked look-up tables for the two maps.
-//
-// lambda: a chunk of CL base-k digits d (value < k^CL) maps to the packed
-//   offset (x | y << 16) = sum over the chunk's levels of tau(digit) s^level.
-// nu: a chunk of CN base-s digit pairs (xc, yc), both < s^CN, maps to the
-//   chunk's replica digits read as a base-k number, or kNuHole32 when any
-//   level's digit pair is not a replica offset (explicit hole test; the
-//   paper's arithmetic hash has no hole value).
-// The top chunk of each map covers the remaining r - CL*(chunks-1) levels
-// and has its own table, so digits above level r never contribute.
-// ---------------------------------------------------------------------------
-struct MapParams {
-    int32_t s, k, r, n;       // n = s^r < 2^31
-    uint64_t N;               // k^r
-    int32_t nlam, nnu;        // number of chunks (0 when r == 0)
-    uint32_t klam, slam;      // k^CL, s^CL
-    uint32_t snu, snu_top;    // s^CN, s^(top nu chunk levels)
-    uint64_t knu;             // k^CN
-    Div64 dklam64;
-    Div32 dklam32;
-    Div32 dsnu;
-    const uint32_t *lam_lo, *lam_top, *nu_lo, *nu_top;
-};
+// Chunked map tables: MapParams (host_tables.h).
 
 // lambda(c) for c < N (Section "Revisiting lambda"); 32-bit index variant
 // for N <= 2^32, 64-bit otherwise.
@@ -157,31 +113,6 @@ __device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t i)
     return z ^ (z >> 31);
 }
 
-// ---------------------------------------------------------------------------
-// Host-side fractal handle.
-// ---------------------------------------------------------------------------
-struct TileConfig;   // defined in life_tile.hip
-struct XTileConfig;  // defined in xtile.hip
-struct MfmaParams;   // defined in mfma_maps.hip
-struct BitboxConfig; // defined in bitbox.hip
-
-struct FractalHost {
-    int32_t s, k, r;
-    int64_t n;
-    uint64_t N;
-    int32_t ox[kMaxK], oy[kMaxK];
-    int32_t hnu[kMaxS * kMaxS];  // replica index of digit pair (x + s*y), -1 if none
-    int device;
-    MapParams P;                  // maps at level r
-    void *d_tables;               // device memory holding the chunk tables
-    // tiled stencil (patterns with a specialised kernel), built on demand
-    int tile_kind;                // 0 = none
-    TileConfig *tile;
-    XTileConfig *xtile;           // expanded-tile kernels (any pattern), null if none
-    MfmaParams *mfma;             // matrix-core map variants, null if unsupported (k > 127)
-    BitboxConfig *bitbox;         // bit-row expanded tiles (dense s = 3 patterns), null if none
-};
-
 // Launch sizes for `steps` steps with at most K per launch (temporal
 // blocking): launches of K steps and one of the remainder.  Every launch swaps
 // the two buffers, so the launch count must have the parity of `steps` for the
@@ -201,12 +132,10 @@ inline std::vector<int> plan_launches(int32_t steps, int K)
     return plan;
 }
 
-// Host helpers (api.cpp)
-sqz_status set_error(sqz_status st, const char *fmt, ...);
+// Host helpers (api.hip; the HIP-free ones are in host_tables.h)
 sqz_status hip_error(hipError_t e, const char *what);
+// map tables of `level` (map_tables) uploaded to new device memory *d_mem; P's table pointers set
 sqz_status build_map_params(const FractalHost &F, int level, MapParams &P, void **d_mem);
-void host_lambda(const FractalHost &F, int level, uint64_t c, int64_t &x, int64_t &y);
-int64_t host_nu(const FractalHost &F, int level, int64_t x, int64_t y);  // -1 for holes / outside
 
 // Kernel launchers (maps.hip)
 sqz_status launch_lambda(const MapParams &P, const uint64_t *idx, int64_t count, int32_t *xy,

@@ -89,154 +89,43 @@ template <class Pat>
 sqz_status prepare(FractalHost &F)
 {
     constexpr const BlockPlan &PL = PlanOf<Pat>::value;
-    constexpr int J = Pat::J;
+    using LDS = TileLds<Pat>;
     TileConfig *T = new TileConfig();
     const int mtop = F.r >= Pat::MBIG ? Pat::MMAX : (Pat::MSMALL < Pat::MMAX ? Pat::MSMALL : Pat::MMAX);
     T->M = F.r < mtop ? F.r : mtop;
     const int M = T->M;
     T->tile = (uint32_t)cpow(Pat::K, M);
-    T->nblocks = (uint32_t)cpow(Pat::K, M - J);
-    using LDS = TileLds<Pat>;
-    const int64_t side = cpow(Pat::S, M), box = PL.box;
+    T->nblocks = (uint32_t)cpow(Pat::K, M - Pat::J);
 
-    // tile halo slots: cells of adjacent tiles that touch a cell of this tile
-    struct Slot {
-        int dx, dy;
-        int64_t idx, px, py;  // cell index in the neighbour tile; position relative to this tile
-    };
-    std::vector<Slot> slots;
-    for (uint64_t c = 0; c < T->tile; ++c) {
-        int64_t x, y;
-        host_lambda(F, M, c, x, y);
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int64_t qx = x + dx, qy = y + dy;
-                if (qx >= 0 && qy >= 0 && qx < side && qy < side) continue;
-                const int tdx = qx < 0 ? -1 : (qx >= side ? 1 : 0), tdy = qy < 0 ? -1 : (qy >= side ? 1 : 0);
-                const int64_t j = host_nu(F, M, qx - tdx * side, qy - tdy * side);
-                if (j < 0) continue;
-                bool seen = false;
-                for (const Slot &s : slots) seen |= s.px == qx && s.py == qy;
-                if (!seen) slots.push_back(Slot{tdx, tdy, j, qx, qy});
-            }
+    // tables of the tile (the same for every tile): rings, halos, LDS entries
+    TileSpec S;
+    S.M = M;
+    S.J = Pat::J;
+    S.nc = PL.nc;
+    S.box = PL.box;
+    S.ngrp = PL.ngrp;
+    for (int g = 0; g < 8; ++g) {
+        S.g_dx[g] = g < PL.ngrp ? PL.g_dx[g] : 0;
+        S.g_dy[g] = g < PL.ngrp ? PL.g_dy[g] : 0;
     }
-    if (slots.size() > (size_t)kMaxTileHalo) {
+    S.lds_zero = LDS::ZERO;
+    S.lds_virt = LDS::VIRT;
+    S.lds_ring2 = LDS::RING2;
+    S.max_tile_halo = kMaxTileHalo;
+    S.max_ring = kMaxRing;
+    S.max_steps = kMaxSteps;
+    TileTables TT;
+    if (tile_tables(F, S, TT) != SQZ_OK) {
         delete T;
-        return set_error(SQZ_ERR_UNSUPPORTED, "tile halo of %zu cells exceeds %d", slots.size(), kMaxTileHalo);
+        return SQZ_ERR_UNSUPPORTED;
     }
-    T->nthalo = (uint32_t)slots.size();
-
-    // rings 2..kMaxSteps (several steps per launch): breadth-first from ring 1
-    // over member cells outside the tile (ring d = graph distance d from the
-    // tile); all rings must fit kMaxRing lanes.
-    std::vector<Slot> ring = slots;  // rings in order, ring 1 first
-    std::vector<uint32_t> start = {0, (uint32_t)slots.size()};
-    auto find = [&](int64_t qx, int64_t qy) {
-        for (size_t i = 0; i < ring.size(); ++i)
-            if (ring[i].px == qx && ring[i].py == qy) return (int64_t)i;
-        return (int64_t)-1;
-    };
-    auto outside_member = [&](int64_t qx, int64_t qy, int &tdx, int &tdy) {
-        tdx = qx < 0 ? -1 : (qx >= side ? 1 : 0);
-        tdy = qy < 0 ? -1 : (qy >= side ? 1 : 0);
-        return host_nu(F, M, qx - tdx * side, qy - tdy * side);
-    };
-    uint32_t ksteps = 1;
-    for (int d = 2; d <= kMaxSteps; ++d) {
-        for (uint32_t c = start[d - 2]; c < start[d - 1]; ++c)
-            for (int dy = -1; dy <= 1; ++dy)
-                for (int dx = -1; dx <= 1; ++dx) {
-                    const int64_t qx = ring[c].px + dx, qy = ring[c].py + dy;
-                    if (qx >= 0 && qy >= 0 && qx < side && qy < side) continue;
-                    int tdx, tdy;
-                    const int64_t j = outside_member(qx, qy, tdx, tdy);
-                    if (j >= 0 && find(qx, qy) < 0) ring.push_back(Slot{tdx, tdy, j, qx, qy});
-                }
-        start.push_back((uint32_t)ring.size());
-        // (ring cells must also lie in adjacent tiles: d < side)
-        if (T->nthalo == 0 || start[d] > (uint32_t)kMaxRing || d >= side) break;
-        ksteps = (uint32_t)d;  // rings 1..d fit: d steps per launch
-    }
-    T->ksteps = ksteps;
-    for (int d = 0; d <= kMaxSteps; ++d) T->ring_start[d] = start[d <= (int)ksteps ? d : ksteps];
-    T->tstride = T->ring_start[ksteps];
-    T->nsrc = ksteps >= 2 ? T->ring_start[ksteps - 1] : 0;
-    ring.resize(T->tstride);
-
-    // adjacent blocks of other tiles that hold ring-1 cells (one LDS word each)
-    auto floor_div = [](int64_t a, int64_t b) { return a >= 0 ? a / b : -((-a + b - 1) / b); };
-    std::vector<std::pair<int64_t, int64_t>> vblk;
-    auto virt_of = [&](int64_t bx, int64_t by) {
-        for (size_t g = 0; g < vblk.size(); ++g)
-            if (vblk[g].first == bx && vblk[g].second == by) return (int64_t)g;
-        return (int64_t)-1;
-    };
-    for (const Slot &s : slots) {
-        const int64_t bx = floor_div(s.px, box), by = floor_div(s.py, box);
-        if (virt_of(bx, by) < 0) vblk.emplace_back(bx, by);
-    }
-    // LDS entry (byte offset of the word << 16 | bit) of a tile cell and of ring cell i
-    auto entry = [](uint32_t word, uint32_t bit) { return (4u * word) << 16 | bit; };
-    const uint32_t zero_entry = entry(LDS::ZERO, 0);
-    auto tile_entry = [&](int64_t j) { return entry((uint32_t)(j / PL.nc), (uint32_t)(j % PL.nc)); };
-    auto ring_entry = [&](size_t i) {
-        uint32_t d = 1;
-        while ((uint32_t)i >= T->ring_start[d]) ++d;
-        if (d == 1) {
-            const Slot &s = ring[i];
-            const int64_t g = virt_of(floor_div(s.px, box), floor_div(s.py, box));
-            return entry(LDS::VIRT + (uint32_t)g, (uint32_t)(s.idx % PL.nc));
-        }
-        const uint32_t k = (uint32_t)i - T->nthalo;  // rings 2.. packed in order
-        return entry(LDS::RING2 + k / 32, k % 32);
-    };
-    std::vector<uint32_t> home(T->tstride ? T->tstride : 1, zero_entry);
-    for (uint32_t i = 0; i < T->tstride; ++i) home[i] = ring_entry(i);
-    // LDS sources of the neighbours of every ring cell that is advanced
-    std::vector<uint32_t> rsrc(T->nsrc ? (size_t)T->nsrc * 8 : 1, zero_entry);
-    for (uint32_t c = 0; c < T->nsrc; ++c) {
-        int n = 0;
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-                if (!dx && !dy) continue;
-                const int64_t qx = ring[c].px + dx, qy = ring[c].py + dy;
-                uint32_t e = zero_entry;
-                if (qx >= 0 && qy >= 0 && qx < side && qy < side) {
-                    const int64_t j = host_nu(F, M, qx, qy);
-                    if (j >= 0) e = tile_entry(j);
-                } else {
-                    int tdx, tdy;
-                    if (outside_member(qx, qy, tdx, tdy) >= 0) {
-                        const int64_t i = find(qx, qy);  // always a loaded ring cell: ring d-1, d or d+1
-                        if (i >= 0 && i < (int64_t)T->tstride) e = ring_entry((size_t)i);
-                    }
-                }
-                rsrc[(size_t)c * 8 + n++] = e;
-            }
-    }
-
-    // adjacent-block words of every block: a block of the tile, the word of
-    // an adjacent block of another tile, or a zero word (no such block)
-    const int NG = PL.ngrp, NP = (NG + 1) / 2;
-    T->nbstride = NP > 4 ? (uint32_t)((NP + 3) / 4 * 4) : 4u;
-    std::vector<uint32_t> nbt((size_t)T->nblocks * T->nbstride, 0);
-    const int64_t bside = cpow(Pat::S, M - J);
-    for (uint32_t b = 0; b < T->nblocks; ++b) {
-        int64_t bx, by;
-        host_lambda(F, M - J, b, bx, by);
-        for (int g = 0; g < NG; ++g) {
-            const int64_t nbx = bx + PL.g_dx[g], nby = by + PL.g_dy[g];
-            uint32_t w = LDS::ZERO;
-            if (nbx >= 0 && nby >= 0 && nbx < bside && nby < bside) {
-                const int64_t nb = host_nu(F, M - J, nbx, nby);
-                if (nb >= 0) w = (uint32_t)nb;
-            } else {
-                const int64_t v = virt_of(nbx, nby);
-                if (v >= 0) w = LDS::VIRT + (uint32_t)v;
-            }
-            nbt[(size_t)b * T->nbstride + g / 2] |= (4u * w) << (16 * (g & 1));
-        }
-    }
+    T->nthalo = TT.nthalo;
+    T->ksteps = TT.ksteps;
+    for (int d = 0; d <= kMaxSteps; ++d) T->ring_start[d] = TT.ring_start[d];
+    T->tstride = TT.tstride;
+    T->nsrc = TT.nsrc;
+    T->nbstride = TT.nbstride;
+    const std::vector<uint32_t> &nbt = TT.nbt, &rsrc = TT.rsrc, &home = TT.home;
 
     // coarse maps and per-tile halo indices
     sqz_status st = build_map_params(F, F.r - M, T->Pc, &T->d_coarse_tables);
@@ -250,8 +139,9 @@ sqz_status prepare(FractalHost &F)
     T->d_ringsrc = nullptr;
     T->d_ringhome = nullptr;
     int4 *d_slots = nullptr;
-    std::vector<int4> hs(T->tstride ? T->tstride : 1);
-    for (size_t s = 0; s < T->tstride; ++s) hs[s] = make_int4(ring[s].dx, ring[s].dy, (int)ring[s].idx, 0);
+    std::vector<int4> hs(T->tstride ? T->tstride : 1, make_int4(0, 0, 0, 0));
+    for (size_t s = 0; s < T->tstride; ++s)
+        hs[s] = make_int4(TT.slots[4 * s], TT.slots[4 * s + 1], TT.slots[4 * s + 2], 0);
     auto upload = [](uint32_t **d, const std::vector<uint32_t> &h) {
         hipError_t e = hipMalloc(d, h.size() * sizeof(uint32_t));
         return e == hipSuccess ? hipMemcpy(*d, h.data(), h.size() * sizeof(uint32_t), hipMemcpyHostToDevice) : e;

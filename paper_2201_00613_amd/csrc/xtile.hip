@@ -105,13 +105,14 @@ __global__ void __launch_bounds__(256) k_mass_partial(const G *__restrict__ u, u
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-__global__ void __launch_bounds__(256) k_mass_final(double *part, uint64_t N, double offset)
+// Folds the kMassGrid partials part[0..kMassGrid) into *result.
+__global__ void __launch_bounds__(256) k_mass_final(const double *part, double *result, uint64_t N, double offset)
 {
     __shared__ double sh[256];
     double acc = 0.0;
-    for (int i = threadIdx.x; i < kMassGrid; i += 256) acc += part[1 + i];
+    for (int i = threadIdx.x; i < kMassGrid; i += 256) acc += part[i];
     const double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) part[0] = s + (double)N * offset;
+    if (threadIdx.x == 0) *result = s + (double)N * offset;
 }
 
 __global__ void __launch_bounds__(256) k_encode_bf16(const float *__restrict__ u, float offset, uint16_t *__restrict__ b,
@@ -139,41 +140,6 @@ unsigned grid_for(uint64_t count)
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
-struct RingSlot {
-    uint16_t pos;
-    uint32_t info;
-};
-
-static void ring_slots(const FractalHost &F, int M, uint32_t P, std::vector<RingSlot> &out)
-{
-    int64_t side = 1;
-    uint64_t KM = 1;
-    for (int i = 0; i < M; ++i) {
-        side *= F.s;
-        KM *= F.k;
-    }
-    std::vector<uint8_t> seen((size_t)P * P, 0);
-    out.clear();
-    for (uint64_t c = 0; c < KM; ++c) {
-        int64_t x, y;
-        host_lambda(F, M, c, x, y);
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int64_t qx = x + dx, qy = y + dy;
-                if (qx >= 0 && qy >= 0 && qx < side && qy < side) continue;
-                const int tdx = qx < 0 ? -1 : (qx >= side ? 1 : 0), tdy = qy < 0 ? -1 : (qy >= side ? 1 : 0);
-                const int64_t j = host_nu(F, M, qx - tdx * side, qy - tdy * side);
-                if (j < 0) continue;
-                const uint32_t pos = (uint32_t)((qy + 1) * P + (qx + 1));
-                if (seen[pos]) continue;
-                seen[pos] = 1;
-                const int d = (tdy + 1) * 3 + (tdx + 1);
-                const uint32_t d8 = (uint32_t)(d < 4 ? d : d - 1);
-                out.push_back(RingSlot{(uint16_t)pos, (d8 << 16) | (uint32_t)j});
-            }
-    }
-}
-
 template <class Op, int PT>
 static unsigned occupancy_grid(size_t lds, uint64_t ntiles, int device)
 {
@@ -196,7 +162,7 @@ sqz_status xtile_prepare(FractalHost &F)
     if (F.r < 1) return SQZ_OK;
     // the largest level whose expanded tile fits the LDS budget in binary32
     int M = F.r < 12 ? F.r : 12;
-    std::vector<RingSlot> ring;
+    std::vector<XRingSlot> ring;
     for (; M >= 1; --M) {
         uint64_t B = 1, KM = 1;
         for (int i = 0; i < M; ++i) {
@@ -206,7 +172,7 @@ sqz_status xtile_prepare(FractalHost &F)
         const uint64_t P = (B + 2 + 3) / 4 * 4;  // ring on both sides, pitch a multiple of 4
         if (P * P > 65535 || KM > 65535) continue;
         if (xt_layout((uint32_t)P, (uint32_t)KM, 0, 4, true, false, nullptr) > kXLdsBudget) continue;
-        ring_slots(F, M, (uint32_t)P, ring);
+        xtile_ring_slots(F, M, (uint32_t)P, ring);
         if (xt_layout((uint32_t)P, (uint32_t)KM, (uint32_t)ring.size(), 4, true, false, nullptr) <= kXLdsBudget) break;
     }
     if (M < 1) return SQZ_OK;  // no expanded tile for this pattern
@@ -223,34 +189,11 @@ sqz_status xtile_prepare(FractalHost &F)
     const uint32_t P = X->P, KM = X->KM, R = X->R;
 
     // tables: lambda positions, cell entries (diffusion), ring positions, ring info
-    std::vector<uint16_t> lam(KM);
-    std::vector<uint32_t> ent(KM);
-    const int64_t side = (int64_t)X->B;
-    for (uint32_t c = 0; c < KM; ++c) {
-        int64_t x, y;
-        host_lambda(F, M, c, x, y);
-        lam[c] = (uint16_t)((y + 1) * P + (x + 1));
-        // member neighbours inside the tile, and per adjacent tile the member
-        // cells of that tile (its own copy of the level-M pattern) it touches
-        uint32_t inner = 0, cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-                if (dx == 0 && dy == 0) continue;
-                const int64_t qx = x + dx, qy = y + dy;
-                const int tdx = qx < 0 ? -1 : (qx >= side ? 1 : 0), tdy = qy < 0 ? -1 : (qy >= side ? 1 : 0);
-                const bool member = host_nu(F, M, qx - tdx * side, qy - tdy * side) >= 0;
-                if (!member) continue;
-                if (tdx == 0 && tdy == 0) {
-                    ++inner;
-                } else {
-                    const int d = (tdy + 1) * 3 + (tdx + 1);
-                    ++cnt[d < 4 ? d : d - 1];
-                }
-            }
-        uint32_t e = lam[c] | inner << 16;
-        for (int d8 = 0; d8 < 8; ++d8) e |= cnt[d8] << deg_field(d8);  // sides <= 3, corners <= 1
-        ent[c] = e;
-    }
+    std::vector<uint16_t> lam;
+    std::vector<uint32_t> ent;
+    int shifts[8];
+    for (int d8 = 0; d8 < 8; ++d8) shifts[d8] = deg_field(d8);
+    xtile_cell_entries(F, M, P, shifts, lam, ent);
     const size_t o_lam = 0, o_ent = xt_align16(o_lam + KM * 2), o_rpos = xt_align16(o_ent + (size_t)KM * 4),
                  o_rinfo = xt_align16(o_rpos + (size_t)R * 2), total = xt_align16(o_rinfo + (size_t)R * 4 + 4);
     std::vector<uint8_t> blob(total, 0);
@@ -330,42 +273,18 @@ static sqz_status xtile_prepare_multi(FractalHost &F, XTileConfig *X)
         if (K > B) continue;
         const uint32_t P = (uint32_t)((B + 2 * K + 3) / 4 * 4), rows = (uint32_t)(B + 2 * K);
         if ((uint64_t)P * rows > 65535) continue;
-        // ring slots by layer: member cells of the adjacent tiles within K of the box
-        struct Slot {
-            uint16_t pos;
-            uint32_t info;
-        };
-        std::vector<Slot> ring;
-        std::vector<uint32_t> start(1, 0);
-        for (int d = 1; d <= K; ++d) {
-            for (int64_t qy = -K; qy < B + K; ++qy)
-                for (int64_t qx = -K; qx < B + K; ++qx) {
-                    const int64_t ex = qx < 0 ? -qx : (qx >= B ? qx - B + 1 : 0);
-                    const int64_t ey = qy < 0 ? -qy : (qy >= B ? qy - B + 1 : 0);
-                    if ((ex > ey ? ex : ey) != d) continue;
-                    const int tdx = qx < 0 ? -1 : (qx >= B ? 1 : 0), tdy = qy < 0 ? -1 : (qy >= B ? 1 : 0);
-                    const int64_t j = host_nu(F, M, qx - tdx * B, qy - tdy * B);
-                    if (j < 0) continue;
-                    const int dd = (tdy + 1) * 3 + (tdx + 1);
-                    const uint32_t d8 = (uint32_t)(dd < 4 ? dd : dd - 1);
-                    ring.push_back(Slot{(uint16_t)((qy + K) * P + (qx + K)), (d8 << 16) | (uint32_t)j});
-                }
-            start.push_back((uint32_t)ring.size());
-        }
+        // ring slots by layer (member cells of the adjacent tiles within K of the box),
+        // box positions and membership of the tile's cells
+        std::vector<XRingSlot> ring;
+        std::vector<uint32_t> start;
+        std::vector<uint16_t> lam;
+        std::vector<uint8_t> mem;
+        xtile_layer_tables(F, M, K, P, rows, ring, start, lam, mem);
         const uint32_t R = (uint32_t)ring.size();
         if (R > 4 * 256) continue;
         const size_t lds_life = xt_layoutK(P, rows, KM, R, 1, true, nullptr);
         const size_t lds_diff = xt_layoutK(P, rows, KM, R, 4, false, nullptr);
         if (lds_life > kXLdsBudgetK || lds_diff > kXLdsBudgetK) continue;
-        // tables: lambda positions, membership of the tile's cells, ring slots
-        std::vector<uint16_t> lam(KM);
-        std::vector<uint8_t> mem((size_t)P * rows, 0);
-        for (uint32_t c = 0; c < KM; ++c) {
-            int64_t x, y;
-            host_lambda(F, M, c, x, y);
-            lam[c] = (uint16_t)((y + K) * P + (x + K));
-            mem[lam[c]] = 1;
-        }
         const size_t o_lam = 0, o_mem = xt_align16(o_lam + KM * 2), o_rpos = xt_align16(o_mem + (size_t)P * rows),
                      o_rinfo = xt_align16(o_rpos + (size_t)R * 2), total = xt_align16(o_rinfo + (size_t)R * 4 + 4);
         std::vector<uint8_t> blob(total, 0);
@@ -521,16 +440,24 @@ sqz_status launch_diffuse(const FractalHost &F, int dtype, float coef, int round
     return e == hipSuccess ? SQZ_OK : hip_error(e, "diffusion (cell) launch");
 }
 
-sqz_status launch_mass(const FractalHost &F, int dtype, const void *u, double offset, double *work, hipStream_t st)
+// The two mass kernels with the partials at `part` (kMassGrid doubles) and
+// the sum written to *result.
+static sqz_status mass_launches(const FractalHost &F, int dtype, const void *u, double offset, double *part,
+                                double *result, hipStream_t st)
 {
     if (dtype == SQZ_F32)
-        hipLaunchKernelGGL(k_mass_partial<float>, dim3(kMassGrid), dim3(256), 0, st, (const float *)u, F.N, work + 1);
+        hipLaunchKernelGGL(k_mass_partial<float>, dim3(kMassGrid), dim3(256), 0, st, (const float *)u, F.N, part);
     else
         hipLaunchKernelGGL(k_mass_partial<uint16_t>, dim3(kMassGrid), dim3(256), 0, st, (const uint16_t *)u, F.N,
-                           work + 1);
-    hipLaunchKernelGGL(k_mass_final, dim3(1), dim3(256), 0, st, work, F.N, offset);
+                           part);
+    hipLaunchKernelGGL(k_mass_final, dim3(1), dim3(256), 0, st, (const double *)part, result, F.N, offset);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? SQZ_OK : hip_error(e, "mass launch");
+}
+
+sqz_status launch_mass(const FractalHost &F, int dtype, const void *u, double offset, double *work, hipStream_t st)
+{
+    return mass_launches(F, dtype, u, offset, work + 1, work, st);
 }
 
 sqz_status launch_bf16_convert(const FractalHost &F, int encode, const float *u, float offset, uint16_t *b,
