@@ -59,19 +59,19 @@ def run_launches(F, steps: int) -> int:
     return n + (1 if n % 2 != steps % 2 else 0)
 
 
-def compact_run(torch, F, seed, p, steps, warmup, impl="auto"):
+def compact_run(torch, F, seed, p, steps, warmup, impl="auto", form="auto"):
     """Seconds for `steps` Life steps after `warmup` untimed ones.  impl "auto" runs
-    them as one sqz_compact_run call (the library's step loop); other impls launch
-    one step at a time."""
+    them as one sqz_compact_run_form call (the library's step loop, in run form
+    `form`); other impls launch one step at a time."""
     a = F.fill_bernoulli(seed, p)
     b = torch.empty_like(a)
     if impl == "auto":
-        x = F.compact_run(a, b, warmup)
+        x = F.compact_run(a, b, warmup, form=form)
         y = b if x is a else a
         torch.cuda.synchronize()
         start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         start.record()
-        F.compact_run(x, y, steps)
+        F.compact_run(x, y, steps, form=form)
         end.record()
         torch.cuda.synchronize()
         sec = start.elapsed_time(end) / 1e3
@@ -100,26 +100,62 @@ def bb_run(torch, F, seed, p, steps, warmup):
     return sec
 
 
-def profiled_traffic(workload: str):
-    """Counter-measured bytes per launch of the tiled kernel, from the committed
-    rocprofv3 summary, if the kernel source is unchanged since it was taken."""
+def tile_source_hash() -> str:
     import hashlib
-    import re
 
     src = os.path.join(ROOT, "paper_2201_00613_amd", "csrc")
     h = hashlib.sha256()
     for f in ("life_tile.hip", "tile_device.h", "common.h"):
         h.update(open(os.path.join(src, f), "rb").read())
-    path = os.path.join(ROOT, "profiles", "k_life_tileK_triangle_r16.md")
+    return h.hexdigest()[:16]
+
+
+def profiled_counters(profile: str, workload: str):
+    """Counter figures of a tiled kernel (bytes and vector-ALU instructions per
+    dispatch) from a committed rocprofv3 summary under profiles/, if the kernel
+    source is unchanged since it was taken (sha256 prefix of the tile sources)."""
+    import re
+
+    path = os.path.join(ROOT, "profiles", profile)
     if not os.path.exists(path):
         return None
     m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
     if not m:
         return None
     rec = json.loads(m.group(1))
-    if rec["workload"] != workload or rec["source_sha256_16"] != h.hexdigest()[:16]:
+    if rec["workload"] != workload or rec["source_sha256_16"] != tile_source_hash():
         return None
     return rec
+
+
+# Vector-ALU peak of the chip: the datasheet's binary32 vector rate, 157.3 TFLOP/s at
+# 2.4 GHz on 256 CUs, is 256 FLOP per CU per clock, i.e. 128 lanes of fused
+# multiply-add, two 64-lane wave-instructions per CU per clock.
+VALU_PEAK_PER_CU_CLOCK = 157.3e12 / (NUM_CUS * CLOCK_HZ) / 128
+VALU_PEAK_G = VALU_PEAK_PER_CU_CLOCK * NUM_CUS * CLOCK_HZ / 1e9
+
+
+def alu_roofline(rec, steps: int, sec: float, launches: int, cells: int, profile: str):
+    """Roofline of a tiled Life run bound by vector-ALU issue: counter-measured VALU
+    wave-instructions per dispatch (from the committed profile, for a dispatch of the
+    same number of steps) over the live launch time, against the chip's peak; HBM
+    counter bytes per dispatch over the same time as `traffic`.  None when the
+    profile does not hold a dispatch of this many steps."""
+    if not rec:
+        return None
+    per = steps // launches if launches and steps % launches == 0 else None
+    entry = rec["dispatch"].get(str(per)) if per else None
+    if entry is None:
+        return None
+    launch_s = sec / launches
+    achieved = entry["valu_insts"] / launch_s / 1e9
+    ceiling = rec["valu_mix_ceiling_per_cu_clock"] * NUM_CUS * CLOCK_HZ / 1e9
+    return {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_G, "unit": "G VALU wave-instructions/s",
+            "frac": achieved / VALU_PEAK_G, "traffic": entry["traffic_bytes"] / launch_s / 1e9,
+            "traffic_unit": "GB/s", "traffic_vs_algorithmic": entry["traffic_bytes"] / (BYTES_PER_UPDATE * cells),
+            "per_cu_clock": achieved * 1e9 / NUM_CUS / CLOCK_HZ,
+            "measured_mix_ceiling": ceiling, "frac_of_measured_mix_ceiling": achieved / ceiling,
+            "counters_from": f"profiles/{profile} (dispatches of {per} steps; source hash {rec['source_sha256_16']})"}
 
 
 def cpu_baseline(r: int, seed: int, p: float, min_sec: float, max_steps: int) -> dict:
@@ -283,12 +319,12 @@ def batch_leg(torch, sqz, steps: int) -> dict:
     return res
 
 
-def repeat_stats(torch, F, seed, p, steps: int, reps: int) -> dict:
+def repeat_stats(torch, F, seed, p, steps: int, reps: int, form: str = "auto") -> dict:
     """Mean and standard error of ms per step over `reps` further timed runs of the
-    same `steps` (each one sqz_compact_run call on freshly filled buffers)."""
+    same `steps` (each one sqz_compact_run_form call on freshly filled buffers)."""
     import statistics
 
-    ms = [compact_run(torch, F, seed, p, steps, 2) * 1e3 / steps for _ in range(reps)]
+    ms = [compact_run(torch, F, seed, p, steps, 2, form=form) * 1e3 / steps for _ in range(reps)]
     return {"n": reps, "mean_ms_per_step": statistics.fmean(ms),
             "stderr_ms_per_step": statistics.stdev(ms) / len(ms) ** 0.5 if reps > 1 else 0.0,
             "min_ms_per_step": min(ms), "max_ms_per_step": max(ms)}
@@ -361,6 +397,8 @@ def main() -> int:
                     help="untimed steps first (20: two launches of the ten-step kernel the timed run uses)")
     ap.add_argument("--level", type=int, default=16)
     ap.add_argument("--impl", default="auto", choices=["auto", "tile", "cell"])
+    ap.add_argument("--form", default="auto", choices=["auto", "launches", "resident"],
+                    help="run form of sqz_compact_run_form (auto: resident when the tiles fit the chip)")
     ap.add_argument("--bb-steps", type=int, default=10)
     ap.add_argument("--r20-steps", type=int, default=20)
     ap.add_argument("--no-bb", action="store_true")
@@ -381,6 +419,9 @@ def main() -> int:
     ap.add_argument("--cpu-max-steps", type=int, default=8)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only time a plain device copy of this many bytes (counter calibration)")
+    ap.add_argument("--profile-run", type=int, default=0,
+                    help="only run the headline workload: one untimed and three timed runs of this many steps in "
+                         "--form (every dispatch of a profiled kernel then has the same size)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the library has a "
@@ -402,11 +443,24 @@ def main() -> int:
         return 0
     seed, p, r = 2201, 0.5, args.level
     F = sqz.Fractal(*TRIANGLE, r)
-    log(f"[bench] triangle r={r}: {F.cells} cells, tile level {F.tile_level}, impl {args.impl}")
-    sec = compact_run(torch, F, seed, p, args.steps, args.warmup, args.impl)
+    form = args.form
+    if args.profile_run:
+        sec = [compact_run(torch, F, seed, p, args.profile_run, args.profile_run, form=form)]
+        sec += [compact_run(torch, F, seed, p, args.profile_run, 0, form=form) for _ in range(2)]
+        print(json.dumps({"profile_run": args.profile_run, "form": form, "level": r,
+                          "ms_per_step": [x * 1e3 / args.profile_run for x in sec]}), flush=True)
+        return 0
+    if args.impl != "auto":
+        used = "one step per launch"
+    elif form == "resident" or (form == "auto" and F.resident_run and args.steps >= 2):
+        used = "resident"
+    else:
+        used = "launches"
+    log(f"[bench] triangle r={r}: {F.cells} cells, tile level {F.tile_level}, impl {args.impl}, run form {used}")
+    sec = compact_run(torch, F, seed, p, args.steps, args.warmup, args.impl, form)
     ups = F.cells * args.steps / sec
     ms = sec * 1e3 / args.steps
-    launches = run_launches(F, args.steps) if args.impl == "auto" else args.steps
+    launches = {"resident": 1, "launches": run_launches(F, args.steps)}.get(used, args.steps)
     # algorithmic bytes per launch: each launch reads and writes every cell once
     gbs = BYTES_PER_UPDATE * F.cells * launches / sec / 1e9
     log(f"[bench] compact: {ms:.4f} ms/step ({launches} launches), {ups:.4e} cell-updates/s, "
@@ -418,13 +472,30 @@ def main() -> int:
         "vs_baseline": None, "dtype": "u8", "data": "synthetic",
         "config": {"workload": f"sierpinski-triangle-r{r}-life-b3s23", "fractal": "sierpinski triangle s=2 k=3",
                    "level": r, "cells": F.cells, "bernoulli_p": p, "seed": seed, "impl": args.impl,
-                   "tile_level": F.tile_level, "steps_per_launch": args.steps / launches,
-                   "note": "2 x 43 MB working set is Infinity-Cache resident"},
-        "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gbs / HBM_PEAK_GBS, "traffic": None,
-                     # 2 B per cell-update over the step time: the bytes one-step launches would move
-                     "step_equivalent_gbs": BYTES_PER_UPDATE * F.cells * args.steps / sec / 1e9},
+                   "run_form": used, "tile_level": F.tile_level, "launches": launches,
+                   "steps_between_exchanges" if used == "resident" else "steps_per_launch":
+                       F.run_steps_per_launch if used == "resident" else args.steps / launches,
+                   "note": "2 x 43 MB working set is Infinity-Cache resident" if r == 16 else ""},
     }
+    hbm = {"algorithmic_gbs_per_launch": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS,
+           # 2 B per cell-update over the step time: the bytes one-step launches would move
+           "step_equivalent_gbs": BYTES_PER_UPDATE * F.cells * args.steps / sec / 1e9}
+    profile = {"resident": "k_life_tileR_triangle_r16.md", "launches": "k_life_tileK_triangle_r16.md"}.get(used)
+    rec = profiled_counters(profile, out["config"]["workload"]) if profile else None
+    out["roofline"] = alu_roofline(rec, args.steps, sec, launches, F.cells, profile) or {
+        "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+        "traffic": None, "note": "no committed counter profile for this kernel source and step count"}
+    out["roofline"]["hbm"] = hbm
+    if used == "resident":
+        sl = compact_run(torch, F, seed, p, args.steps, args.warmup, "auto", "launches")
+        nl = run_launches(F, args.steps)
+        out["launches_form"] = {"ms_per_step": sl * 1e3 / args.steps, "cell_updates_per_s": F.cells * args.steps / sl,
+                                "launches": nl, "algorithmic_gbs_per_launch": BYTES_PER_UPDATE * F.cells * nl / sl / 1e9}
+        rl = profiled_counters("k_life_tileK_triangle_r16.md", out["config"]["workload"])
+        alu = alu_roofline(rl, args.steps, sl, nl, F.cells, "k_life_tileK_triangle_r16.md")
+        if alu:
+            out["launches_form"]["roofline"] = alu
+        log(f"[bench] launches of {F.run_steps_per_launch} steps: {sl * 1e3 / args.steps:.4f} ms/step")
     if args.impl == "auto" and F.run_steps_per_launch >= 2:
         s1 = compact_run(torch, F, seed, p, args.steps, args.warmup, "tile")
         out["one_step_per_launch"] = {"ms_per_step": s1 * 1e3 / args.steps,
@@ -432,24 +503,11 @@ def main() -> int:
                                       "algorithmic_gbs": BYTES_PER_UPDATE * F.cells * args.steps / s1 / 1e9}
         log(f"[bench] one step per launch: {s1 * 1e3 / args.steps:.4f} ms/step")
     if args.reps > 0:
-        out["repeats"] = repeat_stats(torch, F, seed, p, args.steps, args.reps)
+        out["repeats"] = repeat_stats(torch, F, seed, p, args.steps, args.reps, form)
     out["memory_reduction_factor"] = F.n * F.n / F.cells  # n^2 bytes expanded vs N bytes compact
     out["paper_context"] = {"hardware": "NVIDIA A100-40GB", "speedup_vs_bb": "~12x (level 16, its best block size)",
                             "memory_reduction_factor": "~315x at level 20; 99.8x at level 16 (rho = 1)",
                             "note": "the paper's figures, context only"}
-    rec = profiled_traffic(out["config"]["workload"]) if args.impl == "auto" else None
-    if rec:
-        out["roofline"]["traffic"] = rec["traffic_bytes_per_launch"] / (sec / launches) / 1e9
-        out["roofline"]["traffic_bytes_per_launch"] = rec["traffic_bytes_per_launch"]
-        out["roofline"]["traffic_vs_algorithmic"] = rec["traffic_bytes_per_launch"] / (BYTES_PER_UPDATE * F.cells)
-        K = rec["steps_per_launch"]
-        if "valu_insts_per_launch" in rec and args.steps % K == 0 and launches == args.steps // K:
-            # vector-ALU issue of the same launches: counter-measured instructions per launch over
-            # the live launch time, against the calibrated ceiling for the kernel's instruction mix
-            per_cu_clock = rec["valu_insts_per_launch"] / (sec / launches) / NUM_CUS / CLOCK_HZ
-            out["roofline"]["valu_issue"] = {
-                "achieved": per_cu_clock, "ceiling": rec["valu_ceiling_per_cu_clock"],
-                "unit": "wave-instructions per CU per clock", "frac": per_cu_clock / rec["valu_ceiling_per_cu_clock"]}
     if not args.no_bb:
         bsec = bb_run(torch, F, seed, p, args.bb_steps, 2)
         bb_ups = F.cells * args.bb_steps / bsec

@@ -103,6 +103,29 @@ typedef enum sqz_impl {
  *                 (SQZ_ERR_UNSUPPORTED otherwise).  Results equal SCALAR's. */
 typedef enum sqz_map_impl { SQZ_MAP_SCALAR = 0, SQZ_MAP_MFMA = 1 } sqz_map_impl;
 
+/* How sqz_compact_run_form advances a run.
+ *   SQZ_RUN_AUTO: RESIDENT when the fractal offers it (sqz_info.resident_run),
+ *                 the buffers are 16-byte aligned and steps >= 2; else LAUNCHES.
+ *   SQZ_RUN_LAUNCHES: one kernel launch per group of up to
+ *                 sqz_info.run_steps_per_launch steps, each reading its input
+ *                 buffer whole and writing its output buffer whole (temporal
+ *                 blocking within a launch, Section "Moving from Thread-level
+ *                 to Block-level" for the tiles).
+ *   SQZ_RUN_RESIDENT: all steps in one launch, one workgroup per
+ *                 level-M subtree and every subtree held in on-chip memory for
+ *                 the whole run; every run_steps_per_launch steps the subtrees
+ *                 exchange only the cells their neighbours read (through the
+ *                 two caller buffers) at a grid-wide barrier.  Offered for
+ *                 patterns with a bit-sliced tiled kernel whose subtrees all fit
+ *                 on the chip at once (the level-16 triangle: 729 subtrees of
+ *                 level 10).  Runs on one fractal must not overlap on the device
+ *                 (each run uses the fractal's barrier counter) and need the
+ *                 whole GPU: a run that overlaps another resident run, or
+ *                 cannot get all its workgroups on the chip, gives up its
+ *                 barrier waits after seconds; the next run call on the
+ *                 fractal then returns SQZ_ERR_HIP. */
+typedef enum sqz_run_form { SQZ_RUN_AUTO = 0, SQZ_RUN_LAUNCHES = 1, SQZ_RUN_RESIDENT = 2 } sqz_run_form;
+
 /* Storage type of the diffusion field. */
 typedef enum sqz_dtype { SQZ_F32 = 0, SQZ_BF16 = 1 } sqz_dtype;
 
@@ -151,6 +174,7 @@ typedef struct sqz_info {
                                      16-byte alignment) or bit-row tiles (8-byte), 3 with
                                      multi-step expanded tiles, else 1 */
     int32_t bits_level;  /* level M of the bit-row tiles of SQZ_IMPL_BITS (0 if none) */
+    int32_t resident_run; /* 1 if sqz_compact_run_form offers SQZ_RUN_RESIDENT for this fractal */
 } sqz_info;
 
 /*
@@ -244,6 +268,18 @@ SQZ_API sqz_status sqz_compact_step_impl(const sqz_fractal *f, sqz_impl impl, co
  */
 SQZ_API sqz_status sqz_compact_run(const sqz_fractal *f, uint8_t *d_a, uint8_t *d_b, int32_t steps,
                            void *stream);
+
+/*
+ * As sqz_compact_run (which is form SQZ_RUN_AUTO) with an explicit run form
+ * (sqz_run_form above; Section "Experimental Setup and Results": the Life
+ * iterations of the benchmark).  Both buffers are read and written: their
+ * contents other than the result are unspecified afterwards.
+ *   SQZ_RUN_RESIDENT: SQZ_ERR_UNSUPPORTED if the fractal does not offer it,
+ *   SQZ_ERR_INVALID for buffers that are not 16-byte aligned.  Unknown forms:
+ *   SQZ_ERR_INVALID.
+ */
+SQZ_API sqz_status sqz_compact_run_form(const sqz_fractal *f, sqz_run_form form, uint8_t *d_a, uint8_t *d_b,
+                                        int32_t steps, void *stream);
 
 /*
  * Bounding-box baseline (Section "Experimental Setup and Results", approach

@@ -11,13 +11,15 @@ import ctypes
 
 from ._lib import (BF16, F32, HOLE, IMPL_AUTO, IMPL_BITS, IMPL_CELL, IMPL_CELL_MFMA, IMPL_TILE, IMPL_XTILE,
                    LAYOUT_COMPACT, LAYOUT_EXPANDED, MAP_MFMA, MAP_SCALAR, MASS_WORK_DOUBLES, ROUND_NEAREST_EVEN,
-                   ROUND_STOCHASTIC, Diffusion, Info, SqueezeError, check, lib)
+                   ROUND_STOCHASTIC, RUN_AUTO, RUN_LAUNCHES, RUN_RESIDENT, Diffusion, Info, SqueezeError, check,
+                   lib)
 
 __all__ = ["Fractal", "SqueezeError", "HOLE", "descriptor_check", "IMPLS"]
 
 IMPLS = {"auto": IMPL_AUTO, "cell": IMPL_CELL, "tile": IMPL_TILE, "xtile": IMPL_XTILE, "cell_mfma": IMPL_CELL_MFMA,
          "bits": IMPL_BITS}
 MAP_IMPLS = {"scalar": MAP_SCALAR, "mfma": MAP_MFMA}
+RUN_FORMS = {"auto": RUN_AUTO, "launches": RUN_LAUNCHES, "resident": RUN_RESIDENT}
 DTYPES = {"f32": F32, "bf16": BF16}
 ROUNDINGS = {"nearest": ROUND_NEAREST_EVEN, "stochastic": ROUND_STOCHASTIC}
 
@@ -76,6 +78,7 @@ class Fractal:
         self.tile_level = info.tile_level
         self.xtile_level = info.xtile_level
         self.run_steps_per_launch = info.run_steps_per_launch
+        self.resident_run = bool(info.resident_run)
         self.bits_level = info.bits_level
         self.offsets = [tuple(map(int, xy)) for xy in offsets]
 
@@ -160,13 +163,15 @@ class Fractal:
             check(lib().sqz_compact_step_impl(self._h, IMPLS[impl], _ptr(src), _ptr(dst), st))
         return dst
 
-    def compact_run(self, a, b, steps: int):
-        """steps Life steps ping-ponging a -> b -> a ...; returns the tensor holding the result."""
+    def compact_run(self, a, b, steps: int, form: str = "auto"):
+        """steps Life steps ping-ponging a -> b -> a ...; returns the tensor holding the result.
+        form: "auto", "launches" (one launch per group of steps) or "resident" (one launch,
+        tiles held on chip for the whole run)."""
         torch, dev, st = self._ctx()
         self._need(a, torch.uint8, self.cells, "a")
         self._need(b, torch.uint8, self.cells, "b")
         with dev:
-            check(lib().sqz_compact_run(self._h, _ptr(a), _ptr(b), steps, st))
+            check(lib().sqz_compact_run_form(self._h, RUN_FORMS[form], _ptr(a), _ptr(b), steps, st))
         return a if steps % 2 == 0 else b
 
     def expanded_step(self, src, dst):

@@ -13,6 +13,7 @@ HOLE = (1 << 64) - 1
 LAYOUT_COMPACT, LAYOUT_EXPANDED = 0, 1
 IMPL_AUTO, IMPL_CELL, IMPL_TILE, IMPL_XTILE, IMPL_CELL_MFMA, IMPL_BITS = 0, 1, 2, 3, 4, 5
 MAP_SCALAR, MAP_MFMA = 0, 1
+RUN_AUTO, RUN_LAUNCHES, RUN_RESIDENT = 0, 1, 2
 F32, BF16 = 0, 1
 ROUND_NEAREST_EVEN, ROUND_STOCHASTIC = 0, 1
 MASS_WORK_DOUBLES = 1025
@@ -31,6 +32,7 @@ class Info(ctypes.Structure):
         ("compact_w", ctypes.c_uint64), ("compact_h", ctypes.c_uint64),
         ("has_tile", ctypes.c_int32), ("xtile_level", ctypes.c_int32),
         ("run_steps_per_launch", ctypes.c_int32), ("bits_level", ctypes.c_int32),
+        ("resident_run", ctypes.c_int32),
     ]
 
 
@@ -79,6 +81,8 @@ SIGNATURES = {
                                              ctypes.c_void_p]),
     "sqz_compact_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                        ctypes.c_void_p]),
+    "sqz_compact_run_form": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_int32, ctypes.c_void_p]),
     "sqz_expanded_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "sqz_diffuse_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Diffusion), ctypes.c_uint64, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p]),

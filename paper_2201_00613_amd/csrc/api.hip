@@ -163,6 +163,7 @@ sqz_status sqz_fractal_info(const sqz_fractal *f, sqz_info *out)
                   kx = xtile_steps_per_launch(f->h);
         const int k = f->h.tile_kind ? kt : (f->h.bitbox ? kb : kx);
         out->run_steps_per_launch = k > 1 ? k : 1;
+        out->resident_run = tile_resident(f->h) ? 1 : 0;
     }
     return SQZ_OK;
 }
@@ -296,12 +297,28 @@ sqz_status sqz_compact_step(const sqz_fractal *f, const uint8_t *d_in, uint8_t *
 
 sqz_status sqz_compact_run(const sqz_fractal *f, uint8_t *d_a, uint8_t *d_b, int32_t steps, void *stream)
 {
+    return sqz_compact_run_form(f, SQZ_RUN_AUTO, d_a, d_b, steps, stream);
+}
+
+sqz_status sqz_compact_run_form(const sqz_fractal *f, sqz_run_form form, uint8_t *d_a, uint8_t *d_b, int32_t steps,
+                                void *stream)
+{
     sqz_status st = check_handle(f);
     if (st != SQZ_OK) return st;
+    if (form != SQZ_RUN_AUTO && form != SQZ_RUN_LAUNCHES && form != SQZ_RUN_RESIDENT)
+        return set_error(SQZ_ERR_INVALID, "unknown run form %d", (int)form);
     if (steps < 0) return set_error(SQZ_ERR_INVALID, "steps < 0");
     if (!d_a || !d_b) return set_error(SQZ_ERR_INVALID, "NULL buffer");
     if (overlap(d_a, d_b, f->h.N)) return set_error(SQZ_ERR_INVALID, "d_a and d_b overlap");
     const bool aligned = !(((uintptr_t)d_a | (uintptr_t)d_b) & 15);
+    if (form == SQZ_RUN_RESIDENT) {
+        if (!tile_resident(f->h))
+            return set_error(SQZ_ERR_UNSUPPORTED, "no resident run: the tiles of this fractal do not fit the chip at once");
+        if (!aligned) return set_error(SQZ_ERR_INVALID, "the resident run needs 16-byte aligned buffers");
+        return launch_life_tile_resident(f->h, d_a, d_b, steps, (hipStream_t)stream);
+    }
+    if (form == SQZ_RUN_AUTO && steps >= 2 && aligned && tile_resident(f->h))
+        return launch_life_tile_resident(f->h, d_a, d_b, steps, (hipStream_t)stream);
     const bool aligned8 = !(((uintptr_t)d_a | (uintptr_t)d_b) & 7);
     const bool tiled = f->h.tile_kind && aligned, bits = !tiled && f->h.bitbox && aligned8;
     const int K = tiled ? tile_steps_per_launch(f->h)

@@ -213,5 +213,8 @@ const FractalHost &fractal_host_of(const sqz_fractal *f);
 sqz_status launch_life_tile(const FractalHost &F, const uint8_t *in, uint8_t *out, hipStream_t st);
 int tile_steps_per_launch(const FractalHost &F);  // most Life steps one tiled launch can take (0: no tiles)
 sqz_status launch_life_tile_steps(const FractalHost &F, const uint8_t *in, uint8_t *out, int steps, hipStream_t st);
+bool tile_resident(const FractalHost &F);  // the resident run is available
+// all steps in one launch with the tiles held in LDS (all on the chip at once); result in a (steps even) or b
+sqz_status launch_life_tile_resident(const FractalHost &F, uint8_t *a, uint8_t *b, int steps, hipStream_t st);
 
 }  // namespace sqz

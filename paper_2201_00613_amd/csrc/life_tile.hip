@@ -1,6 +1,7 @@
 // Bit-sliced block-level Life kernels (device code in tile_device.h) and
 // their host-side preparation: tile halo slots, block-halo tables, per-tile
 // halo indices.
+#include <algorithm>
 #include <type_traits>
 #include <vector>
 
@@ -13,12 +14,22 @@ namespace sqz {
 #endif
 constexpr int kTileNT = SQZ_TILE_NT;
 
-// Lanes per workgroup of a pattern's tiled kernels: 512 for the level-10
-// tiles of large triangles (2,187 blocks), else kTileNT.
+#ifndef SQZ_BIG_NT  // lanes per workgroup of the level-10 triangle tiles
+#define SQZ_BIG_NT 512
+#endif
+#ifndef SQZ_TILEK_FULL  // 1: the multi-step launches run whole slots without a branch (more registers)
+#define SQZ_TILEK_FULL 0
+#endif
+#ifndef SQZ_BIG_WAVES  // minimum waves per SIMD (register budget) of their multi-step kernels
+#define SQZ_BIG_WAVES 7
+#endif
+
+// Lanes per workgroup of a pattern's tiled kernels: SQZ_BIG_NT for the
+// level-10 tiles of large triangles (2,187 blocks), else kTileNT.
 template <class Pat>
 constexpr int nt_of()
 {
-    return std::is_same<Pat, PatTriangleBig>::value ? 512 : kTileNT;
+    return std::is_same<Pat, PatTriangleBig>::value ? SQZ_BIG_NT : kTileNT;
 }
 
 template <class Pat, int NT>
@@ -37,7 +48,7 @@ __global__ void __launch_bounds__(NT) k_life_tile(TileArgs A, const uint8_t *__r
 }
 
 template <class Pat, int K, int NT>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 256 ? 8 : 7)))
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 256 ? 8 : SQZ_BIG_WAVES)))
 k_life_tileK(TileArgs A, const uint8_t *__restrict__ in, uint8_t *__restrict__ out)
 {
     using LDS = TileLds<Pat>;
@@ -45,11 +56,36 @@ k_life_tileK(TileArgs A, const uint8_t *__restrict__ in, uint8_t *__restrict__ o
     __shared__ __align__(16) uint32_t s_ring[kRingTab];
     uint32_t *const buf[3] = {s_buf[0], s_buf[1], s_buf[2]};
     const uint32_t G = gridDim.x;
+    const bool full = SQZ_TILEK_FULL && A.nblocks == LDS::NBMAX;  // every tile has the pattern's largest level
     for (uint64_t round = 0; round * G < A.ntiles; ++round) {
         const uint64_t t = round * G + xcd_remap(blockIdx.x, G);
         if (t >= A.ntiles) break;  // uniform across the workgroup
-        tile_bodyK<Pat, K, NT>(A, in, out, t, buf, s_ring);
+        if (full)
+            tile_bodyK<Pat, K, NT, true>(A, in, out, t, buf, s_ring);
+        else
+            tile_bodyK<Pat, K, NT>(A, in, out, t, buf, s_ring);
     }
+}
+
+#ifndef SQZ_RESIDENT_PAD  // LDS reserved per workgroup of the resident run (bytes; balance, see prepare_resident)
+#define SQZ_RESIDENT_PAD(pad) (pad)
+#endif
+
+// Resident run: one workgroup per tile for all steps, every tile on the chip at once.
+template <class Pat, int NT>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 256 ? 8 : SQZ_BIG_WAVES)))
+k_life_tileR(TileArgs A, ResidentArgs P)
+{
+    using LDS = TileLds<Pat>;
+    __shared__ uint32_t s_buf[3 * LDS::WORDS];
+    __shared__ __align__(16) uint32_t s_ring[kRingTab];
+    __shared__ uint32_t s_rs[kMaxSteps + 1];
+    tile_bodyR<Pat, NT>(A, P, xcd_remap(blockIdx.x, gridDim.x), s_buf, s_ring, s_rs);
+}
+
+__global__ void k_zero_words(uint32_t *p, uint32_t n)
+{
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
 }
 
 // Tile-halo cells of every tile: global compact index of each slot's cell.
@@ -83,6 +119,111 @@ bool matches(const FractalHost &F)
     for (int j = 0; j < Pat::K; ++j)
         if (F.ox[j] != Pat::OX[j] || F.oy[j] != Pat::OY[j]) return false;
     return true;
+}
+
+// The resident run is offered when every tile fits on the chip at once (one
+// workgroup per tile, occupancy from the kernel's registers and LDS) and the
+// tiles take at least two steps between exchanges.  Failure to set it up only
+// leaves it unavailable.
+template <class Pat>
+void prepare_resident(FractalHost &F, const TileTables &TT)
+{
+    TileConfig *T = F.tile;
+    constexpr int NT = nt_of<Pat>();
+    if (T->ksteps < 2 || TT.bound.empty()) return;
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_life_tileR<Pat, NT>, NT, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, F.device) != hipSuccess || cus < 1)
+        return;
+    // The occupancy query counts waves per CU, but a workgroup's waves are dealt
+    // to the CU's four SIMDs, so one of them takes ceil(waves / 4): with the
+    // per-SIMD wave limit of the kernel's registers, that bounds the workgroups a
+    // CU holds at once.  A grid larger than what surely fits is never resident.
+    hipFuncAttributes fa;
+    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(k_life_tileR<Pat, NT>)) != hipSuccess) return;
+    {
+        const int vgprs = fa.numRegs > 0 ? (fa.numRegs + 7) / 8 * 8 : 512;
+        const int simd_waves = std::min(8, 512 / vgprs), wg_simd = (NT / 64 + 3) / 4;
+        per_cu = std::min(per_cu, simd_waves / wg_simd);
+    }
+    if ((uint64_t)per_cu * (uint64_t)cus < T->ntiles) return;
+    // Balance: a CU that receives more tiles than ceil(tiles / CUs) sets the time of
+    // every round, so reserve unused LDS per workgroup until no more than that many
+    // fit on a CU (the smallest such reservation, found with the occupancy query).
+    const int target = (int)((T->ntiles + (uint64_t)cus - 1) / (uint64_t)cus);
+    uint32_t pad = 0;
+    int lds_cu = 0;
+    if (per_cu > target &&
+        hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, F.device) == hipSuccess &&
+        (size_t)lds_cu / (size_t)target > fa.sharedSizeBytes) {
+        // occupancy(lo) > target; find the least hi with occupancy <= target
+        uint32_t lo = 0, hi = (uint32_t)((size_t)lds_cu / (size_t)target - fa.sharedSizeBytes);
+        int occ = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_life_tileR<Pat, NT>, NT, hi) == hipSuccess &&
+            occ <= target && occ >= 1) {
+            while (hi - lo > 256) {
+                const uint32_t mid = (lo + hi) / 2;
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_life_tileR<Pat, NT>, NT, mid) != hipSuccess)
+                    break;
+                (occ <= target ? hi : lo) = mid;
+            }
+            int lds_wg = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_life_tileR<Pat, NT>, NT, hi) == hipSuccess &&
+                occ == target &&
+                hipDeviceGetAttribute(&lds_wg, hipDeviceAttributeMaxSharedMemoryPerBlock, F.device) == hipSuccess &&
+                fa.sharedSizeBytes + hi <= (size_t)lds_wg)
+                pad = hi;
+        }
+        (void)hipGetLastError();
+    }
+    T->lds_pad = pad;
+    uint32_t *d_bound = nullptr, *d_bar = nullptr, *h_flag = nullptr;
+    hipError_t e = hipMalloc(&d_bound, TT.bound.size() * sizeof(uint32_t));
+    if (e == hipSuccess)
+        e = hipMemcpy(d_bound, TT.bound.data(), TT.bound.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&d_bar, bar_words(T->ntiles) * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipHostMalloc(&h_flag, sizeof(uint32_t), hipHostMallocMapped | hipHostMallocCoherent);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        if (d_bound) (void)hipFree(d_bound);
+        if (d_bar) (void)hipFree(d_bar);
+        return;
+    }
+    *h_flag = 0;
+    T->nbound = (uint32_t)TT.bound.size();
+    T->d_bound = d_bound;
+    T->d_bar = d_bar;
+    T->h_flag = h_flag;
+}
+
+template <class Pat>
+sqz_status launch_resident(const FractalHost &F, uint8_t *a, uint8_t *b, int steps, hipStream_t st)
+{
+    const TileConfig *T = F.tile;
+    if (__atomic_exchange_n(T->h_flag, 0u, __ATOMIC_ACQ_REL))
+        return set_error(SQZ_ERR_HIP, "a grid barrier of an earlier resident run timed out: its result is invalid");
+    constexpr int NT = nt_of<Pat>();
+    TileArgs A = tile_args(F);
+    ResidentArgs P;
+    P.a = a;
+    P.b = b;
+    P.steps = steps;
+    P.kstep = (int32_t)T->ksteps;
+    P.nbound = T->nbound;
+    P.bound = T->d_bound;
+    P.bar = T->d_bar;
+    P.flag = T->h_flag;
+    hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(256), 0, st, T->d_bar, bar_words(T->ntiles));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_error(e, "resident run: barrier reset");
+    // An ordinary launch: the occupancy check at set-up guarantees that the grid
+    // fits the chip at once, so on an otherwise idle device every workgroup is
+    // resident; a workgroup that waits for the chip to be shared with other work
+    // starts when that work ends, and the bounded barrier wait catches the rest.
+    hipLaunchKernelGGL((k_life_tileR<Pat, NT>), dim3((unsigned)T->ntiles), dim3(NT), SQZ_RESIDENT_PAD(T->lds_pad), st,
+                       A, P);
+    e = hipGetLastError();
+    return e == hipSuccess ? SQZ_OK : hip_error(e, "resident run launch");
 }
 
 template <class Pat>
@@ -171,7 +312,13 @@ sqz_status prepare(FractalHost &F)
         delete T;
         return hip_error(e, "tile table setup");
     }
+    T->nbound = 0;
+    T->lds_pad = 0;
+    T->d_bound = nullptr;
+    T->d_bar = nullptr;
+    T->h_flag = nullptr;
     F.tile = T;
+    prepare_resident<Pat>(F, TT);
     return SQZ_OK;
 }
 
@@ -235,6 +382,9 @@ void tile_release(FractalHost &F)
     (void)hipFree(F.tile->d_ringsrc);
     (void)hipFree(F.tile->d_ringhome);
     (void)hipFree(F.tile->d_coarse_tables);
+    if (F.tile->d_bound) (void)hipFree(F.tile->d_bound);
+    if (F.tile->d_bar) (void)hipFree(F.tile->d_bar);
+    if (F.tile->h_flag) (void)hipHostFree(F.tile->h_flag);
     delete F.tile;
     F.tile = nullptr;
 }
@@ -247,6 +397,23 @@ sqz_status launch_life_tile(const FractalHost &F, const uint8_t *in, uint8_t *ou
 }
 
 int tile_steps_per_launch(const FractalHost &F) { return F.tile ? (int)F.tile->ksteps : 0; }
+
+bool tile_resident(const FractalHost &F) { return F.tile && F.tile->d_bar; }
+
+sqz_status launch_life_tile_resident(const FractalHost &F, uint8_t *a, uint8_t *b, int steps, hipStream_t st)
+{
+    if (!tile_resident(F)) return set_error(SQZ_ERR_UNSUPPORTED, "the tiles of this fractal do not fit the chip at once");
+    if (((uintptr_t)a & 15) || ((uintptr_t)b & 15))
+        return set_error(SQZ_ERR_INVALID, "tiled kernel needs 16-byte aligned buffers");
+    if (steps < 1) return SQZ_OK;
+    switch (F.tile_kind) {
+    case kTriangle: return launch_resident<PatTriangle>(F, a, b, steps, st);
+    case kTriangleBig: return launch_resident<PatTriangleBig>(F, a, b, steps, st);
+    case kTrianglePaper: return launch_resident<PatTrianglePaper>(F, a, b, steps, st);
+    case kVicsek: return launch_resident<PatVicsek>(F, a, b, steps, st);
+    }
+    return set_error(SQZ_ERR_UNSUPPORTED, "no tiled kernel");
+}
 
 sqz_status launch_life_tile_steps(const FractalHost &F, const uint8_t *in, uint8_t *out, int steps, hipStream_t st)
 {

@@ -254,6 +254,12 @@ struct TileConfig {
     uint32_t *d_ringhome;  // [tstride] LDS word and bit of each ring cell
     MapParams Pc;          // maps at the coarse level r-M
     void *d_coarse_tables;
+    // resident run (all tiles on the chip at once), null / 0 when unavailable
+    uint32_t nbound;       // boundary cells per tile (exported at every exchange)
+    uint32_t lds_pad;      // LDS bytes reserved per workgroup so that at most ceil(tiles / CUs) share a CU
+    uint32_t *d_bound;     // [nbound] their tile-local indices
+    uint32_t *d_bar;       // {arrivals, timed out} of the grid barrier
+    uint32_t *h_flag;      // pinned host word: a barrier wait of an earlier run timed out
 };
 
 struct TileArgs {
@@ -462,7 +468,10 @@ __device__ __forceinline__ void load_nb(const TileArgs &A, NbRegs<Pat, NT> &R)
 
 // Phase C: one lane per level-J block.  Reads the block's word and the words
 // of its adjacent blocks from `src`, writes the block's new word to `dst`.
-template <class Pat, int NT>
+// Full: the tile has all TileLds<Pat>::NBMAX blocks (its level is the pattern's
+// largest), so every slot but the last is whole and runs without a branch,
+// which lets the compiler overlap one slot's LDS reads with another's logic.
+template <class Pat, int NT, bool Full = false>
 __device__ __forceinline__ void tile_blocks(const TileArgs &A, NbRegs<Pat, NT> &R, const uint32_t *src, uint32_t *dst)
 {
     R.keep_packed();
@@ -472,21 +481,56 @@ __device__ __forceinline__ void tile_blocks(const TileArgs &A, NbRegs<Pat, NT> &
     constexpr uint32_t CELLS = NC == 32 ? 0xFFFFFFFFu : ((1u << NC) - 1u);
     constexpr int NL = PL.nlayer;
     constexpr int NG = LDS::NGRP;
+    constexpr int NS = NbRegs<Pat, NT>::NSLOT;
+    auto update = [&](uint32_t x, const uint32_t(&w)[NG]) {
+        uint32_t L[NL];
 #pragma unroll
-    for (int s = 0; s < NbRegs<Pat, NT>::NSLOT; ++s) {
-        const uint32_t b = threadIdx.x + s * NT;
-        if (b < A.nblocks) {
-            const uint32_t x = src[b];
-            uint32_t w[NG];
+        for (int l = 0; l < NL; ++l) L[l] = 0;
+        apply_moves<Pat, NL>(x, L, std::make_index_sequence<PL.nterm>{});
+        apply_halo<Pat, NL, NG>(w, L, std::make_index_sequence<PL.nhterm>{});
+        return life_rule<NL>(x, L) & CELLS;
+    };
+    if constexpr (Full) {
+        // software pipeline: the words of slot s + 1 are read before slot s is
+        // updated and stored (lanes past the last block read block 0's words)
+        uint32_t xc, wc[NG];
+        {
+            const uint32_t b = (NT <= LDS::NBMAX || threadIdx.x < A.nblocks) ? threadIdx.x : 0u;
+            xc = src[b];
 #pragma unroll
             for (int g = 0; g < NG; ++g)
-                w[g] = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(src) + R.at(s, g));
-            uint32_t L[NL];
+                wc[g] = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(src) + R.at(0, g));
+        }
 #pragma unroll
-            for (int l = 0; l < NL; ++l) L[l] = 0;
-            apply_moves<Pat, NL>(x, L, std::make_index_sequence<PL.nterm>{});
-            apply_halo<Pat, NL, NG>(w, L, std::make_index_sequence<PL.nhterm>{});
-            dst[b] = life_rule<NL>(x, L) & CELLS;
+        for (int s = 0; s < NS; ++s) {
+            const uint32_t b = threadIdx.x + s * NT;
+            const uint32_t x = xc;
+            uint32_t w[NG];
+#pragma unroll
+            for (int g = 0; g < NG; ++g) w[g] = wc[g];
+            if (s + 1 < NS) {
+                const uint32_t bn = threadIdx.x + (s + 1) * NT;
+                xc = src[((s + 2) * NT <= LDS::NBMAX || bn < A.nblocks) ? bn : 0u];
+#pragma unroll
+                for (int g = 0; g < NG; ++g)
+                    wc[g] = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(src) +
+                                                                R.at(s + 1 < NS ? s + 1 : s, g));
+            }
+            const uint32_t v = update(x, w);
+            if ((s + 1) * NT <= LDS::NBMAX || b < A.nblocks) dst[b] = v;
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const uint32_t b = threadIdx.x + s * NT;
+            if (b < A.nblocks) {
+                const uint32_t x = src[b];
+                uint32_t w[NG];
+#pragma unroll
+                for (int g = 0; g < NG; ++g)
+                    w[g] = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(src) + R.at(s, g));
+                dst[b] = update(x, w);
+            }
         }
     }
 }
@@ -615,7 +659,7 @@ __device__ __forceinline__ void tile_body(const TileArgs &A, const uint8_t *__re
 // buffers rotate: round j reads buf[(j-1)%3], writes buf[j%3] and clears the
 // ring words of buf[(j+1)%3]; buf[2] first holds the packed bytes.  s_ring:
 // kRingTab words, 16-byte aligned.
-template <class Pat, int K, int NT = kBlock>
+template <class Pat, int K, int NT = kBlock, bool Full = false>
 __device__ __forceinline__ void tile_bodyK(const TileArgs &A, const uint8_t *__restrict__ in,
                                            uint8_t *__restrict__ out, uint64_t t, uint32_t *const buf[3],
                                            uint32_t *s_ring)
@@ -657,7 +701,7 @@ __device__ __forceinline__ void tile_bodyK(const TileArgs &A, const uint8_t *__r
     for (int j = 1; j <= K; ++j) {
         const uint32_t *src = buf[(j - 1) % 3];
         uint32_t *dst = buf[j % 3];
-        tile_blocks<Pat, NT>(A, R, src, dst);
+        tile_blocks<Pat, NT, Full>(A, R, src, dst);
         if (j < K) {
             uint32_t *clr = buf[(j + 1) % 3];
             if (tid < LDS::WORDS - LDS::VIRT) clr[LDS::VIRT + tid] = 0;
@@ -676,6 +720,188 @@ __device__ __forceinline__ void tile_bodyK(const TileArgs &A, const uint8_t *__r
     }
     tile_store<Pat, NT, true>(A, out, A0, o, W, buf[K % 3]);  // streaming: read next by another launch
     __syncthreads();
+}
+
+
+// ---------------------------------------------------------------------------
+// Resident run: the tiles stay in LDS for the whole run.
+//
+// When every tile of the fractal fits on the chip at once (one workgroup per
+// tile, all co-resident), the tile's state is loaded
+// from HBM once, advanced for all steps in LDS, and stored once.  Every
+// kstep steps the workgroups exchange only the cells other tiles hold as
+// ring cells: each tile writes the current states of its boundary cells
+// (`bound`, tile-local indices; the same for every tile) to their compact
+// positions in one of the two caller buffers, the grid meets at a barrier,
+// and each tile reads its ring cells from there, then advances kstep more
+// steps exactly as the multi-step launch does (tile_bodyK).  Exchange
+// buffers alternate between b and a, so a tile writing the exports of one
+// exchange never meets a tile still reading the previous one; the final
+// state goes to a (steps even) or b (odd) after one more barrier.
+// ---------------------------------------------------------------------------
+struct ResidentArgs {
+    uint8_t *a, *b;        // caller buffers; a holds the start
+    int32_t steps;         // Life steps of the run (>= 1)
+    int32_t kstep;         // steps between exchanges (2 .. ring depth)
+    uint32_t nbound;       // boundary cells per tile
+    const uint32_t *bound; // their tile-local indices
+    uint32_t *bar;         // device words of the grid barrier (bar_words(grid)), zero at launch
+    uint32_t *flag;        // host-visible word: set to 1 when a barrier wait timed out
+};
+
+// Polls of a barrier wait before it gives up (each poll is a device-scope load
+// and a short sleep, about a microsecond: seconds in all, far above any
+// legitimate wait of a co-resident grid).
+constexpr uint32_t kSpinLimit = 1u << 22;
+
+// Grid barrier of a launch whose workgroups are all on the chip at once.  The
+// cells the tiles exchange are written and read only with device-scope atomic
+// byte accesses (stores and loads that the eight XCDs' separate L2 caches pass
+// through to device-coherent memory), so no cache write-back or invalidation
+// is needed: each wave waits until its exchange stores have completed, the
+// workgroup meets, and one lane counts the arrival.  Counting is two-level, so
+// that no counter takes more than kBarGroup atomic additions per barrier: the
+// workgroups of a group of kBarGroup consecutive block indices add to their
+// group's counter (own 128-byte line), the last of a group to arrive adds to
+// the global counter, and every workgroup polls the global counter until all
+// groups have arrived.  Counts accumulate over the run (barrier i waits for
+// i arrivals per member).  The workgroup meets again before any lane reads
+// what others wrote.  The wait is bounded: after kSpinLimit polls, or as soon
+// as another workgroup has given up, the workgroup marks the run as timed out
+// (device word and host-visible flag) and goes on, so every wave reaches the
+// end of the kernel; such a run's results are invalid and the host reports it.
+constexpr uint32_t kBarGroup = 27;
+constexpr uint32_t kBarStride = 32;  // words between counters (128 bytes)
+
+__host__ __device__ constexpr uint32_t bar_words(uint64_t grid)
+{
+    return (uint32_t)((1 + (grid + kBarGroup - 1) / kBarGroup) * kBarStride);
+}
+
+__device__ __forceinline__ void grid_barrier(uint32_t *bar, uint32_t nbar, uint32_t *flag)
+{
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's exchange stores are complete
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t G = gridDim.x, g = blockIdx.x / kBarGroup, ng = (G + kBarGroup - 1) / kBarGroup;
+        const uint32_t gs = G - g * kBarGroup < kBarGroup ? G - g * kBarGroup : kBarGroup;
+        const uint32_t old =
+            __hip_atomic_fetch_add(bar + kBarStride * (1 + g), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (old + 1 == nbar * gs) __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t target = nbar * ng;
+        for (uint32_t spin = 0;; ++spin) {
+            const uint64_t v =
+                __hip_atomic_load(reinterpret_cast<uint64_t *>(bar), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((uint32_t)v >= target) break;
+            if ((v >> 32) != 0 || spin == kSpinLimit) {
+                __hip_atomic_store(bar + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+    __syncthreads();
+}
+
+// One tile for the whole run.  s_buf: three LDS buffers of TileLds<Pat>::WORDS
+// words, one after another; s_ring: kRingTab words (16-byte aligned); s_rs:
+// kMaxSteps + 1 words.  grid = number of tiles, all resident.
+template <class Pat, int NT>
+__device__ __forceinline__ void tile_bodyR(const TileArgs &A, const ResidentArgs &P, uint64_t t, uint32_t *s_buf,
+                                           uint32_t *s_ring, uint32_t *s_rs)
+{
+    using LDS = TileLds<Pat>;
+    constexpr uint32_t NC = PlanOf<Pat>::value.nc;
+    constexpr uint32_t WORDS = LDS::WORDS;
+    static_assert(kMaxRing <= NT, "one lane per ring cell");
+    const uint32_t tid = threadIdx.x;
+    const uint64_t S0 = t * A.tile;
+    const uint64_t A0 = S0 & ~31ull;
+    const uint32_t o = (uint32_t)(S0 - A0);
+    const uint32_t W = (o + A.tile + 31) / 32;
+
+    uint64_t gi = kHole64;
+    uint32_t home = 0;
+    if (tid < A.tstride) {
+        gi = A.tile_halo[t * A.tstride + tid];
+        home = A.ringhome[tid];
+    }
+    NbRegs<Pat, NT> R;
+    load_nb<Pat, NT>(A, R);
+    for (uint32_t i = tid; i < A.nsrc * 8; i += NT) s_ring[i] = A.ringsrc[i];
+    if (tid <= (uint32_t)kMaxSteps) s_rs[tid] = A.ring_start[tid];
+    tile_pack<NT>(A, P.a, A0, W, s_buf + 2 * WORDS);
+    if (tid < WORDS - LDS::ZERO) {
+        s_buf[LDS::ZERO + tid] = 0;
+        s_buf[WORDS + LDS::ZERO + tid] = 0;
+        s_buf[2 * WORDS + LDS::ZERO + tid] = 0;
+    }
+    const bool here = gi != kHole64;  // ring cell tid exists
+    uint32_t v = 0;
+    if (tid < kMaxRing) {
+        v = here ? (P.a[gi] & 1u) : 0u;
+        s_ring[kMaxRing * 8 + tid] = home;
+    }
+    __syncthreads();
+    tile_convert<Pat, NT>(A, o, s_buf + 2 * WORDS, s_buf);
+    if (v) atomicOr(lds_word(s_buf, home), 1u << (home & 31));
+    __syncthreads();
+
+    uint32_t cur = 0, nbar = 0;  // buffer holding the state; barriers passed
+    int32_t done = 0;
+    for (;;) {
+        const int32_t ks = P.steps - done < P.kstep ? P.steps - done : P.kstep;
+        for (int32_t j = 1; j <= ks; ++j) {
+            const uint32_t nx = cur == 2 ? 0 : cur + 1, cl = nx == 2 ? 0 : nx + 1;
+            const uint32_t *src = s_buf + cur * WORDS;
+            uint32_t *dst = s_buf + nx * WORDS;
+            if (A.nblocks == LDS::NBMAX)
+                tile_blocks<Pat, NT, true>(A, R, src, dst);
+            else
+                tile_blocks<Pat, NT>(A, R, src, dst);
+            if (j < ks) {
+                uint32_t *clr = s_buf + cl * WORDS;
+                if (tid < WORDS - LDS::VIRT) clr[LDS::VIRT + tid] = 0;
+                if (tid < s_rs[ks - j]) {
+                    const uint4 e0 = *reinterpret_cast<const uint4 *>(s_ring + tid * 8);
+                    const uint4 e1 = *reinterpret_cast<const uint4 *>(s_ring + tid * 8 + 4);
+                    const uint32_t cnt = lds_bit(src, e0.x) + lds_bit(src, e0.y) + lds_bit(src, e0.z) +
+                                         lds_bit(src, e0.w) + lds_bit(src, e1.x) + lds_bit(src, e1.y) +
+                                         lds_bit(src, e1.z) + lds_bit(src, e1.w);
+                    const uint32_t h = s_ring[kMaxRing * 8 + tid];
+                    const uint32_t self = lds_bit(src, h);
+                    if (here & ((cnt == 3) | (self & (cnt == 2)))) atomicOr(lds_word(dst, h), 1u << (h & 31));
+                }
+            }
+            __syncthreads();
+            cur = nx;
+        }
+        done += ks;
+        if (done >= P.steps) break;
+        // exchange: boundary cells out, ring cells in
+        uint8_t *xb = (nbar & 1) ? P.a : P.b;
+        const uint32_t *st = s_buf + cur * WORDS;
+        for (uint32_t i = tid; i < P.nbound; i += NT) {
+            const uint32_t z = P.bound[i];
+            __hip_atomic_store(xb + S0 + z, (uint8_t)((st[z / NC] >> (z % NC)) & 1u), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (tid < WORDS - LDS::VIRT) {
+            s_buf[LDS::VIRT + tid] = 0;
+            s_buf[WORDS + LDS::VIRT + tid] = 0;
+            s_buf[2 * WORDS + LDS::VIRT + tid] = 0;
+        }
+        ++nbar;
+        grid_barrier(P.bar, nbar, P.flag);
+        v = 0;
+        if (tid < kMaxRing) v = here ? (__hip_atomic_load(xb + gi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1u) : 0u;
+        if (v) atomicOr(lds_word(s_buf + cur * WORDS, home), 1u << (home & 31));
+        __syncthreads();
+    }
+    ++nbar;
+    grid_barrier(P.bar, nbar, P.flag);  // every tile has read its last ring cells
+    tile_store<Pat, NT, true>(A, (P.steps & 1) ? P.b : P.a, A0, o, W, s_buf + cur * WORDS);
 }
 
 }  // namespace sqz

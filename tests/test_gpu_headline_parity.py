@@ -1,12 +1,15 @@
-"""Oracle parity of the kernel behind the headline figures: the bit-sliced
-level-10 triangle tiles with ten steps per launch, which sqz_compact_run
-launches from level 16 up (Section "Moving from Thread-level to Block-level";
-the Life workload of Section "Experimental Setup and Results").
+"""Oracle parity of the kernels behind the headline figures: the bit-sliced
+level-10 triangle tiles that sqz_compact_run uses from level 16 up (Section
+"Moving from Thread-level to Block-level"; the Life workload of Section
+"Experimental Setup and Results"), in both run forms: the resident run (one
+launch, all 729 tiles of the level-16 triangle held in LDS at once, ring
+cells exchanged every ten steps; the default at level 16) and launches of ten
+steps (the form of every larger level).
 
 * Level 16, seed 2201, Bernoulli(0.5): all 43,046,721 cells after 20 steps
-  (two ten-step launches) and after 100 steps (ten launches) against the
-  oracle's neighbour-table steps, and the bounding-box grid after the same
-  steps gathered through the oracle's replication order.
+  and after 100 steps, in each run form, against the oracle's neighbour-table
+  steps, and the bounding-box grid after the same steps gathered through the
+  oracle's replication order.
 * Level 20, seed 2201, Bernoulli(0.3), 20 steps: more than a million cells
   against the oracle's window light cones, more than half of them within
   distance 10 of their tile's box edge (where the ring cells that a
@@ -21,26 +24,42 @@ from gpu_common import gpu_fractal, mismatch, oracle_fractal, to_np, torch_or_sk
 pytestmark = pytest.mark.gpu
 
 
-def test_r16_full_array_20_and_100_steps():
+_R16 = {}
+
+
+def r16_oracle():
+    """The oracle's level-16 start (seed 2201, Bernoulli(0.5)) and its states after 20
+    and 100 steps, computed once per session."""
+    if not _R16:
+        O = oracle_fractal("triangle", 16)
+        start = O.fill_compact(2201, 0.5)
+        print("r16: oracle neighbour table", flush=True)
+        nb = O.neighbour_table()
+        _R16[0] = start
+        _R16[20] = O.life_steps(start, 20, nb)
+        _R16[100] = O.life_steps(_R16[20], 80, nb)
+        del nb
+    return _R16
+
+
+@pytest.mark.parametrize("form", ["resident", "launches"])
+def test_r16_full_array_20_and_100_steps(form):
     torch = torch_or_skip()
     F, O = gpu_fractal("triangle", 16), oracle_fractal("triangle", 16)
-    assert F.tile_level == 10 and F.run_steps_per_launch == 10
+    assert F.tile_level == 10 and F.run_steps_per_launch == 10 and F.resident_run
     seed, p = 2201, 0.5
-    start = O.fill_compact(seed, p)
+    want = r16_oracle()
     a = F.fill_bernoulli(seed, p)
-    mismatch(to_np(a), start, "fill r=16")
-    print("r16: oracle neighbour table", flush=True)
-    nb = O.neighbour_table()
-    want = {20: O.life_steps(start, 20, nb)}
-    want[100] = O.life_steps(want[20], 80, nb)
-    del nb
+    mismatch(to_np(a), want[0], "fill r=16")
     for steps in (20, 100):
-        print(f"r16: {steps} steps, full array", flush=True)
+        print(f"r16: {steps} steps, full array, {form}", flush=True)
         x, y = a.clone(), torch.empty_like(a)
-        res = F.compact_run(x, y, steps)
+        res = F.compact_run(x, y, steps, form=form)
         assert res is x  # even step count: result in the first buffer
-        mismatch(to_np(res), want[steps], f"r16 {steps} steps (ten-step launches)")
+        mismatch(to_np(res), want[steps], f"r16 {steps} steps ({form})")
         del x, y, res
+    if form != "launches":
+        return
     # the bounding-box kernel over the same steps, gathered through the oracle's order
     order = torch.from_numpy(O.order().astype(np.int64)).cuda()
     gidx = order[:, 1] * F.n + order[:, 0]

@@ -1,7 +1,8 @@
-"""GPU parity of the multi-step tiled kernels (up to ten Life steps per launch,
-used by sqz_compact_run): every step count, every tiled pattern, bit-exact
-against one-step launches and the oracle, with the result in the documented
-buffer."""
+"""GPU parity of the multi-step tiled kernels used by sqz_compact_run, in both
+run forms: "launches" (up to ten Life steps per launch) and "resident" (one
+launch, tiles held in LDS, ring cells exchanged every ten steps).
+Every step count, every tiled pattern, bit-exact against one-step launches and
+the oracle, with the result in the documented buffer."""
 import numpy as np
 import pytest
 
@@ -14,11 +15,16 @@ CASES = [("triangle", 3), ("triangle", 5), ("triangle", 8), ("triangle", 9), ("t
          ("vicsek", 8)]
 
 
+FORMS = ["launches", "resident"]
+
+
+@pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("name,r", CASES)
-def test_run_equals_single_steps_and_oracle(name, r):
+def test_run_equals_single_steps_and_oracle(name, r, form):
     torch = torch_or_skip()
     F, O = gpu_fractal(name, r), oracle_fractal(name, r)
     assert F.has_tile
+    assert F.resident_run  # at most 3^3 level-8 tiles here: all fit on the chip
     # ring slots exist even for a single tile (all absent); ring cells must lie in the
     # adjacent tiles, so a launch takes fewer than s^M steps
     assert F.run_steps_per_launch == min(10, F.s ** F.tile_level - 1)
@@ -27,33 +33,35 @@ def test_run_equals_single_steps_and_oracle(name, r):
     for steps in range(0, 23):
         a = F.fill_bernoulli(2201, 0.5)
         b = torch.zeros_like(a)
-        res = F.compact_run(a, b, steps)
+        res = F.compact_run(a, b, steps, form=form)
         assert res is (a if steps % 2 == 0 else b)
         x, y = F.fill_bernoulli(2201, 0.5), torch.empty_like(a)
         for _ in range(steps):
             F.compact_step(x, y, impl="tile")
             x, y = y, x
-        assert torch.equal(res, x), (name, r, steps)
+        assert torch.equal(res, x), (name, r, form, steps)
         if nb is not None and steps in (2, 3, 4, 7, 10, 12, 15, 21):
             mismatch(to_np(res), O.life_steps(start, steps, nb), f"{name} r={r} {steps} steps")
 
 
+@pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("steps", [2, 3, 4, 5, 6, 7, 8, 9, 10, 14, 20])
-def test_all_alive_multi_step(steps):
+def test_all_alive_multi_step(steps, form):
     """All cells alive at t = 0: ring cells change state in the first step, so later
     steps depend on their recomputed states."""
     torch = torch_or_skip()
     F, O = gpu_fractal("triangle", 10), oracle_fractal("triangle", 10)
     a = torch.ones(F.cells, dtype=torch.uint8, device="cuda")
-    res = F.compact_run(a, torch.empty_like(a), steps)
-    mismatch(to_np(res), O.life_steps(np.ones(F.cells, np.uint8), steps), f"all alive, {steps} steps")
+    res = F.compact_run(a, torch.empty_like(a), steps, form=form)
+    mismatch(to_np(res), O.life_steps(np.ones(F.cells, np.uint8), steps), f"all alive, {steps} steps ({form})")
 
 
-def test_r16_run_equals_single_steps():
+@pytest.mark.parametrize("form", FORMS)
+def test_r16_run_equals_single_steps(form):
     torch = torch_or_skip()
     F = gpu_fractal("triangle", 16)
     a = F.fill_bernoulli(9, 0.5)
-    r1 = F.compact_run(a.clone(), torch.empty_like(a), 20)
+    r1 = F.compact_run(a.clone(), torch.empty_like(a), 20, form=form)
     x, y = a.clone(), torch.empty_like(a)
     for _ in range(20):
         F.compact_step(x, y, impl="tile")
@@ -72,12 +80,15 @@ def test_large_triangle_tiles_equal_thread_level(r):
     torch = torch_or_skip()
     F = gpu_fractal("triangle", r)
     assert F.tile_level == (10 if r >= 16 else 8) and F.run_steps_per_launch == 10
+    assert F.resident_run == (r == 16)  # 729 level-10 tiles fit the chip; 2,187 tiles do not
     a = F.fill_bernoulli(31, 0.4)
-    r1 = F.compact_run(a.clone(), torch.empty_like(a), 13)
     x, y = a.clone(), torch.empty_like(a)
     for _ in range(13):
         F.compact_step(x, y, impl="cell")
         x, y = y, x
-    assert torch.equal(r1, x)
-    del a, r1, x, y
+    for form in ["launches"] + (["resident"] if F.resident_run else []):
+        r1 = F.compact_run(a.clone(), torch.empty_like(a), 13, form=form)
+        assert torch.equal(r1, x), form
+        del r1
+    del a, x, y
     torch.cuda.empty_cache()
