@@ -347,6 +347,22 @@ SQZ_API sqz_status sqz_diffuse_run(const sqz_fractal *f, const sqz_diffusion *d,
 SQZ_API sqz_status sqz_mass_f64(const sqz_fractal *f, sqz_dtype dtype, const void *d_u, double offset,
                                 double *d_work, void *stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the sum of
+ * sqz_mass_f64, bit-identical to it, with no workspace argument.  Its kMassGrid
+ * = 1024 partial sums (8 KiB) live in a static device array of the library,
+ * one per GPU, held until the process ends; the call allocates nothing (no
+ * hipMalloc, hipFree or allocating library routine).  The scratch size does
+ * not depend on N, so no fractal is too large for it.  d_out: one double on
+ * the device, receives the sum.  Every call on a GPU shares that GPU's
+ * scratch: calls that overlap on one GPU (streams not ordered with each other)
+ * race and may return wrong sums.  NULL or overlapping buffers, or an unknown
+ * dtype: SQZ_ERR_INVALID.
+ */
+SQZ_API sqz_status sqz_mass_f64_noalloc(const sqz_fractal *f, sqz_dtype dtype, const void *d_u, double offset,
+                                        double *d_out, void *stream);
+
 /* bfloat16 storage conversion: d_b[c] = bf16_nearest_even(d_u[c] - offset).
  * d_u: N floats, d_b: N uint16; NULL or overlapping buffers: SQZ_ERR_INVALID. */
 SQZ_API sqz_status sqz_bf16_encode(const sqz_fractal *f, const float *d_u, float offset, uint16_t *d_b,

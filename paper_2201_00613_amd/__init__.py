@@ -272,6 +272,16 @@ class Fractal:
             check(lib().sqz_mass_f64(self._h, DTYPES[dtype], _ptr(u), offset, _ptr(work), st))
         return work[0]
 
+    def mass_f64_noalloc(self, u, out, dtype: str = "f32", offset: float = 0.0):
+        """mass_f64 with the partial sums in the library's static scratch (sqz_mass_f64_noalloc);
+        `out`: a one-element float64 device tensor, receives the sum."""
+        torch, dev, st = self._ctx()
+        self._need(u, self._field_dtype(dtype), self.cells, "u")
+        self._need(out, torch.float64, 1, "out")
+        with dev:
+            check(lib().sqz_mass_f64_noalloc(self._h, DTYPES[dtype], _ptr(u), offset, _ptr(out), st))
+        return out[0]
+
     def bf16_encode(self, u, offset: float, out=None):
         torch, dev, st = self._ctx()
         self._need(u, torch.float32, self.cells, "u")

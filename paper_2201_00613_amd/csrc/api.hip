@@ -494,6 +494,18 @@ sqz_status sqz_mass_f64(const sqz_fractal *f, sqz_dtype dtype, const void *d_u, 
     return launch_mass(f->h, dtype, d_u, offset, d_work, (hipStream_t)stream);
 }
 
+sqz_status sqz_mass_f64_noalloc(const sqz_fractal *f, sqz_dtype dtype, const void *d_u, double offset, double *d_out,
+                                void *stream)
+{
+    sqz_status st = check_handle(f);
+    if (st != SQZ_OK) return st;
+    if (dtype != SQZ_F32 && dtype != SQZ_BF16) return set_error(SQZ_ERR_INVALID, "unknown dtype %d", (int)dtype);
+    if (!d_u || !d_out) return set_error(SQZ_ERR_INVALID, "NULL buffer");
+    if (ranges_overlap(d_u, f->h.N * dtype_size(dtype), d_out, sizeof(double)))
+        return set_error(SQZ_ERR_INVALID, "d_u and d_out overlap");
+    return launch_mass_noalloc(f->h, dtype, d_u, offset, d_out, (hipStream_t)stream);
+}
+
 sqz_status sqz_bf16_encode(const sqz_fractal *f, const float *d_u, float offset, uint16_t *d_b, void *stream)
 {
     sqz_status st = check_handle(f);

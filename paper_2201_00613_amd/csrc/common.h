@@ -183,6 +183,9 @@ sqz_status launch_life_xtile(const FractalHost &F, const uint8_t *in, uint8_t *o
 sqz_status launch_diffuse(const FractalHost &F, int dtype, float coef, int rounding, uint64_t seed, uint64_t step,
                           const void *in, void *out, int use_tile, hipStream_t st);
 sqz_status launch_mass(const FractalHost &F, int dtype, const void *u, double offset, double *work, hipStream_t st);
+// the same sum with the partials in the library's static scratch; *result = the sum
+sqz_status launch_mass_noalloc(const FractalHost &F, int dtype, const void *u, double offset, double *result,
+                               hipStream_t st);
 sqz_status launch_bf16_convert(const FractalHost &F, int encode, const float *u, float offset, uint16_t *b,
                                hipStream_t st);
 int mass_grid();

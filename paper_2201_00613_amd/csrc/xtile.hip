@@ -3,6 +3,7 @@
 // diffusion, binary64 mass and bfloat16 conversion kernels.
 #include <string.h>
 
+#include <mutex>
 #include <vector>
 
 #include "xtile_device.h"
@@ -459,6 +460,43 @@ sqz_status launch_mass(const FractalHost &F, int dtype, const void *u, double of
 {
     return mass_launches(F, dtype, u, offset, work + 1, work, st);
 }
+
+// Partial sums of the allocation-free mass (sqz_mass_f64_noalloc): kMassGrid
+// doubles, whatever the fractal's size.  Each GPU the library runs on holds
+// its own copy until the process ends.  In host code `scratch` names a
+// host-side stand-in, not device memory: kernels get the address that
+// hipGetSymbolAddress returns for the current device, looked up on the first
+// call on each device and kept in scratch_dev.
+static __device__ __align__(256) double scratch[kMassGrid];
+
+constexpr int kMaxDevices = 64;
+static double *scratch_dev[kMaxDevices];
+static std::mutex scratch_mu;
+
+sqz_status launch_mass_noalloc(const FractalHost &F, int dtype, const void *u, double offset, double *result,
+                               hipStream_t st)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_error(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return set_error(SQZ_ERR_UNSUPPORTED, "device %d >= %d", dev, kMaxDevices);
+    double *part = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(scratch_mu);
+        if (!scratch_dev[dev]) {
+            void *p = nullptr;
+            e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !p) return hip_error(e != hipSuccess ? e : hipErrorInvalidSymbol, "scratch address");
+            scratch_dev[dev] = static_cast<double *>(p);
+        }
+        part = scratch_dev[dev];
+    }
+    const uintptr_t r = (uintptr_t)result, p0 = (uintptr_t)part;
+    if (r < p0 + kMassGrid * sizeof(double) && p0 < r + sizeof(double))
+        return set_error(SQZ_ERR_INVALID, "d_out lies in the library's scratch");
+    return mass_launches(F, dtype, u, offset, part, result, st);
+}
+
 
 sqz_status launch_bf16_convert(const FractalHost &F, int encode, const float *u, float offset, uint16_t *b,
                                hipStream_t st)
