@@ -3,11 +3,19 @@
 Workload (N=1): level-16 Sierpinski triangle, replicas (0,0),(1,0),(0,1),
 43,046,721 compact cells, uint8 states from a Bernoulli(0.5) SplitMix64 start
 (seed 2201), B3/S23 steps ping-ponging between two compact buffers.  One
-"step" is one B3/S23 update of every cell; sqz_compact_run advances up to ten
-steps per kernel launch (temporal blocking), so K timed steps are fewer
-launches.  The same steps on the 65536 x 65536 bounding-box grid give the
-speedup; the level-20 triangle (3.49e9 cells, 20 steps, Bernoulli(0.3)) gives
-the largest workload.
+"step" is one B3/S23 update of every cell.  The K timed steps are one
+sqz_compact_run call: at level 16 its default run form is one launch that
+holds all 729 tiles in LDS for all K steps (exchanging ring cells every ten
+steps); the launches form (ten steps per launch) is timed beside it.  The
+same steps on the 65536 x 65536 bounding-box grid give the speedup; the
+level-20 triangle (3.49e9 cells, 20 steps, Bernoulli(0.3)) gives the largest
+workload.
+
+Roofline: the tiled Life kernels are bound by vector-ALU issue, so `roofline`
+reports counter-measured VALU wave-instructions per dispatch (from the
+committed rocprofv3 summary of the same kernel source and dispatch size) over
+the live dispatch time, against the chip's peak of two wave64 instructions per
+CU per clock; HBM bytes are secondary fields.
 
 Prints one JSON line.  Inputs are resident in HBM before timing starts.
 """
@@ -348,6 +356,30 @@ def carpet_life_leg(torch, sqz, steps: int) -> dict:
     return res
 
 
+GOLDEN_C5 = os.path.join(ROOT, "tests", "golden", "carpet_r9_diffusion.npz")
+
+
+def golden_error(torch, F, field, dtype: str, offset: float, steps: int):
+    """Error of the level-9 carpet diffusion after `steps` steps against the stored
+    binary64 values (tests/golden/carpet_r9_diffusion.npz, written from the CPU
+    oracle): max |u - u64| over the stored cells over the binary64 field's infinity
+    norm.  None when no stored checkpoint has this step count."""
+    import numpy as np
+
+    if not os.path.exists(GOLDEN_C5):
+        return None
+    g = np.load(GOLDEN_C5, allow_pickle=False)
+    hit = [i for i, t in enumerate(g["steps"]) if int(t) == steps]
+    if not hit or int(g["level"]) != F.r or abs(float(g["coef"]) - 0.1) > 1e-12 or int(g["seed"]) != 2201:
+        return None
+    i = hit[0]
+    u = field if dtype == "f32" else F.bf16_decode(field, offset)
+    got = u[torch.from_numpy(g["idx"]).cuda()].double().cpu().numpy()
+    return {"t": steps, "cells": int(g["idx"].size),
+            "value": float(np.max(np.abs(got - g["values"][i])) / g["inf_norm"][i]),
+            "bar": 1e-5 if dtype == "f32" else 2e-2}
+
+
 def diffusion_leg(torch, sqz, steps: int) -> dict:
     """Carpet r=9 (134,217,728 cells), coef 0.1, U(0,1) start: binary32 and bfloat16
     (offset storage, stochastic rounding) for `steps` steps; binary64 mass drift."""
@@ -383,6 +415,9 @@ def diffusion_leg(torch, sqz, steps: int) -> dict:
                       "algorithmic_gbs": nbytes * F.cells * steps / sec / 1e9,
                       "hbm_frac": nbytes * F.cells * steps / sec / 1e9 / HBM_PEAK_GBS,
                       "mass_rel_drift": (m1 - m0) / m0}
+        err = golden_error(torch, F, r, dtype, offset, steps)
+        if err is not None:
+            res[dtype]["rel_error_vs_binary64"] = err
         del a, b, r
     del u, F
     torch.cuda.empty_cache()
@@ -419,6 +454,7 @@ def main() -> int:
     ap.add_argument("--cpu-max-steps", type=int, default=8)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only time a plain device copy of this many bytes (counter calibration)")
+    ap.add_argument("--p", type=float, default=None, help="Bernoulli start density of --profile-run (default 0.5)")
     ap.add_argument("--profile-run", type=int, default=0,
                     help="only run the headline workload: one untimed and three timed runs of this many steps in "
                          "--form (every dispatch of a profiled kernel then has the same size)")
@@ -445,9 +481,10 @@ def main() -> int:
     F = sqz.Fractal(*TRIANGLE, r)
     form = args.form
     if args.profile_run:
-        sec = [compact_run(torch, F, seed, p, args.profile_run, args.profile_run, form=form)]
-        sec += [compact_run(torch, F, seed, p, args.profile_run, 0, form=form) for _ in range(2)]
-        print(json.dumps({"profile_run": args.profile_run, "form": form, "level": r,
+        pp = args.p if args.p is not None else p
+        sec = [compact_run(torch, F, seed, pp, args.profile_run, args.profile_run, form=form)]
+        sec += [compact_run(torch, F, seed, pp, args.profile_run, 0, form=form) for _ in range(2)]
+        print(json.dumps({"profile_run": args.profile_run, "form": form, "level": r, "bernoulli_p": pp,
                           "ms_per_step": [x * 1e3 / args.profile_run for x in sec]}), flush=True)
         return 0
     if args.impl != "auto":
@@ -541,6 +578,10 @@ def main() -> int:
                       "algorithmic_gbs_per_launch": gbs20, "hbm_frac": gbs20 / HBM_PEAK_GBS,
                       "step_equivalent_gbs": BYTES_PER_UPDATE * F20.cells * args.r20_steps / s20 / 1e9,
                       "bernoulli_p": 0.3}
+        r20_alu = alu_roofline(profiled_counters("k_life_tileK_triangle_r20.md", "sierpinski-triangle-r20-life-b3s23"),
+                               args.r20_steps, s20, l20, F20.cells, "k_life_tileK_triangle_r20.md")
+        if r20_alu:
+            out["r20"]["roofline"] = r20_alu
         log(f"[bench] r=20: {ms20:.3f} ms/step, {l20} launches, {gbs20:.1f} GB/s per launch "
             f"({100 * gbs20 / HBM_PEAK_GBS:.1f}% of HBM peak)")
         del F20
