@@ -38,6 +38,9 @@ struct sqz_fractal;  // api.hip
 namespace sqz {
 
 enum BatchKind : uint32_t { kBTri = 1, kBTriPaper = 2, kBVicsek = 3, kBX68 = 4, kBX84 = 5, kBXAny = 6, kBCell = 7, kBBits = 8 };
+#ifndef SQZ_BATCH_INTERLEAVE  // 1: tiled launches take the pattern kinds evenly interleaved
+#define SQZ_BATCH_INTERLEAVE 1
+#endif
 
 constexpr uint32_t kCellUnit = 4096;
 
@@ -565,6 +568,32 @@ sqz_status batch_create(const sqz_fractal *const *fr, int32_t count, BatchHost *
     }
     cell_start[count] = cstart;
     H->offsets[count] = off;
+    // The tiled launch forms take the instances in an order that spreads every
+    // pattern kind evenly over the launch (each instance keyed by the middle
+    // of its share of its kind's cells), so that the workgroups on the chip at
+    // any time mix tile bodies that load different units (vector ALU, LDS,
+    // memory); instances of one kind keep their relative order.
+    if (SQZ_BATCH_INTERLEAVE) {
+        std::map<uint32_t, uint64_t> kind_total, kind_seen;
+        for (const TiledInst &T : H->tiled) kind_total[T.kind] += T.units * T.unit_cells;
+        std::vector<std::pair<double, size_t>> key(H->tiled.size());
+        for (size_t q = 0; q < H->tiled.size(); ++q) {
+            const TiledInst &T = H->tiled[q];
+            const uint64_t c = T.units * T.unit_cells;
+            key[q] = {(kind_seen[T.kind] + 0.5 * (double)c) / (double)kind_total[T.kind], q};
+            kind_seen[T.kind] += c;
+        }
+        std::stable_sort(key.begin(), key.end());
+        std::vector<TiledInst> ord;
+        ord.reserve(H->tiled.size());
+        for (const auto &k : key) ord.push_back(H->tiled[k.second]);
+        H->tiled.swap(ord);
+        H->tcost_total = 0;
+        for (TiledInst &T : H->tiled) {
+            T.cost_start = H->tcost_total;
+            H->tcost_total += T.units * T.unit_cells;
+        }
+    }
     H->total_cells = cstart;
     H->total_bytes = off;
     H->lds = std::max<size_t>(lds, 16);
