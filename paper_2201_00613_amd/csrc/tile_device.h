@@ -128,6 +128,35 @@ constexpr int local_nu(int x, int y)
     return c;
 }
 
+// Layer colouring of the in-block moves: every distinct shift (source bit
+// index minus target bit index) gets one layer, such that two shifts that
+// reach a common target bit get different layers (graph colouring by
+// backtracking, at most 8 layers).  Then each shift is a single move term
+// whose mask holds all its target bits.  Returns the number of layers, 0 if
+// no colouring with at most 8 layers exists.
+struct ShiftColouring {
+    int nsh;
+    int sh[64];
+    bool conf[64][64];
+    int col[64];
+};
+
+constexpr bool colour_from(ShiftColouring &c, const int (&order)[64], int idx, int k)
+{
+    if (idx == c.nsh) return true;
+    const int a = order[idx];
+    for (int col = 0; col < k; ++col) {
+        bool ok = true;
+        for (int b = 0; b < c.nsh && ok; ++b)
+            if (c.conf[a][b] && c.col[b] == col) ok = false;
+        if (!ok) continue;
+        c.col[a] = col;
+        if (colour_from(c, order, idx + 1, k)) return true;
+        c.col[a] = -1;
+    }
+    return false;
+}
+
 template <class Pat>
 constexpr BlockPlan derive_plan()
 {
@@ -151,6 +180,51 @@ constexpr BlockPlan derive_plan()
         p.lx[i] = x;
         p.ly[i] = y;
     }
+    // in-block shifts and their conflicts (two shifts reaching one target bit)
+    ShiftColouring c{};
+    int tshift[32][8] = {};
+    int ntshift[32] = {};
+    for (int i = 0; i < p.nc; ++i)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                if (!dx && !dy) continue;
+                const int qx = p.lx[i] + dx, qy = p.ly[i] + dy;
+                if (qx < 0 || qy < 0 || qx >= p.box || qy >= p.box) continue;
+                const int j = local_nu<Pat>(qx, qy);
+                if (j < 0) continue;
+                int a = -1;
+                for (int q = 0; q < c.nsh; ++q)
+                    if (c.sh[q] == j - i) a = q;
+                if (a < 0) {
+                    a = c.nsh++;
+                    c.sh[a] = j - i;
+                }
+                tshift[i][ntshift[i]++] = a;
+            }
+    for (int i = 0; i < p.nc; ++i)
+        for (int u = 0; u < ntshift[i]; ++u)
+            for (int w = 0; w < ntshift[i]; ++w)
+                if (u != w) c.conf[tshift[i][u]][tshift[i][w]] = true;
+    int order[64] = {};
+    int degc[64] = {};
+    for (int a = 0; a < c.nsh; ++a) {
+        order[a] = a;
+        c.col[a] = -1;
+        for (int b = 0; b < c.nsh; ++b) degc[a] += c.conf[a][b] ? 1 : 0;
+    }
+    for (int u = 1; u < c.nsh; ++u)  // most-constrained shift first
+        for (int w = u; w > 0 && degc[order[w]] > degc[order[w - 1]]; --w) {
+            const int t = order[w];
+            order[w] = order[w - 1];
+            order[w - 1] = t;
+        }
+    int maxdeg = 0;
+    for (int i = 0; i < p.nc; ++i) maxdeg = ntshift[i] > maxdeg ? ntshift[i] : maxdeg;
+    bool coloured = false;
+    for (int k = maxdeg < 1 ? 1 : maxdeg; k <= 8 && !coloured; ++k) {
+        for (int a = 0; a < c.nsh; ++a) c.col[a] = -1;
+        coloured = colour_from(c, order, 0, k);
+    }
     for (int i = 0; i < p.nc; ++i) {
         bool used[8] = {};
         int nused = 0;
@@ -165,18 +239,33 @@ constexpr BlockPlan derive_plan()
                     if (j < 0) continue;
                     const int shift = j - i;  // source bit j -> target bit i
                     int layer = -1;
-                    for (int t = 0; t < p.nterm && layer < 0; ++t)
-                        if (p.t_shift[t] == shift && !used[p.t_layer[t]]) {
-                            layer = p.t_layer[t];
-                            p.t_mask[t] |= 1u << i;
+                    if (coloured) {  // the shift's own layer and term
+                        for (int a = 0; a < c.nsh; ++a)
+                            if (c.sh[a] == shift) layer = c.col[a];
+                        int t = -1;
+                        for (int q = 0; q < p.nterm; ++q)
+                            if (p.t_shift[q] == shift) t = q;
+                        if (t < 0) {
+                            t = p.nterm++;
+                            p.t_layer[t] = layer;
+                            p.t_shift[t] = shift;
+                            p.t_mask[t] = 0;
                         }
-                    if (layer < 0) {
-                        for (int l = 0; l < 8 && layer < 0; ++l)
-                            if (!used[l]) layer = l;
-                        p.t_layer[p.nterm] = layer;
-                        p.t_shift[p.nterm] = shift;
-                        p.t_mask[p.nterm] = 1u << i;
-                        ++p.nterm;
+                        p.t_mask[t] |= 1u << i;
+                    } else {  // greedy: a term of this shift whose layer is free for bit i
+                        for (int t = 0; t < p.nterm && layer < 0; ++t)
+                            if (p.t_shift[t] == shift && !used[p.t_layer[t]]) {
+                                layer = p.t_layer[t];
+                                p.t_mask[t] |= 1u << i;
+                            }
+                        if (layer < 0) {
+                            for (int l = 0; l < 8 && layer < 0; ++l)
+                                if (!used[l]) layer = l;
+                            p.t_layer[p.nterm] = layer;
+                            p.t_shift[p.nterm] = shift;
+                            p.t_mask[p.nterm] = 1u << i;
+                            ++p.nterm;
+                        }
                     }
                     used[layer] = true;
                     ++nused;
@@ -205,6 +294,10 @@ constexpr BlockPlan derive_plan()
             int layer = -1;
             for (int l = 0; l < 8 && layer < 0; ++l)
                 if (!used[l]) layer = l;
+            if (layer < 0) {
+                p.ok = false;
+                return p;
+            }
             used[layer] = true;
             ++nused;
             p.ht_layer[p.nhterm] = layer;
@@ -212,6 +305,8 @@ constexpr BlockPlan derive_plan()
             p.ht_bit[p.nhterm] = i;
             ++p.nhterm;
         }
+        for (int l = 0; l < 8; ++l)
+            if (used[l] && l + 1 > p.nlayer) p.nlayer = l + 1;
         if (nused > p.nlayer) p.nlayer = nused;
     }
     for (int h = 0; h < p.nhalo; ++h) {
