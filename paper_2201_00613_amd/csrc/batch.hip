@@ -38,6 +38,9 @@ struct sqz_fractal;  // api.hip
 namespace sqz {
 
 enum BatchKind : uint32_t { kBTri = 1, kBTriPaper = 2, kBVicsek = 3, kBX68 = 4, kBX84 = 5, kBXAny = 6, kBCell = 7, kBBits = 8 };
+#ifndef SQZ_BATCH_TILE_MAP  // 1: the workgroup-per-tile launch interleaves the kinds tile by tile
+#define SQZ_BATCH_TILE_MAP 1
+#endif
 #ifndef SQZ_BATCH_INTERLEAVE  // 1: tiled launches take the pattern kinds evenly interleaved
 #define SQZ_BATCH_INTERLEAVE 1
 #endif
@@ -245,6 +248,7 @@ struct TiledArgs {
     const TiledInst *inst;
     const uint64_t *cost_start;  // ninst + 1 entries
     const uint64_t *tile_start;  // ninst + 1 prefix sums of tile counts
+    const uint32_t *tile_map;    // workgroup-per-tile form: instance << 20 | tile, one entry per tile (or null)
     uint32_t ninst;
     uint64_t total_cost;
 };
@@ -318,6 +322,11 @@ k_batch_tiles(TiledArgs B, const uint8_t *__restrict__ in, uint8_t *__restrict__
     extern __shared__ __align__(16) unsigned char smem[];
     if constexpr (PerTile) {
         const uint64_t b = xcd_remap(blockIdx.x, gridDim.x);
+        if (B.tile_map) {
+            const uint32_t v = B.tile_map[b];
+            tiled_run<K>(B.inst[v >> 20], in, out, v & 0xFFFFFu, smem);
+            return;
+        }
         uint32_t a = 0, e = B.ninst;
         while (e - a > 1) {
             const uint32_t m = (a + e) / 2;
@@ -381,6 +390,7 @@ struct BatchHost {
     std::vector<TiledInst> tiled;
     TiledInst *d_tiled;
     uint64_t *d_tcost, *d_ttiles;
+    uint32_t *d_tmap;  // tile order of the workgroup-per-tile form (null: instance order)
     uint64_t tcost_total, ttiles_total;
     size_t tlds;
     int Kt_max, Kt;             // steps per launch: most allowed, chosen
@@ -623,6 +633,32 @@ sqz_status batch_create(const sqz_fractal *const *fr, int32_t count, BatchHost *
         if (e == hipSuccess) e = hipMemcpy(H->d_tcost, cs.data(), sizeof(uint64_t) * (m + 1), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMalloc(&H->d_ttiles, sizeof(uint64_t) * (m + 1));
         if (e == hipSuccess) e = hipMemcpy(H->d_ttiles, ts.data(), sizeof(uint64_t) * (m + 1), hipMemcpyHostToDevice);
+        // workgroup-per-tile order: the tiles of every pattern kind spread evenly over
+        // the launch, each tile keyed by the middle of its place among its kind's tiles
+        H->d_tmap = nullptr;
+        bool fits = m < 4096;
+        for (size_t q = 0; q < m && fits; ++q) fits = H->tiled[q].units <= 0xFFFFFu;
+        if (e == hipSuccess && fits && SQZ_BATCH_TILE_MAP) {
+            std::map<uint32_t, uint64_t> kind_tiles, kind_seen;
+            for (const TiledInst &T : H->tiled) kind_tiles[T.kind] += T.units;
+            std::vector<std::pair<double, uint32_t>> key;
+            key.reserve(H->ttiles_total);
+            for (size_t q = 0; q < m; ++q) {
+                const TiledInst &T = H->tiled[q];
+                const double n = (double)kind_tiles[T.kind];
+                for (uint64_t j = 0; j < T.units; ++j)
+                    key.push_back({((double)kind_seen[T.kind]++ + 0.5) / n, (uint32_t)(q << 20 | j)});
+            }
+            std::stable_sort(key.begin(), key.end(),
+                             [](const std::pair<double, uint32_t> &x, const std::pair<double, uint32_t> &y) {
+                                 return x.first < y.first;
+                             });
+            std::vector<uint32_t> map(key.size());
+            for (size_t i = 0; i < key.size(); ++i) map[i] = key[i].second;
+            e = hipMalloc(&H->d_tmap, sizeof(uint32_t) * map.size());
+            if (e == hipSuccess)
+                e = hipMemcpy(H->d_tmap, map.data(), sizeof(uint32_t) * map.size(), hipMemcpyHostToDevice);
+        }
         H->Kt = H->Kt_max;
         int per_cu = 0;
         if (e == hipSuccess)
@@ -713,6 +749,7 @@ void batch_destroy(BatchHost *H)
     (void)hipFree(H->d_tiled);
     (void)hipFree(H->d_tcost);
     (void)hipFree(H->d_ttiles);
+    if (H->d_tmap) (void)hipFree(H->d_tmap);
     for (BatchGroup &G : H->groups) {
         (void)hipFree(G.d_args);
         (void)hipFree(G.d_base);
@@ -819,6 +856,7 @@ static sqz_status launch_tiled(const BatchHost *H, int form, unsigned wg_per_cu,
     A.inst = H->d_tiled;
     A.cost_start = H->d_tcost;
     A.tile_start = H->d_ttiles;
+    A.tile_map = H->d_tmap;
     A.ninst = (uint32_t)H->tiled.size();
     A.total_cost = H->tcost_total;
     uint64_t grid = form == 2 ? H->ttiles_total : (uint64_t)H->cus * wg_per_cu;
