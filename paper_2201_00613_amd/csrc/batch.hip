@@ -321,21 +321,27 @@ k_batch_tiles(TiledArgs B, const uint8_t *__restrict__ in, uint8_t *__restrict__
 {
     extern __shared__ __align__(16) unsigned char smem[];
     if constexpr (PerTile) {
+        // one call site of the tile bodies (each inlined once: the kernel's
+        // code must stay small enough for the instruction cache)
         const uint64_t b = xcd_remap(blockIdx.x, gridDim.x);
+        uint32_t a = 0;
+        uint64_t j;
         if (B.tile_map) {
             const uint32_t v = B.tile_map[b];
-            tiled_run<K>(B.inst[v >> 20], in, out, v & 0xFFFFFu, smem);
-            return;
+            a = v >> 20;
+            j = v & 0xFFFFFu;
+        } else {
+            uint32_t e = B.ninst;
+            while (e - a > 1) {
+                const uint32_t m = (a + e) / 2;
+                if (B.tile_start[m] <= b)
+                    a = m;
+                else
+                    e = m;
+            }
+            j = b - B.tile_start[a];
         }
-        uint32_t a = 0, e = B.ninst;
-        while (e - a > 1) {
-            const uint32_t m = (a + e) / 2;
-            if (B.tile_start[m] <= b)
-                a = m;
-            else
-                e = m;
-        }
-        tiled_run<K>(B.inst[a], in, out, b - B.tile_start[a], smem);
+        tiled_run<K>(B.inst[a], in, out, j, smem);
         return;
     }
     const uint64_t lo = B.total_cost * blockIdx.x / gridDim.x;
