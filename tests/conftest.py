@@ -13,6 +13,7 @@ def pytest_configure(config):
     config.addinivalue_line("markers", "slow: long-running CPU check")
 
 
+@pytest.hookimpl(trylast=True)  # after -m deselection: only the selected tests count
 def pytest_collection_modifyitems(config, items):
     # A run that selects GPU tests stops at once, with one message, when the HIP
     # library has not been built (there is no CPU path to fall back on); every
