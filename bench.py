@@ -380,9 +380,16 @@ def golden_error(torch, F, field, dtype: str, offset: float, steps: int):
             "bar": 1e-5 if dtype == "f32" else 2e-2}
 
 
+MASS_EVERY = 100  # diffusion steps between binary64 mass reductions (and one at the end)
+
+
 def diffusion_leg(torch, sqz, steps: int) -> dict:
     """Carpet r=9 (134,217,728 cells), coef 0.1, U(0,1) start: binary32 and bfloat16
-    (offset storage, stochastic rounding) for `steps` steps; binary64 mass drift."""
+    (offset storage, stochastic rounding) for `steps` steps, with a binary64 mass
+    reduction on the device every MASS_EVERY steps and at the end inside the timed
+    region (each into its own work buffer, read after the clock stops); the mass
+    drift at every checkpoint and the error against the stored binary64 values."""
+    from paper_2201_00613_amd import MASS_WORK_DOUBLES
     from paper_2201_00613_amd import workloads as W
 
     F = sqz.Fractal(*W.CARPET, 9)
@@ -403,18 +410,28 @@ def diffusion_leg(torch, sqz, steps: int) -> dict:
             offset = mean
         F.diffuse_run(a, b, 2, 0.1, dtype=dtype, **kw)  # warm-up (result discarded)
         a = u.clone() if dtype == "f32" else F.bf16_encode(u, mean)
+        nchk = max(1, (steps + MASS_EVERY - 1) // MASS_EVERY)
+        work = torch.empty((nchk, MASS_WORK_DOUBLES), dtype=torch.float64, device=u.device)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        r = F.diffuse_run(a, b, steps, 0.1, dtype=dtype, **kw)
+        src, dst, done, r = a, b, 0, a
+        for i in range(nchk):
+            n = min(MASS_EVERY, steps - done)
+            r = F.diffuse_run(src, dst, n, 0.1, dtype=dtype, first_step=done, **kw)
+            if r is dst:
+                src, dst = dst, src
+            done += n
+            F.mass_f64(r, dtype=dtype, offset=offset, work=work[i])
         e1.record()
         torch.cuda.synchronize()
         sec = e0.elapsed_time(e1) / 1e3
-        m1 = float(F.mass_f64(r, dtype=dtype, offset=offset))
+        drift = [(float(m) - m0) / m0 for m in work[:, 0].cpu()]
         res[dtype] = {"ms_per_step": sec * 1e3 / steps, "cell_updates_per_s": F.cells * steps / sec,
                       "algorithmic_gbs": nbytes * F.cells * steps / sec / 1e9,
                       "hbm_frac": nbytes * F.cells * steps / sec / 1e9 / HBM_PEAK_GBS,
-                      "mass_rel_drift": (m1 - m0) / m0}
+                      "mass_every": MASS_EVERY, "mass_rel_drift": drift[-1],
+                      "mass_rel_drift_max": max(drift, key=abs)}
         err = golden_error(torch, F, r, dtype, offset, steps)
         if err is not None:
             res[dtype]["rel_error_vs_binary64"] = err
