@@ -136,6 +136,55 @@ def test_r20_light_cones():
     torch.cuda.empty_cache()
 
 
+def test_r21_indices_past_2_32():
+    """Level-21 triangle (10,460,353,203 cells, two 10.5 GB buffers): compact indices
+    past 2^32 and tile starts past 2^32 bytes.  One step exhaustively over a range
+    across index 2^32; twelve steps (a ten-step launch and a two-step launch) on
+    windows along the tile edges of the tiles around index 2^32 and of the last
+    tiles, and on light-cone samples over the whole array."""
+    torch = torch_or_skip()
+    F, O = gpu_fractal("triangle", 21), oracle_fractal("triangle", 21)
+    assert F.cells > 2 ** 33 and F.tile_level == 10 and not F.resident_run
+    seed, p, t = 2201, 0.3, 12
+    side = 2 ** F.tile_level
+    print("r21: fill and one step", flush=True)
+    a = F.fill_bernoulli(seed, p)
+    b = torch.empty_like(a)
+    F.compact_step(a, b)
+    c0 = 2 ** 32 - 100_000
+    mismatch(to_np(b[c0:c0 + 200_000]), _range_step(O, seed, p, c0, 200_000), "r21 one step across 2^32")
+    print("r21: twelve steps", flush=True)
+    res = F.compact_run(a, b, t)
+    assert res is a
+    per_tile = 3 ** F.tile_level
+    ntiles = F.cells // per_tile
+    t32 = 2 ** 32 // per_tile
+    tiles = np.array([t32 - 1, t32, t32 + 1, ntiles - 2, ntiles - 1, 0], dtype=np.int64)
+    tiles_xy = oracle_fractal("triangle", F.r - F.tile_level).lam(tiles)
+    idx, want = [], []
+    horiz = [(X * side - 10, Y * side - 10) for X, Y in tiles_xy]
+    vert = [(X * side - 10, Y * side + 10) for X, Y in tiles_xy]
+    for corners, w, h in ((horiz, side + 20, 20), (vert, 20, side)):
+        win = O.life_windows(seed, p, corners, w, h, t)
+        for q, (x0, y0) in enumerate(corners):
+            yy, xx = np.mgrid[y0:y0 + h, x0:x0 + w]
+            c = O.nu(np.stack([xx.ravel(), yy.ravel()], 1))
+            keep = c >= 0
+            idx.append(c[keep])
+            want.append(win[q].ravel()[keep])
+    rng = np.random.default_rng(21)
+    c = rng.integers(0, F.cells, 3000)
+    c[:6] = [0, 2 ** 32 - 1, 2 ** 32, 2 ** 32 + 1, F.cells - 2, F.cells - 1]
+    idx.append(c)
+    want.append(O.light_cone(seed, p, O.lam(c), t))
+    idx, want = np.concatenate(idx), np.concatenate(want)
+    assert int((idx >= 2 ** 32).sum()) > idx.size // 2
+    print(f"r21: {idx.size} samples", flush=True)
+    mismatch(to_np(res[torch.from_numpy(idx).cuda()]), want, "r21 twelve steps")
+    del a, b, res
+    torch.cuda.empty_cache()
+
+
 def _range_step(O, seed, p, c0, count):
     """Oracle one-step states of cells [c0, c0+count) from the seeded start, without
     materialising all N cells: each cell's one-step light cone."""
