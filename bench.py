@@ -4,9 +4,11 @@ Workload (N=1): level-16 Sierpinski triangle, replicas (0,0),(1,0),(0,1),
 43,046,721 compact cells, uint8 states from a Bernoulli(0.5) SplitMix64 start
 (seed 2201), B3/S23 steps ping-ponging between two compact buffers.  One
 "step" is one B3/S23 update of every cell.  The K timed steps are one
-sqz_compact_run call: at level 16 its default run form is one launch that
-holds all 729 tiles in LDS for all K steps (exchanging ring cells every ten
-steps); the launches form (ten steps per launch) is timed beside it.  The
+sqz_compact_run call, in the run form the library picks for K steps: from 30
+steps (and where launches would need an extra one-step launch) one launch
+that holds all 729 tiles in LDS for all K steps, exchanging ring cells every
+ten steps; otherwise launches of ten steps.  The other form is timed beside
+it.  The
 same steps on the 65536 x 65536 bounding-box grid give the speedup; the
 level-20 triangle (3.49e9 cells, 20 steps, Bernoulli(0.3)) gives the largest
 workload.
@@ -506,11 +508,22 @@ def main() -> int:
         return 0
     if args.impl != "auto":
         used = "one step per launch"
-    elif form == "resident" or (form == "auto" and F.resident_run and args.steps >= 2):
+    elif form == "resident" or (form == "auto" and F.auto_run_form(args.steps) == "resident"):
         used = "resident"
     else:
         used = "launches"
     log(f"[bench] triangle r={r}: {F.cells} cells, tile level {F.tile_level}, impl {args.impl}, run form {used}")
+    # The comparison legs (the other run form, one step per launch) run first: they are
+    # reported beside the headline, whose W warm-up and K timed steps then find the
+    # device past its first kernels of the process (code loaded, clocks up).
+    other = None
+    if used == "resident":
+        other = ("launches", compact_run(torch, F, seed, p, args.steps, args.warmup, "auto", "launches"))
+    elif used == "launches" and args.impl == "auto" and F.resident_run:
+        other = ("resident", compact_run(torch, F, seed, p, args.steps, args.warmup, "auto", "resident"))
+    s1 = None
+    if args.impl == "auto" and F.run_steps_per_launch >= 2:
+        s1 = compact_run(torch, F, seed, p, args.steps, args.warmup, "tile")
     sec = compact_run(torch, F, seed, p, args.steps, args.warmup, args.impl, form)
     ups = F.cells * args.steps / sec
     ms = sec * 1e3 / args.steps
@@ -540,8 +553,8 @@ def main() -> int:
         "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
         "traffic": None, "note": "no committed counter profile for this kernel source and step count"}
     out["roofline"]["hbm"] = hbm
-    if used == "resident":
-        sl = compact_run(torch, F, seed, p, args.steps, args.warmup, "auto", "launches")
+    if other and other[0] == "launches":
+        sl = other[1]
         nl = run_launches(F, args.steps)
         out["launches_form"] = {"ms_per_step": sl * 1e3 / args.steps, "cell_updates_per_s": F.cells * args.steps / sl,
                                 "launches": nl, "algorithmic_gbs_per_launch": BYTES_PER_UPDATE * F.cells * nl / sl / 1e9}
@@ -550,8 +563,16 @@ def main() -> int:
         if alu:
             out["launches_form"]["roofline"] = alu
         log(f"[bench] launches of {F.run_steps_per_launch} steps: {sl * 1e3 / args.steps:.4f} ms/step")
-    if args.impl == "auto" and F.run_steps_per_launch >= 2:
-        s1 = compact_run(torch, F, seed, p, args.steps, args.warmup, "tile")
+    elif other and other[0] == "resident":
+        sr = other[1]
+        out["resident_form"] = {"ms_per_step": sr * 1e3 / args.steps, "cell_updates_per_s": F.cells * args.steps / sr,
+                                "launches": 1}
+        rr = profiled_counters("k_life_tileR_triangle_r16.md", out["config"]["workload"])
+        alu = alu_roofline(rr, args.steps, sr, 1, F.cells, "k_life_tileR_triangle_r16.md")
+        if alu:
+            out["resident_form"]["roofline"] = alu
+        log(f"[bench] resident run: {sr * 1e3 / args.steps:.4f} ms/step")
+    if s1 is not None:
         out["one_step_per_launch"] = {"ms_per_step": s1 * 1e3 / args.steps,
                                       "cell_updates_per_s": F.cells * args.steps / s1,
                                       "algorithmic_gbs": BYTES_PER_UPDATE * F.cells * args.steps / s1 / 1e9}

@@ -105,7 +105,12 @@ typedef enum sqz_map_impl { SQZ_MAP_SCALAR = 0, SQZ_MAP_MFMA = 1 } sqz_map_impl;
 
 /* How sqz_compact_run_form advances a run.
  *   SQZ_RUN_AUTO: RESIDENT when the fractal offers it (sqz_info.resident_run),
- *                 the buffers are 16-byte aligned and steps >= 2; else LAUNCHES.
+ *                 the buffers are 16-byte aligned, and either steps >= 30 or
+ *                 LAUNCHES would need an extra launch to leave the result in the
+ *                 buffer the step count's parity names (steps >= 2); else
+ *                 LAUNCHES.  The resident run's fixed cost (loading and storing
+ *                 every subtree once) pays from about 30 steps, measured on an
+ *                 MI355X; sqz_run_form_auto reports the choice.
  *   SQZ_RUN_LAUNCHES: one kernel launch per group of up to
  *                 sqz_info.run_steps_per_launch steps, each reading its input
  *                 buffer whole and writing its output buffer whole (temporal
@@ -280,6 +285,14 @@ SQZ_API sqz_status sqz_compact_run(const sqz_fractal *f, uint8_t *d_a, uint8_t *
  */
 SQZ_API sqz_status sqz_compact_run_form(const sqz_fractal *f, sqz_run_form form, uint8_t *d_a, uint8_t *d_b,
                                         int32_t steps, void *stream);
+
+/*
+ * The run form sqz_compact_run (SQZ_RUN_AUTO) takes for `steps` steps on
+ * 16-byte aligned buffers: SQZ_RUN_RESIDENT or SQZ_RUN_LAUNCHES, written to
+ * *form.  Touches no device.  NULL handle or form, or steps < 0:
+ * SQZ_ERR_INVALID.
+ */
+SQZ_API sqz_status sqz_run_form_auto(const sqz_fractal *f, int32_t steps, sqz_run_form *form);
 
 /*
  * Bounding-box baseline (Section "Experimental Setup and Results", approach

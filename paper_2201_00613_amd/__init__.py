@@ -174,6 +174,13 @@ class Fractal:
             check(lib().sqz_compact_run_form(self._h, RUN_FORMS[form], _ptr(a), _ptr(b), steps, st))
         return a if steps % 2 == 0 else b
 
+    def auto_run_form(self, steps: int) -> str:
+        """The run form compact_run(form="auto") takes for `steps` steps (sqz_run_form_auto):
+        "resident" or "launches"."""
+        form = ctypes.c_int(0)
+        check(lib().sqz_run_form_auto(self._h, steps, ctypes.byref(form)))
+        return {v: k for k, v in RUN_FORMS.items()}[form.value]
+
     def expanded_step(self, src, dst):
         torch, dev, st = self._ctx()
         self._need(src.view(-1), torch.uint8, self.n * self.n, "src")

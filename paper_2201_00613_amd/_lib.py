@@ -83,6 +83,7 @@ SIGNATURES = {
                                        ctypes.c_void_p]),
     "sqz_compact_run_form": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                             ctypes.c_int32, ctypes.c_void_p]),
+    "sqz_run_form_auto": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int)]),
     "sqz_expanded_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "sqz_diffuse_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Diffusion), ctypes.c_uint64, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p]),

@@ -300,6 +300,31 @@ sqz_status sqz_compact_run(const sqz_fractal *f, uint8_t *d_a, uint8_t *d_b, int
     return sqz_compact_run_form(f, SQZ_RUN_AUTO, d_a, d_b, steps, stream);
 }
 
+// SQZ_RUN_AUTO's choice on aligned buffers: the resident run when it is offered
+// and either the run is long enough for its fixed cost (loading and storing
+// every tile once, about 25 us at level 16 against 4.6 us per ten-step launch
+// more than its rounds) or the launches would need a one-step launch of their
+// own to land the result in the buffer of the step count's parity.
+constexpr int32_t kAutoResidentSteps = 30;
+
+static bool auto_resident(const FractalHost &h, int32_t steps)
+{
+    if (steps < 2 || !tile_resident(h)) return false;
+    if (steps >= kAutoResidentSteps) return true;
+    const int K = tile_steps_per_launch(h);
+    return plan_launches(steps, K).size() > (size_t)((steps + K - 1) / K);
+}
+
+sqz_status sqz_run_form_auto(const sqz_fractal *f, int32_t steps, sqz_run_form *form)
+{
+    sqz_status st = check_handle(f);
+    if (st != SQZ_OK) return st;
+    if (!form) return set_error(SQZ_ERR_INVALID, "NULL form");
+    if (steps < 0) return set_error(SQZ_ERR_INVALID, "steps < 0");
+    *form = auto_resident(f->h, steps) ? SQZ_RUN_RESIDENT : SQZ_RUN_LAUNCHES;
+    return SQZ_OK;
+}
+
 sqz_status sqz_compact_run_form(const sqz_fractal *f, sqz_run_form form, uint8_t *d_a, uint8_t *d_b, int32_t steps,
                                 void *stream)
 {
@@ -317,7 +342,7 @@ sqz_status sqz_compact_run_form(const sqz_fractal *f, sqz_run_form form, uint8_t
         if (!aligned) return set_error(SQZ_ERR_INVALID, "the resident run needs 16-byte aligned buffers");
         return launch_life_tile_resident(f->h, d_a, d_b, steps, (hipStream_t)stream);
     }
-    if (form == SQZ_RUN_AUTO && steps >= 2 && aligned && tile_resident(f->h))
+    if (form == SQZ_RUN_AUTO && aligned && auto_resident(f->h, steps))
         return launch_life_tile_resident(f->h, d_a, d_b, steps, (hipStream_t)stream);
     const bool aligned8 = !(((uintptr_t)d_a | (uintptr_t)d_b) & 7);
     const bool tiled = f->h.tile_kind && aligned, bits = !tiled && f->h.bitbox && aligned8;

@@ -182,6 +182,7 @@ void prepare_resident(FractalHost &F, const TileTables &TT)
     if (e == hipSuccess)
         e = hipMemcpy(d_bound, TT.bound.data(), TT.bound.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMalloc(&d_bar, bar_words(T->ntiles) * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMemset(d_bar, 0, bar_words(T->ntiles) * sizeof(uint32_t));  // counts carry over between runs
     if (e == hipSuccess) e = hipHostMalloc(&h_flag, sizeof(uint32_t), hipHostMallocMapped | hipHostMallocCoherent);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -200,8 +201,12 @@ template <class Pat>
 sqz_status launch_resident(const FractalHost &F, uint8_t *a, uint8_t *b, int steps, hipStream_t st)
 {
     const TileConfig *T = F.tile;
-    if (__atomic_exchange_n(T->h_flag, 0u, __ATOMIC_ACQ_REL))
+    if (__atomic_exchange_n(T->h_flag, 0u, __ATOMIC_ACQ_REL)) {
+        // the counts of the failed run are unknown: clear them for the next run
+        hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(256), 0, st, T->d_bar, bar_words(T->ntiles));
+        (void)hipGetLastError();
         return set_error(SQZ_ERR_HIP, "a grid barrier of an earlier resident run timed out: its result is invalid");
+    }
     constexpr int NT = nt_of<Pat>();
     TileArgs A = tile_args(F);
     ResidentArgs P;
@@ -213,16 +218,13 @@ sqz_status launch_resident(const FractalHost &F, uint8_t *a, uint8_t *b, int ste
     P.bound = T->d_bound;
     P.bar = T->d_bar;
     P.flag = T->h_flag;
-    hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(256), 0, st, T->d_bar, bar_words(T->ntiles));
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_error(e, "resident run: barrier reset");
     // An ordinary launch: the occupancy check at set-up guarantees that the grid
     // fits the chip at once, so on an otherwise idle device every workgroup is
     // resident; a workgroup that waits for the chip to be shared with other work
     // starts when that work ends, and the bounded barrier wait catches the rest.
     hipLaunchKernelGGL((k_life_tileR<Pat, NT>), dim3((unsigned)T->ntiles), dim3(NT), SQZ_RESIDENT_PAD(T->lds_pad), st,
                        A, P);
-    e = hipGetLastError();
+    const hipError_t e = hipGetLastError();
     return e == hipSuccess ? SQZ_OK : hip_error(e, "resident run launch");
 }
 

@@ -840,7 +840,7 @@ struct ResidentArgs {
     int32_t kstep;         // steps between exchanges (2 .. ring depth)
     uint32_t nbound;       // boundary cells per tile
     const uint32_t *bound; // their tile-local indices
-    uint32_t *bar;         // device words of the grid barrier (bar_words(grid)), zero at launch
+    uint32_t *bar;         // device words of the grid barrier (bar_words(grid)); counts carry over between runs
     uint32_t *flag;        // host-visible word: set to 1 when a barrier wait timed out
 };
 
@@ -859,9 +859,13 @@ constexpr uint32_t kSpinLimit = 1u << 22;
 // workgroups of a group of kBarGroup consecutive block indices add to their
 // group's counter (own 128-byte line), the last of a group to arrive adds to
 // the global counter, and every workgroup polls the global counter until all
-// groups have arrived.  Counts accumulate over the run (barrier i waits for
-// i arrivals per member).  The workgroup meets again before any lane reads
-// what others wrote.  The wait is bounded: after kSpinLimit polls, or as soon
+// groups have arrived.  Counts accumulate over runs, modulo 2^32 (barrier i
+// since the counters were cleared waits for i arrivals per member, compared
+// wrap-safe); word 2 holds the barriers completed by earlier runs, read by
+// every workgroup at its start and advanced by workgroup 0 after the run's
+// last barrier, so that no run has to clear the counters (clearing them
+// costs a launch of its own) and replays of a captured run stay in step.
+// The workgroup meets again before any lane reads what others wrote.  The wait is bounded: after kSpinLimit polls, or as soon
 // as another workgroup has given up, the workgroup marks the run as timed out
 // (device word and host-visible flag) and goes on, so every wave reaches the
 // end of the kernel; such a run's results are invalid and the host reports it.
@@ -887,7 +891,7 @@ __device__ __forceinline__ void grid_barrier(uint32_t *bar, uint32_t nbar, uint3
         for (uint32_t spin = 0;; ++spin) {
             const uint64_t v =
                 __hip_atomic_load(reinterpret_cast<uint64_t *>(bar), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if ((uint32_t)v >= target) break;
+            if ((int32_t)((uint32_t)v - target) >= 0) break;
             if ((v >> 32) != 0 || spin == kSpinLimit) {
                 __hip_atomic_store(bar + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_store(flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -943,7 +947,9 @@ __device__ __forceinline__ void tile_bodyR(const TileArgs &A, const ResidentArgs
     if (v) atomicOr(lds_word(s_buf, home), 1u << (home & 31));
     __syncthreads();
 
-    uint32_t cur = 0, nbar = 0;  // buffer holding the state; barriers passed
+    uint32_t cur = 0, nbar = 0;  // buffer holding the state; barriers passed in this run
+    // barriers completed by earlier runs (used by the counting lane only)
+    const uint32_t base = tid == 0 ? __hip_atomic_load(P.bar + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
     int32_t done = 0;
     for (;;) {
         const int32_t ks = P.steps - done < P.kstep ? P.steps - done : P.kstep;
@@ -988,14 +994,16 @@ __device__ __forceinline__ void tile_bodyR(const TileArgs &A, const ResidentArgs
             s_buf[2 * WORDS + LDS::VIRT + tid] = 0;
         }
         ++nbar;
-        grid_barrier(P.bar, nbar, P.flag);
+        grid_barrier(P.bar, base + nbar, P.flag);
         v = 0;
         if (tid < kMaxRing) v = here ? (__hip_atomic_load(xb + gi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1u) : 0u;
         if (v) atomicOr(lds_word(s_buf + cur * WORDS, home), 1u << (home & 31));
         __syncthreads();
     }
     ++nbar;
-    grid_barrier(P.bar, nbar, P.flag);  // every tile has read its last ring cells
+    grid_barrier(P.bar, base + nbar, P.flag);  // every tile has read its last ring cells (and the base)
+    if (blockIdx.x == 0 && tid == 0)
+        __hip_atomic_store(P.bar + 2, base + nbar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     tile_store<Pat, NT, true>(A, (P.steps & 1) ? P.b : P.a, A0, o, W, s_buf + cur * WORDS);
 }
 

@@ -52,8 +52,8 @@ def test_resident_equals_launches(name, r):
 
 
 def test_back_to_back_runs_equal_one_run():
-    """Each run resets its barrier: six runs of 7 steps in a row on one stream equal one
-    run of 42 steps (and the launches form)."""
+    """The grid-barrier counts carry over from run to run: six runs of 7 steps in a row
+    on one stream equal one run of 42 steps (and the launches form)."""
     torch = torch_or_skip()
     F = gpu_fractal("triangle", 16)
     assert F.resident_run
@@ -70,17 +70,94 @@ def test_back_to_back_runs_equal_one_run():
     torch.cuda.empty_cache()
 
 
-def test_zero_steps_and_auto_choice():
+def test_runs_of_mixed_lengths_in_a_row():
+    """Runs of 1, 2, 9, 10, 11, 25, 0, 3 and 20 steps in a row (each passing a different
+    number of barriers, the 0-step run one) equal the launches form over the same
+    steps, after every run."""
     torch = torch_or_skip()
+    F = gpu_fractal("triangle", 12)
+    assert F.resident_run
+    a = F.fill_bernoulli(91, 0.4)
+    x, y = a.clone(), torch.empty_like(a)
+    u, v = a.clone(), torch.empty_like(a)
+    for steps in (1, 2, 9, 10, 11, 25, 0, 3, 20):
+        x1 = F.compact_run(x, y, steps, form="resident")
+        y = x if x1 is y else y
+        x = x1
+        u1 = F.compact_run(u, v, steps, form="launches")
+        v = u if u1 is v else v
+        u = u1
+        assert torch.equal(x, u), steps
+
+
+def test_graph_replays_of_a_resident_run():
+    """A resident run of 20 steps captured once into a graph and replayed three times,
+    with eager work and synchronisation between the replays: after replay k the
+    state equals 20 k steps of the launches form."""
+    torch = torch_or_skip()
+    F = gpu_fractal("triangle", 12)
+    assert F.resident_run
+    a = F.fill_bernoulli(17, 0.5)
+    x, y = a.clone(), torch.empty_like(a)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # warm-up outside the capture, then restore the start
+        F.compact_run(x, y, 20, form="resident")
+        x.copy_(a)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        res = F.compact_run(x, y, 20, form="resident")
+    assert res is x
+    torch.cuda.synchronize()
+    assert torch.equal(x, a)  # capture records, it does not run
+    u, v = a.clone(), torch.empty_like(a)
+    for k in range(1, 4):
+        g.replay()
+        torch.cuda.synchronize()
+        u = F.compact_run(u, v, 20, form="launches")  # eager work between the replays
+        torch.cuda.synchronize()
+        assert torch.equal(x, u), k
+    del g
+
+
+def _launch_count(steps, K):
+    """Launches of the launches form: full groups of K, the rest, and one more
+    one-step launch when their count's parity differs from the step count's."""
+    n = steps // K + (1 if steps % K else 0)
+    return n + (1 if steps >= 1 and (n & 1) != (steps & 1) else 0)
+
+
+def test_zero_steps_and_auto_choice():
+    """The auto form is the resident run for 30 steps and more, and below that where the
+    launches form needs an extra one-step launch for the result's buffer (never for
+    fewer than two steps); either way the results equal the explicit forms'."""
+    torch = torch_or_skip()
+    import paper_2201_00613_amd as sqz
+
     F = gpu_fractal("triangle", 10)
+    assert F.resident_run
+    K = F.run_steps_per_launch
     a = F.fill_bernoulli(3, 0.5)
     keep = a.clone()
     assert F.compact_run(a, torch.empty_like(a), 0, form="resident") is a
     assert torch.equal(a, keep)
-    # auto takes the resident form from two steps: same result as the explicit forms
-    r_auto = F.compact_run(a.clone(), torch.empty_like(a), 24)
-    r_res = F.compact_run(a.clone(), torch.empty_like(a), 24, form="resident")
-    assert torch.equal(r_auto, r_res)
+    for steps in range(0, 61):
+        want = steps >= 2 and (steps >= 30 or _launch_count(steps, K) > -(-steps // K))
+        assert F.auto_run_form(steps) == ("resident" if want else "launches"), steps
+    for steps in (5, 10, 20, 24, 31):
+        r_auto = F.compact_run(a.clone(), torch.empty_like(a), steps)
+        r_res = F.compact_run(a.clone(), torch.empty_like(a), steps, form="resident")
+        r_lau = F.compact_run(a.clone(), torch.empty_like(a), steps, form="launches")
+        assert torch.equal(r_auto, r_res) and torch.equal(r_auto, r_lau), steps
+    G = gpu_fractal("triangle", 20)  # no resident run: always launches
+    assert not G.resident_run and all(G.auto_run_form(t) == "launches" for t in (2, 30, 100))
+    L = sqz._lib.lib()
+    form = ctypes.c_int(-1)
+    assert L.sqz_run_form_auto(F._h, -1, ctypes.byref(form)) == 1 and form.value == -1
+    assert L.sqz_run_form_auto(F._h, 4, None) == 1
+    assert L.sqz_run_form_auto(None, 4, ctypes.byref(form)) == 1
 
 
 def test_argument_errors():
