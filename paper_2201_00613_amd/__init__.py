@@ -7,6 +7,7 @@ binding raises if the native library is missing or no HIP device is present.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 
 from ._lib import (BF16, F32, HOLE, IMPL_AUTO, IMPL_BITS, IMPL_CELL, IMPL_CELL_MFMA, IMPL_TILE, IMPL_XTILE,
@@ -37,15 +38,27 @@ def descriptor_check(s: int, offsets, r: int) -> dict:
     return {f: getattr(info, f) for f, _ in Info._fields_}
 
 
-def _torch():
-    import torch
+_TORCH = None
+_SAME_DEVICE = contextlib.nullcontext()
 
-    if not torch.cuda.is_available():
-        raise RuntimeError("paper_2201_00613_amd needs a HIP device (torch.cuda.is_available() is False)")
-    return torch
+
+def _torch():
+    global _TORCH
+    if _TORCH is None:
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("paper_2201_00613_amd needs a HIP device (torch.cuda.is_available() is False)")
+        _TORCH = torch
+    return _TORCH
 
 
 def _stream(torch, device):
+    """torch's current stream on `device` as a raw handle (torch's own accessor when it
+    has one: the public current_stream() builds a Stream object on every call)."""
+    raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+    if raw is not None:
+        return ctypes.c_void_p(raw(device.index))
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
@@ -95,8 +108,11 @@ class Fractal:
 
     # -- helpers ------------------------------------------------------------
     def _ctx(self):
+        """(torch, a context that makes the fractal's device current, its current stream);
+        no device switch when the device is current already."""
         torch = _torch()
-        return torch, torch.cuda.device(self.device), _stream(torch, self.device)
+        dev = _SAME_DEVICE if torch.cuda.current_device() == self.device.index else torch.cuda.device(self.device)
+        return torch, dev, _stream(torch, self.device)
 
     def _need(self, t, dtype, numel, name):
         if t.device != self.device or t.dtype != dtype or not t.is_contiguous() or t.numel() != numel:
@@ -347,8 +363,11 @@ class Batch:
             pass
 
     def _ctx(self):
+        """(torch, a context that makes the batch's device current, its current stream);
+        no device switch when the device is current already."""
         torch = _torch()
-        return torch, torch.cuda.device(self.device), _stream(torch, self.device)
+        dev = _SAME_DEVICE if torch.cuda.current_device() == self.device.index else torch.cuda.device(self.device)
+        return torch, dev, _stream(torch, self.device)
 
     def _need(self, t, name):
         torch = _torch()

@@ -832,7 +832,8 @@ __device__ __forceinline__ void tile_bodyK(const TileArgs &A, const uint8_t *__r
 // steps exactly as the multi-step launch does (tile_bodyK).  Exchange
 // buffers alternate between b and a, so a tile writing the exports of one
 // exchange never meets a tile still reading the previous one; the final
-// state goes to a (steps even) or b (odd) after one more barrier.
+// state goes to a (steps even) or b (odd), after one more barrier only when
+// the last exchange went through that buffer.
 // ---------------------------------------------------------------------------
 struct ResidentArgs {
     uint8_t *a, *b;        // caller buffers; a holds the start
@@ -1000,9 +1001,18 @@ __device__ __forceinline__ void tile_bodyR(const TileArgs &A, const ResidentArgs
         if (v) atomicOr(lds_word(s_buf + cur * WORDS, home), 1u << (home & 31));
         __syncthreads();
     }
-    ++nbar;
-    grid_barrier(P.bar, base + nbar, P.flag);  // every tile has read its last ring cells (and the base)
-    if (blockIdx.x == 0 && tid == 0)
+    // The state goes to the buffer of the step count's parity.  A tile reads an
+    // exchange buffer only between the barrier that closes that exchange and its
+    // own arrival at the next barrier, and reads the start buffer `a` only before
+    // its first one; so only the last exchange's buffer (exchange j goes through
+    // b for odd j, a for even j; `a` counts as exchange 0) may still be in use,
+    // and only a store into it must wait for every tile.
+    if ((uint32_t)(P.steps & 1) == (nbar & 1)) {
+        ++nbar;
+        grid_barrier(P.bar, base + nbar, P.flag);
+    }
+    // every workgroup has passed a barrier of this run, so has read the base
+    if (nbar && blockIdx.x == 0 && tid == 0)
         __hip_atomic_store(P.bar + 2, base + nbar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     tile_store<Pat, NT, true>(A, (P.steps & 1) ? P.b : P.a, A0, o, W, s_buf + cur * WORDS);
 }
