@@ -43,6 +43,9 @@ namespace sqz {
 #ifndef SQZ_TRI_TILE_BIG_FROM  // fractal level from which triangle tiles use SQZ_TRI_TILE_LEVEL (else 8)
 #define SQZ_TRI_TILE_BIG_FROM 16
 #endif
+#ifndef SQZ_SPLIT_EXCHANGE  // 1: the resident run updates interior blocks while its exchange barrier completes
+#define SQZ_SPLIT_EXCHANGE 1
+#endif
 #ifndef SQZ_NT_LOAD
 #define SQZ_NT_LOAD 0
 #endif
@@ -566,8 +569,11 @@ __device__ __forceinline__ void load_nb(const TileArgs &A, NbRegs<Pat, NT> &R)
 // Full: the tile has all TileLds<Pat>::NBMAX blocks (its level is the pattern's
 // largest), so every slot but the last is whole and runs without a branch,
 // which lets the compiler overlap one slot's LDS reads with another's logic.
+// sel (not Full): bit s set = update the blocks of slot s (the same for every
+// lane of a wave).
 template <class Pat, int NT, bool Full = false>
-__device__ __forceinline__ void tile_blocks(const TileArgs &A, NbRegs<Pat, NT> &R, const uint32_t *src, uint32_t *dst)
+__device__ __forceinline__ void tile_blocks(const TileArgs &A, NbRegs<Pat, NT> &R, const uint32_t *src, uint32_t *dst,
+                                            uint32_t sel = ~0u)
 {
     R.keep_packed();
     using LDS = TileLds<Pat>;
@@ -618,7 +624,7 @@ __device__ __forceinline__ void tile_blocks(const TileArgs &A, NbRegs<Pat, NT> &
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             const uint32_t b = threadIdx.x + s * NT;
-            if (b < A.nblocks) {
+            if (((sel >> s) & 1u) && b < A.nblocks) {  // sel: the slots to update (uniform per wave)
                 const uint32_t x = src[b];
                 uint32_t w[NG];
 #pragma unroll
@@ -878,28 +884,39 @@ __host__ __device__ constexpr uint32_t bar_words(uint64_t grid)
     return (uint32_t)((1 + (grid + kBarGroup - 1) / kBarGroup) * kBarStride);
 }
 
+// Arrival of this workgroup at barrier n (one lane, after the workgroup has
+// met with every wave's exchange stores complete).
+__device__ __forceinline__ void barrier_arrive(uint32_t *bar, uint32_t n)
+{
+    const uint32_t G = gridDim.x, g = blockIdx.x / kBarGroup;
+    const uint32_t gs = G - g * kBarGroup < kBarGroup ? G - g * kBarGroup : kBarGroup;
+    const uint32_t old = __hip_atomic_fetch_add(bar + kBarStride * (1 + g), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (old + 1 == n * gs) __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait of one lane until every workgroup has arrived at barrier n (bounded).
+__device__ __forceinline__ void barrier_poll(uint32_t *bar, uint32_t n, uint32_t *flag)
+{
+    const uint32_t ng = (gridDim.x + kBarGroup - 1) / kBarGroup, target = n * ng;
+    for (uint32_t spin = 0;; ++spin) {
+        const uint64_t v = __hip_atomic_load(reinterpret_cast<uint64_t *>(bar), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((int32_t)((uint32_t)v - target) >= 0) break;
+        if ((v >> 32) != 0 || spin == kSpinLimit) {
+            __hip_atomic_store(bar + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+}
+
 __device__ __forceinline__ void grid_barrier(uint32_t *bar, uint32_t nbar, uint32_t *flag)
 {
     __builtin_amdgcn_s_waitcnt(0);  // this wave's exchange stores are complete
     __syncthreads();
     if (threadIdx.x == 0) {
-        const uint32_t G = gridDim.x, g = blockIdx.x / kBarGroup, ng = (G + kBarGroup - 1) / kBarGroup;
-        const uint32_t gs = G - g * kBarGroup < kBarGroup ? G - g * kBarGroup : kBarGroup;
-        const uint32_t old =
-            __hip_atomic_fetch_add(bar + kBarStride * (1 + g), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (old + 1 == nbar * gs) __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t target = nbar * ng;
-        for (uint32_t spin = 0;; ++spin) {
-            const uint64_t v =
-                __hip_atomic_load(reinterpret_cast<uint64_t *>(bar), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if ((int32_t)((uint32_t)v - target) >= 0) break;
-            if ((v >> 32) != 0 || spin == kSpinLimit) {
-                __hip_atomic_store(bar + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-                break;
-            }
-            __builtin_amdgcn_s_sleep(2);
-        }
+        barrier_arrive(bar, nbar);
+        barrier_poll(bar, nbar, flag);
     }
     __syncthreads();
 }
@@ -951,6 +968,21 @@ __device__ __forceinline__ void tile_bodyR(const TileArgs &A, const ResidentArgs
     uint32_t cur = 0, nbar = 0;  // buffer holding the state; barriers passed in this run
     // barriers completed by earlier runs (used by the counting lane only)
     const uint32_t base = tid == 0 ? __hip_atomic_load(P.bar + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+    // Slots of this wave with a block that reads ring words (word VIRT and up,
+    // cleared at an exchange and then filled from the other tiles): the first
+    // round after an exchange updates the other slots while the barrier
+    // completes, these after the ring cells have arrived.  The neighbour table
+    // is the same for every tile, so this is too.
+    uint32_t defer = 0;
+#pragma unroll
+    for (int sl = 0; sl < NbRegs<Pat, NT>::NSLOT; ++sl) {
+        bool ring = false;
+        if (tid + sl * NT < A.nblocks)
+#pragma unroll
+            for (int g = 0; g < LDS::NGRP; ++g) ring |= R.at(sl, g) >= 4u * LDS::VIRT;
+        if (__ballot(ring)) defer |= 1u << sl;
+    }
+    const uint8_t *imp = nullptr;  // exchange buffer whose barrier this workgroup has arrived at, not yet passed
     int32_t done = 0;
     for (;;) {
         const int32_t ks = P.steps - done < P.kstep ? P.steps - done : P.kstep;
@@ -958,10 +990,22 @@ __device__ __forceinline__ void tile_bodyR(const TileArgs &A, const ResidentArgs
             const uint32_t nx = cur == 2 ? 0 : cur + 1, cl = nx == 2 ? 0 : nx + 1;
             const uint32_t *src = s_buf + cur * WORDS;
             uint32_t *dst = s_buf + nx * WORDS;
-            if (A.nblocks == LDS::NBMAX)
+            if (imp) {
+                tile_blocks<Pat, NT>(A, R, src, dst, ~defer);
+                if (tid == 0) barrier_poll(P.bar, base + nbar, P.flag);
+                __syncthreads();
+                v = 0;
+                if (tid < kMaxRing)
+                    v = here ? (__hip_atomic_load(imp + gi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1u) : 0u;
+                if (v) atomicOr(lds_word(s_buf + cur * WORDS, home), 1u << (home & 31));
+                __syncthreads();
+                tile_blocks<Pat, NT>(A, R, src, dst, defer);
+                imp = nullptr;
+            } else if (A.nblocks == LDS::NBMAX) {
                 tile_blocks<Pat, NT, true>(A, R, src, dst);
-            else
+            } else {
                 tile_blocks<Pat, NT>(A, R, src, dst);
+            }
             if (j < ks) {
                 uint32_t *clr = s_buf + cl * WORDS;
                 if (tid < WORDS - LDS::VIRT) clr[LDS::VIRT + tid] = 0;
@@ -995,11 +1039,19 @@ __device__ __forceinline__ void tile_bodyR(const TileArgs &A, const ResidentArgs
             s_buf[2 * WORDS + LDS::VIRT + tid] = 0;
         }
         ++nbar;
-        grid_barrier(P.bar, base + nbar, P.flag);
-        v = 0;
-        if (tid < kMaxRing) v = here ? (__hip_atomic_load(xb + gi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1u) : 0u;
-        if (v) atomicOr(lds_word(s_buf + cur * WORDS, home), 1u << (home & 31));
-        __syncthreads();
+        if (SQZ_SPLIT_EXCHANGE) {
+            __builtin_amdgcn_s_waitcnt(0);  // this wave's exchange stores are complete
+            __syncthreads();
+            if (tid == 0) barrier_arrive(P.bar, base + nbar);
+            imp = xb;  // the next round waits for the barrier after updating the other slots
+        } else {
+            grid_barrier(P.bar, base + nbar, P.flag);
+            v = 0;
+            if (tid < kMaxRing)
+                v = here ? (__hip_atomic_load(xb + gi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1u) : 0u;
+            if (v) atomicOr(lds_word(s_buf + cur * WORDS, home), 1u << (home & 31));
+            __syncthreads();
+        }
     }
     // The state goes to the buffer of the step count's parity.  A tile reads an
     // exchange buffer only between the barrier that closes that exchange and its
