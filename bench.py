@@ -162,12 +162,18 @@ def alu_roofline(rec, steps: int, sec: float, launches: int, cells: int, profile
     launch_s = sec / launches
     achieved = entry["valu_insts"] / launch_s / 1e9
     ceiling = rec["valu_mix_ceiling_per_cu_clock"] * NUM_CUS * CLOCK_HZ / 1e9
-    return {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_G, "unit": "G VALU wave-instructions/s",
-            "frac": achieved / VALU_PEAK_G, "traffic": entry["traffic_bytes"] / launch_s / 1e9,
-            "traffic_unit": "GB/s", "traffic_vs_algorithmic": entry["traffic_bytes"] / (BYTES_PER_UPDATE * cells),
-            "per_cu_clock": achieved * 1e9 / NUM_CUS / CLOCK_HZ,
-            "measured_mix_ceiling": ceiling, "frac_of_measured_mix_ceiling": achieved / ceiling,
-            "counters_from": f"profiles/{profile} (dispatches of {per} steps; source hash {rec['source_sha256_16']})"}
+    out = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_G, "unit": "G VALU wave-instructions/s",
+           "frac": achieved / VALU_PEAK_G, "traffic": entry["traffic_bytes"] / launch_s / 1e9,
+           "traffic_unit": "GB/s", "traffic_vs_algorithmic": entry["traffic_bytes"] / (BYTES_PER_UPDATE * cells),
+           "per_cu_clock": achieved * 1e9 / NUM_CUS / CLOCK_HZ,
+           "measured_mix_ceiling": ceiling, "frac_of_measured_mix_ceiling": achieved / ceiling,
+           "counters_from": f"profiles/{profile} (dispatches of {per} steps; source hash {rec['source_sha256_16']})"}
+    if "valu_mix_ceiling_at_occupancy" in rec:
+        # the same mix at the kernel's own occupancy (waves per SIMD its workgroups allow)
+        occ = rec["valu_mix_ceiling_at_occupancy"] * NUM_CUS * CLOCK_HZ / 1e9
+        out.update({"waves_per_simd": rec.get("waves_per_simd"), "mix_ceiling_at_occupancy": occ,
+                    "frac_of_mix_ceiling_at_occupancy": achieved / occ})
+    return out
 
 
 def cpu_baseline(r: int, seed: int, p: float, min_sec: float, max_steps: int) -> dict:

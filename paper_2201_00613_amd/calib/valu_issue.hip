@@ -110,9 +110,10 @@ int main()
     hipDeviceProp_t prop;
     CHECK(hipGetDeviceProperties(&prop, 0));
     const int cus = prop.multiProcessorCount;
-    const int grids[2] = {cus * 4, cus * 16};  // 4 and 8 (the maximum) waves per SIMD, the latter in two rounds
+    // 4, 6 and 8 (the maximum) waves per SIMD, the last in two rounds
+    const int grids[3] = {cus * 4, cus * 6, cus * 16};
     uint32_t *d = nullptr;
-    CHECK(hipMalloc(&d, (size_t)grids[1] * 256 * sizeof(uint32_t)));
+    CHECK(hipMalloc(&d, (size_t)grids[2] * 256 * sizeof(uint32_t)));
     printf("{\"device\": \"%s\", \"compute_units\": %d}\n", prop.name, cus);
     for (int grid : grids) {
         const int iters = 4096;
@@ -126,7 +127,7 @@ int main()
     // shader clock under load: per-wave shader-clock ticks over real-time ticks
     int wall_khz = 0;
     CHECK(hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, 0));
-    const int grid = grids[1];
+    const int grid = grids[2];
     unsigned long long *dt = nullptr;
     CHECK(hipMalloc(&dt, (size_t)grid * 4 * 2 * sizeof(unsigned long long)));
     hipLaunchKernelGGL(k_clock, dim3(grid), dim3(256), 0, 0, dt, d, 4096, 7u);
