@@ -27,27 +27,58 @@ __device__ __forceinline__ void lam_any(const MapParams &P, uint64_t c, uint32_t
         lam_map64(P, c, x, y);
 }
 
+// The standalone maps stream their inputs from HBM: each lane takes kMapUnroll
+// elements (kBlock apart, so every load instruction stays coalesced) per pass
+// and issues all their loads before the first map, so the memory latency is
+// paid once per kMapUnroll elements instead of once per element.
+#ifndef SQZ_MAP_UNROLL
+#define SQZ_MAP_UNROLL 8
+#endif
+constexpr int kMapUnroll = SQZ_MAP_UNROLL;
+
 __global__ void __launch_bounds__(kBlock) k_lambda(MapParams P, const uint64_t *__restrict__ idx, int64_t count,
                                                    int32_t *__restrict__ xy)
 {
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += (int64_t)gridDim.x * kBlock) {
-        uint64_t c = idx[i];
-        int2 out = make_int2(-1, -1);
-        if (c < P.N) {
-            uint32_t x, y;
-            lam_any(P, c, x, y);
-            out = make_int2((int)x, (int)y);
+    const int64_t stride = (int64_t)gridDim.x * kBlock * kMapUnroll;
+    for (int64_t i0 = (int64_t)blockIdx.x * kBlock * kMapUnroll + threadIdx.x; i0 < count; i0 += stride) {
+        uint64_t c[kMapUnroll];
+#pragma unroll
+        for (int u = 0; u < kMapUnroll; ++u) {
+            const int64_t i = i0 + (int64_t)u * kBlock;
+            c[u] = i < count ? idx[i] : ~0ull;
         }
-        reinterpret_cast<int2 *>(xy)[i] = out;
+#pragma unroll
+        for (int u = 0; u < kMapUnroll; ++u) {
+            const int64_t i = i0 + (int64_t)u * kBlock;
+            if (i < count) {
+                int2 out = make_int2(-1, -1);
+                if (c[u] < P.N) {
+                    uint32_t x, y;
+                    lam_any(P, c[u], x, y);
+                    out = make_int2((int)x, (int)y);
+                }
+                reinterpret_cast<int2 *>(xy)[i] = out;
+            }
+        }
     }
 }
 
 __global__ void __launch_bounds__(kBlock) k_nu(MapParams P, const int32_t *__restrict__ xy, int64_t count,
                                                uint64_t *__restrict__ idx)
 {
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += (int64_t)gridDim.x * kBlock) {
-        int2 p = reinterpret_cast<const int2 *>(xy)[i];
-        idx[i] = nu_map(P, p.x, p.y);
+    const int64_t stride = (int64_t)gridDim.x * kBlock * kMapUnroll;
+    for (int64_t i0 = (int64_t)blockIdx.x * kBlock * kMapUnroll + threadIdx.x; i0 < count; i0 += stride) {
+        int2 p[kMapUnroll];
+#pragma unroll
+        for (int u = 0; u < kMapUnroll; ++u) {
+            const int64_t i = i0 + (int64_t)u * kBlock;
+            p[u] = i < count ? reinterpret_cast<const int2 *>(xy)[i] : make_int2(0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < kMapUnroll; ++u) {
+            const int64_t i = i0 + (int64_t)u * kBlock;
+            if (i < count) idx[i] = nu_map(P, p[u].x, p[u].y);
+        }
     }
 }
 
