@@ -196,6 +196,7 @@ void map_tables(const FractalHost &F, int level, MapParams &P, MapTables &T)
         T.off[i] = T.all.size();
         T.all.insert(T.all.end(), parts[i].begin(), parts[i].end());
     }
+    P.ntab = (uint32_t)T.all.size();
 }
 
 void host_lambda(const FractalHost &F, int level, uint64_t c, int64_t &x, int64_t &y)

@@ -67,6 +67,7 @@ struct MapParams {
     Div32 dklam32;
     Div32 dsnu;
     const uint32_t *lam_lo, *lam_top, *nu_lo, *nu_top;  // device tables (set by the uploader)
+    uint32_t ntab;            // words of the four tables, stored contiguously from lam_lo
 };
 
 // Contents of the four map tables of one level, concatenated in the order

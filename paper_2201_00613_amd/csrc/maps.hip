@@ -117,19 +117,60 @@ __global__ void __launch_bounds__(kBlock) k_fill_uniform(MapParams P, uint64_t s
 
 // B3/S23 on the fractal: a member neighbour counts its state; a hole or a
 // point outside the box counts nothing.
-__global__ void __launch_bounds__(kBlock) k_life_cell(MapParams P, const uint8_t *__restrict__ in,
-                                                      uint8_t *__restrict__ out)
+// One lambda and eight nu per cell make about 27 map-table reads per cell,
+// scattered over tables of at most 4 x 4096 words.  Each workgroup copies
+// the tables into LDS once and then strides over the cells, so those reads
+// are LDS reads rather than divergent vector-memory gathers; only the nine
+// state bytes per cell come through the vector-memory path.
+constexpr int kCellBlock = 512;
+
+__global__ void __launch_bounds__(kCellBlock) k_life_cell(MapParams P, const uint8_t *__restrict__ in,
+                                                          uint8_t *__restrict__ out)
 {
-    for (uint64_t c = (uint64_t)blockIdx.x * kBlock + threadIdx.x; c < P.N; c += (uint64_t)gridDim.x * kBlock) {
+    extern __shared__ uint32_t s_tab[];
+    for (uint32_t i = threadIdx.x; i < P.ntab; i += kCellBlock) s_tab[i] = P.lam_lo[i];
+    __syncthreads();
+    MapParams L = P;
+    L.lam_lo = s_tab;
+    L.lam_top = s_tab + (P.lam_top - P.lam_lo);
+    L.nu_lo = s_tab + (P.nu_lo - P.lam_lo);
+    L.nu_top = s_tab + (P.nu_top - P.lam_lo);
+    for (uint64_t c = (uint64_t)blockIdx.x * kCellBlock + threadIdx.x; c < P.N;
+         c += (uint64_t)gridDim.x * kCellBlock) {
         uint32_t x, y;
-        lam_any(P, c, x, y);
+        lam_any(L, c, x, y);
         uint32_t cnt = 0;
+        if (P.nnu >= 2) {
+            // A neighbour inside the centre's lowest nu chunk shares every
+            // higher chunk with it, so its index is the centre's with the
+            // lowest chunk's digits replaced (nu(lambda(c)) = c): one table
+            // read instead of a full nu.  Neighbours across the chunk edge
+            // take the full map.
+            const uint32_t hx = divq(x, P.dsnu), hy = divq(y, P.dsnu);
+            const uint32_t lx = x - hx * P.snu, ly = y - hy * P.snu;
+            const uint64_t chi = c - L.nu_lo[lx + P.snu * ly];
 #pragma unroll
-        for (int j = 0; j < 9; ++j) {
-            if (j == 4) continue;
-            int dx = j % 3 - 1, dy = j / 3 - 1;
-            uint64_t q = nu_map(P, (int32_t)x + dx, (int32_t)y + dy);
-            if (q != kHole64) cnt += in[q];
+            for (int j = 0; j < 9; ++j) {
+                if (j == 4) continue;
+                const int dx = j % 3 - 1, dy = j / 3 - 1;
+                const uint32_t nx = lx + (uint32_t)dx, ny = ly + (uint32_t)dy;
+                uint64_t q;
+                if (nx < P.snu && ny < P.snu) {
+                    const uint32_t e = L.nu_lo[nx + P.snu * ny];
+                    q = e == kNuHole32 ? kHole64 : chi + e;
+                } else {
+                    q = nu_map(L, (int32_t)x + dx, (int32_t)y + dy);
+                }
+                if (q != kHole64) cnt += in[q];
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 9; ++j) {
+                if (j == 4) continue;
+                int dx = j % 3 - 1, dy = j / 3 - 1;
+                uint64_t q = nu_map(L, (int32_t)x + dx, (int32_t)y + dy);
+                if (q != kHole64) cnt += in[q];
+            }
         }
         uint32_t self = in[c];
         out[c] = (uint8_t)(cnt == 3 || (self && cnt == 2));
@@ -176,7 +217,18 @@ sqz_status launch_fill_uniform(const MapParams &P, uint64_t seed, float *out, hi
 
 sqz_status launch_life_cell(const MapParams &P, const uint8_t *in, uint8_t *out, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_life_cell, dim3(grid_for(P.N)), dim3(kBlock), 0, st, P, in, out);
+    // as many workgroups as are resident at once: each copies the tables once
+    const size_t lds = (size_t)P.ntab * sizeof(uint32_t);
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_life_cell, kCellBlock, lds);
+    if (e != hipSuccess) return hip_error(e, "compact_step (cell) occupancy");
+    if (per_cu < 1) return set_error(SQZ_ERR_UNSUPPORTED, "map tables (%zu B) do not fit in LDS", lds);
+    uint64_t grid = (P.N + kCellBlock - 1) / kCellBlock;
+    if (grid > (uint64_t)cus * per_cu) grid = (uint64_t)cus * per_cu;
+    if (grid == 0) grid = 1;
+    hipLaunchKernelGGL(k_life_cell, dim3((unsigned)grid), dim3(kCellBlock), lds, st, P, in, out);
     return after_launch("compact_step (cell) launch");
 }
 
