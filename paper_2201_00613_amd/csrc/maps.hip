@@ -63,9 +63,18 @@ __global__ void __launch_bounds__(kBlock) k_lambda(MapParams P, const uint64_t *
     }
 }
 
+// nu reads three table entries per point; each workgroup first copies the two
+// nu tables into LDS (at most 2 x 4096 words) and then strides over the points.
 __global__ void __launch_bounds__(kBlock) k_nu(MapParams P, const int32_t *__restrict__ xy, int64_t count,
                                                uint64_t *__restrict__ idx)
 {
+    extern __shared__ uint32_t s_nu[];
+    const uint32_t nwords = P.ntab - (uint32_t)(P.nu_lo - P.lam_lo);
+    for (uint32_t i = threadIdx.x; i < nwords; i += kBlock) s_nu[i] = P.nu_lo[i];
+    __syncthreads();
+    MapParams L = P;
+    L.nu_lo = s_nu;
+    L.nu_top = s_nu + (P.nu_top - P.nu_lo);
     const int64_t stride = (int64_t)gridDim.x * kBlock * kMapUnroll;
     for (int64_t i0 = (int64_t)blockIdx.x * kBlock * kMapUnroll + threadIdx.x; i0 < count; i0 += stride) {
         int2 p[kMapUnroll];
@@ -77,7 +86,7 @@ __global__ void __launch_bounds__(kBlock) k_nu(MapParams P, const int32_t *__res
 #pragma unroll
         for (int u = 0; u < kMapUnroll; ++u) {
             const int64_t i = i0 + (int64_t)u * kBlock;
-            if (i < count) idx[i] = nu_map(P, p[u].x, p[u].y);
+            if (i < count) idx[i] = nu_map(L, p[u].x, p[u].y);
         }
     }
 }
@@ -193,7 +202,19 @@ sqz_status launch_lambda(const MapParams &P, const uint64_t *idx, int64_t count,
 
 sqz_status launch_nu(const MapParams &P, const int32_t *xy, int64_t count, uint64_t *idx, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_nu, dim3(grid_for((uint64_t)count)), dim3(kBlock), 0, st, P, xy, count, idx);
+    // as many workgroups as are resident at once (each copies the tables once),
+    // and no more than the points need
+    const size_t lds = (size_t)(P.ntab - (uint32_t)(P.nu_lo - P.lam_lo)) * sizeof(uint32_t);
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_nu, kBlock, lds);
+    if (e != hipSuccess) return hip_error(e, "nu_map occupancy");
+    if (per_cu < 1) return set_error(SQZ_ERR_UNSUPPORTED, "nu tables (%zu B) do not fit in LDS", lds);
+    uint64_t grid = ((uint64_t)count + (uint64_t)kBlock * kMapUnroll - 1) / ((uint64_t)kBlock * kMapUnroll);
+    if (grid > (uint64_t)cus * per_cu) grid = (uint64_t)cus * per_cu;
+    if (grid == 0) grid = 1;
+    hipLaunchKernelGGL(k_nu, dim3((unsigned)grid), dim3(kBlock), lds, st, P, xy, count, idx);
     return after_launch("nu_map launch");
 }
 
