@@ -137,9 +137,10 @@ def test_r20_light_cones():
 
 
 def test_r21_indices_past_2_32():
-    """Level-21 triangle (10,460,353,203 cells, two 10.5 GB buffers): compact indices
+    """Level-21 triangle (10,460,353,203 cells, 10.5 GB buffers): compact indices
     past 2^32 and tile starts past 2^32 bytes.  One step exhaustively over a range
-    across index 2^32; twelve steps (a ten-step launch and a two-step launch) on
+    across index 2^32, and the thread-level step equal to it over the whole array;
+    twelve steps (a ten-step launch and a two-step launch) on
     windows along the tile edges of the tiles around index 2^32 and of the last
     tiles, and on light-cone samples over the whole array."""
     torch = torch_or_skip()
@@ -152,7 +153,14 @@ def test_r21_indices_past_2_32():
     b = torch.empty_like(a)
     F.compact_step(a, b)
     c0 = 2 ** 32 - 100_000
-    mismatch(to_np(b[c0:c0 + 200_000]), _range_step(O, seed, p, c0, 200_000), "r21 one step across 2^32")
+    want1 = _range_step(O, seed, p, c0, 200_000)
+    mismatch(to_np(b[c0:c0 + 200_000]), want1, "r21 one step across 2^32")
+    print("r21: one thread-level step", flush=True)
+    d = torch.empty_like(a)
+    F.compact_step(a, d, impl="cell")  # 64-bit lambda, in-chunk neighbours from 64-bit indices
+    mismatch(to_np(d[c0:c0 + 200_000]), want1, "r21 one thread-level step across 2^32")
+    assert torch.equal(d, b), "r21: thread-level and tiled steps differ"
+    del d
     print("r21: twelve steps", flush=True)
     res = F.compact_run(a, b, t)
     assert res is a
