@@ -45,6 +45,7 @@ __global__ void __launch_bounds__(256) k_valu(uint32_t *out, int iters, uint32_t
             if constexpr (OP == 7) asm volatile("v_fma_f32 %0, %0, %1, %2" : "+v"(a[i]) : "v"(m), "v"(b));
             if constexpr (OP == 8) asm volatile("v_add_u32 %0, %0, %1" : "+v"(a[i]) : "v"(m));
             if constexpr (OP == 9) asm volatile("v_xor_b32 %0, %0, %1" : "+v"(a[i]) : "v"(m));
+            if constexpr (OP == 10) asm volatile("v_lshl_or_b32 %0, %0, 3, %1" : "+v"(a[i]) : "v"(b));
         }
     }
     uint32_t r = 0;
@@ -121,7 +122,8 @@ int main()
             run<2>("v_or3_b32 (VOP3)", d, grid, iters, cus) || run<3>("v_bitop3_b32 (VOP3)", d, grid, iters, cus) ||
             run<4>("v_and_or_b32 (VOP3)", d, grid, iters, cus) || run<5>("v_bfe_u32 (VOP3)", d, grid, iters, cus) ||
             run<6>("v_fmac_f32 (VOP2)", d, grid, iters, cus) || run<7>("v_fma_f32 (VOP3)", d, grid, iters, cus) ||
-            run<8>("v_add_u32 (VOP2)", d, grid, iters, cus) || run<9>("v_xor_b32 (VOP2)", d, grid, iters, cus))
+            run<8>("v_add_u32 (VOP2)", d, grid, iters, cus) || run<9>("v_xor_b32 (VOP2)", d, grid, iters, cus) ||
+            run<10>("v_lshl_or_b32 (VOP3)", d, grid, iters, cus))
             return 1;
     }
     // shader clock under load: per-wave shader-clock ticks over real-time ticks

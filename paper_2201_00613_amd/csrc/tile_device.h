@@ -456,13 +456,39 @@ __device__ __forceinline__ void store16(uint8_t *p, uint4 v)
     }
 }
 
+// (a << S) | c as one instruction.  Written out because the compiler
+// rewrites ((a & m) << s) | c into a shift, an AND with the shifted mask and
+// a separate OR (and folds a single-bit extract into the shift after it).
+template <int S>
+__device__ __forceinline__ uint32_t lshl_or(uint32_t a, uint32_t c)
+{
+    if constexpr (S == 0) {
+        return a | c;
+    } else {
+        uint32_t d;
+        asm("v_lshl_or_b32 %0, %1, %2, %3" : "=v"(d) : "v"(a), "i"(S), "v"(c));
+        return d;
+    }
+}
+template <int B>
+__device__ __forceinline__ uint32_t bit_of(uint32_t a)
+{
+    return (a >> B) & 1u;
+}
+
+// One move: the cells of the block word x that reach their neighbours by a
+// shift of `Shift` bits, placed into layer `Layer`.  A left move masks its
+// sources first, so that the shift and the OR into the layer are one
+// instruction; a single-bit right move extracts its bit and does the same.
 template <int Layer, int Shift, uint32_t Mask, int NL>
 __device__ __forceinline__ void move_term(uint32_t x, uint32_t (&L)[NL])
 {
-    if constexpr (Shift > 0)
-        L[Layer] |= (x >> Shift) & Mask;
+    if constexpr (Shift < 0)
+        L[Layer] = lshl_or<-Shift>(x & (Mask >> -Shift), L[Layer]);
+    else if constexpr ((Mask & (Mask - 1u)) == 0u)
+        L[Layer] = lshl_or<__builtin_ctz(Mask)>(bit_of<__builtin_ctz(Mask) + Shift>(x), L[Layer]);
     else
-        L[Layer] |= (x << (-Shift)) & Mask;
+        L[Layer] |= (x >> Shift) & Mask;
 }
 
 template <class Pat, int NL, size_t... I>
@@ -476,10 +502,7 @@ __device__ __forceinline__ void apply_moves(uint32_t x, uint32_t (&L)[NL], std::
 template <int Layer, int Grp, int Src, int Bit, int NL, int NG>
 __device__ __forceinline__ void halo_term(const uint32_t (&w)[NG], uint32_t (&L)[NL])
 {
-    if constexpr (Bit >= Src)
-        L[Layer] |= (w[Grp] << (Bit - Src)) & (1u << Bit);
-    else
-        L[Layer] |= (w[Grp] >> (Src - Bit)) & (1u << Bit);
+    L[Layer] = lshl_or<Bit>(bit_of<Src>(w[Grp]), L[Layer]);
 }
 
 template <class Pat, int NL, int NG, size_t... I>
