@@ -460,7 +460,7 @@ def main() -> int:
     ap.add_argument("--level", type=int, default=16)
     ap.add_argument("--impl", default="auto", choices=["auto", "tile", "cell"])
     ap.add_argument("--form", default="auto", choices=["auto", "launches", "resident"],
-                    help="run form of sqz_compact_run_form (auto: resident when the tiles fit the chip)")
+                    help="run form of sqz_compact_run_form (auto: the library's choice for the step count)")
     ap.add_argument("--bb-steps", type=int, default=10)
     ap.add_argument("--r20-steps", type=int, default=20)
     ap.add_argument("--no-bb", action="store_true")
