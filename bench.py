@@ -4,7 +4,7 @@ Workload (N=1): level-16 Sierpinski triangle, replicas (0,0),(1,0),(0,1),
 43,046,721 compact cells, uint8 states from a Bernoulli(0.5) SplitMix64 start
 (seed 2201), B3/S23 steps ping-ponging between two compact buffers.  One
 "step" is one B3/S23 update of every cell.  The K timed steps are one
-sqz_compact_run call, in the run form the library picks for K steps: from 25
+sqz_compact_run call, in the run form the library picks for K steps: from 10
 steps (and where launches would need an extra one-step launch) one launch
 that holds all 729 tiles in LDS for all K steps, exchanging ring cells every
 ten steps; otherwise launches of ten steps.  The other form is timed beside

@@ -105,11 +105,11 @@ typedef enum sqz_map_impl { SQZ_MAP_SCALAR = 0, SQZ_MAP_MFMA = 1 } sqz_map_impl;
 
 /* How sqz_compact_run_form advances a run.
  *   SQZ_RUN_AUTO: RESIDENT when the fractal offers it (sqz_info.resident_run),
- *                 the buffers are 16-byte aligned, and either steps >= 25 or
+ *                 the buffers are 16-byte aligned, and either steps >= 10 or
  *                 LAUNCHES would need an extra launch to leave the result in the
  *                 buffer the step count's parity names (steps >= 2); else
  *                 LAUNCHES.  The resident run's fixed cost (loading and storing
- *                 every subtree once) pays from about 25 steps, measured on an
+ *                 every subtree once) pays from about 10 steps, measured on an
  *                 MI355X; sqz_run_form_auto reports the choice.
  *   SQZ_RUN_LAUNCHES: one kernel launch per group of up to
  *                 sqz_info.run_steps_per_launch steps, each reading its input

@@ -302,11 +302,10 @@ sqz_status sqz_compact_run(const sqz_fractal *f, uint8_t *d_a, uint8_t *d_b, int
 
 // SQZ_RUN_AUTO's choice on aligned buffers: the resident run when it is offered
 // and either the run is long enough for its fixed cost (loading and storing
-// every tile once: at level 16 two ten-step launches are ahead at 20 steps,
-// the two forms tie at 21 and the resident run is ahead from 25) or the
-// launches would need a one-step launch of their own to land the result in
-// the buffer of the step count's parity.
-constexpr int32_t kAutoResidentSteps = 25;
+// every tile once: at level 16 it is ahead of launches of ten steps from 10
+// steps on) or the launches would need a one-step launch of their own to land
+// the result in the buffer of the step count's parity.
+constexpr int32_t kAutoResidentSteps = 10;
 
 static bool auto_resident(const FractalHost &h, int32_t steps)
 {

@@ -71,9 +71,11 @@ k_life_tileK(TileArgs A, const uint8_t *__restrict__ in, uint8_t *__restrict__ o
 #define SQZ_RESIDENT_PAD(pad) (pad)
 #endif
 
-// Resident run: one workgroup per tile for all steps, every tile on the chip at once.
+// Resident run: one workgroup per tile for all steps, every tile on the chip at once
+// (at most ceil(tiles / CUs) workgroups per CU: six waves per SIMD for the level-16
+// triangle, so the register budget is that of six).
 template <class Pat, int NT>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 256 ? 8 : SQZ_BIG_WAVES)))
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 256 ? 8 : (SQZ_RES_STATIC ? 6 : SQZ_BIG_WAVES))))
 k_life_tileR(TileArgs A, ResidentArgs P)
 {
     using LDS = TileLds<Pat>;

@@ -27,6 +27,7 @@
 // neighbouring tiles never overwrite each other.
 #pragma once
 
+#include <type_traits>
 #include <utility>
 
 #include "common.h"
@@ -569,6 +570,41 @@ struct NbRegs {
     }
 };
 
+#ifndef SQZ_RES_STATIC  // 1: resident rounds read LDS at fixed buffer addresses through unpacked offsets
+#define SQZ_RES_STATIC 1
+#endif
+#ifndef SQZ_RES_UNPACK  // slots whose offsets the resident rounds hold unpacked (the rest stay packed)
+#define SQZ_RES_UNPACK 3
+#endif
+// The same offsets one per register (twice the registers): with the state
+// buffer at a fixed LDS address, a block's neighbour word is then read with
+// the offset register as the address and the buffer in the instruction's
+// offset field, without an add per read.
+template <class Pat, int NT>
+struct NbOffs {
+    static constexpr int NSLOT = NbRegs<Pat, NT>::NSLOT;
+    static constexpr int NU = SQZ_RES_UNPACK < NSLOT ? SQZ_RES_UNPACK : NSLOT;  // slots held unpacked
+    static constexpr int NP = NbRegs<Pat, NT>::NP;
+    uint32_t o[NU > 0 ? NU : 1][TileLds<Pat>::NGRP];
+    uint32_t p[NSLOT - NU > 0 ? NSLOT - NU : 1][NP];
+    __device__ __forceinline__ uint32_t at(int s, int g) const
+    {
+        if (s < NU) return o[s][g];
+        return g & 1 ? p[s - NU][g >> 1] >> 16 : p[s - NU][g >> 1] & 0xFFFFu;
+    }
+    __device__ __forceinline__ void keep_packed()
+    {
+#pragma unroll
+        for (int s = 0; s < NU; ++s)
+#pragma unroll
+            for (int g = 0; g < TileLds<Pat>::NGRP; ++g) asm volatile("" : "+v"(o[s][g]));
+#pragma unroll
+        for (int s = 0; s < NSLOT - NU; ++s)
+#pragma unroll
+            for (int q = 0; q < NP; ++q) asm volatile("" : "+v"(p[s][q]));
+    }
+};
+
 template <class Pat, int NT>
 __device__ __forceinline__ void load_nb(const TileArgs &A, NbRegs<Pat, NT> &R)
 {
@@ -594,8 +630,8 @@ __device__ __forceinline__ void load_nb(const TileArgs &A, NbRegs<Pat, NT> &R)
 // which lets the compiler overlap one slot's LDS reads with another's logic.
 // sel (not Full): bit s set = update the blocks of slot s (the same for every
 // lane of a wave).
-template <class Pat, int NT, bool Full = false>
-__device__ __forceinline__ void tile_blocks(const TileArgs &A, NbRegs<Pat, NT> &R, const uint32_t *src, uint32_t *dst,
+template <class Pat, int NT, bool Full = false, class Regs = NbRegs<Pat, NT>>
+__device__ __forceinline__ void tile_blocks(const TileArgs &A, Regs &R, const uint32_t *src, uint32_t *dst,
                                             uint32_t sel = ~0u)
 {
     R.keep_packed();
@@ -1005,10 +1041,71 @@ __device__ __forceinline__ void tile_bodyR(const TileArgs &A, const ResidentArgs
             for (int g = 0; g < LDS::NGRP; ++g) ring |= R.at(sl, g) >= 4u * LDS::VIRT;
         if (__ballot(ring)) defer |= 1u << sl;
     }
+    // 512-lane workgroups (six waves per SIMD) have the registers for offsets held
+    // unpacked; the 256-lane ones (eight) keep the packed form
+    constexpr bool STATIC = SQZ_RES_STATIC && NT >= 512;
+    NbOffs<Pat, NT> U;
+    if constexpr (STATIC) {
+#pragma unroll
+        for (int sl = 0; sl < NbOffs<Pat, NT>::NU; ++sl)
+#pragma unroll
+            for (int g = 0; g < LDS::NGRP; ++g) U.o[sl][g] = R.at(sl, g);
+#pragma unroll
+        for (int sl = NbOffs<Pat, NT>::NU; sl < NbOffs<Pat, NT>::NSLOT; ++sl)
+#pragma unroll
+            for (int q = 0; q < NbOffs<Pat, NT>::NP; ++q) U.p[sl - NbOffs<Pat, NT>::NU][q] = R.a[sl][q];
+    }
     const uint8_t *imp = nullptr;  // exchange buffer whose barrier this workgroup has arrived at, not yet passed
     int32_t done = 0;
     for (;;) {
         const int32_t ks = P.steps - done < P.kstep ? P.steps - done : P.kstep;
+        if constexpr (STATIC) {
+        for (int32_t j = 1; j <= ks; ++j) {
+            // one round from buffer C (a compile-time choice, so every LDS
+            // address below is a register plus a constant)
+            auto round = [&](auto Cc) {
+                constexpr uint32_t C = decltype(Cc)::value, NX = C == 2 ? 0 : C + 1, CL = NX == 2 ? 0 : NX + 1;
+                const uint32_t *src = s_buf + C * WORDS;
+                uint32_t *dst = s_buf + NX * WORDS;
+                if (imp) {
+                    tile_blocks<Pat, NT>(A, U, src, dst, ~defer);
+                    if (tid == 0) barrier_poll(P.bar, base + nbar, P.flag);
+                    __syncthreads();
+                    v = 0;
+                    if (tid < kMaxRing)
+                        v = here ? (__hip_atomic_load(imp + gi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1u) : 0u;
+                    if (v) atomicOr(lds_word(s_buf + C * WORDS, home), 1u << (home & 31));
+                    __syncthreads();
+                    tile_blocks<Pat, NT>(A, U, src, dst, defer);
+                    imp = nullptr;
+                } else {
+                    tile_blocks<Pat, NT>(A, U, src, dst);
+                }
+                if (j < ks) {
+                    uint32_t *clr = s_buf + CL * WORDS;
+                    if (tid < WORDS - LDS::VIRT) clr[LDS::VIRT + tid] = 0;
+                    if (tid < s_rs[ks - j]) {
+                        const uint4 e0 = *reinterpret_cast<const uint4 *>(s_ring + tid * 8);
+                        const uint4 e1 = *reinterpret_cast<const uint4 *>(s_ring + tid * 8 + 4);
+                        const uint32_t cnt = lds_bit(src, e0.x) + lds_bit(src, e0.y) + lds_bit(src, e0.z) +
+                                             lds_bit(src, e0.w) + lds_bit(src, e1.x) + lds_bit(src, e1.y) +
+                                             lds_bit(src, e1.z) + lds_bit(src, e1.w);
+                        const uint32_t h = s_ring[kMaxRing * 8 + tid];
+                        const uint32_t self = lds_bit(src, h);
+                        if (here & ((cnt == 3) | (self & (cnt == 2)))) atomicOr(lds_word(dst, h), 1u << (h & 31));
+                    }
+                }
+            };
+            if (cur == 0)
+                round(std::integral_constant<uint32_t, 0>{});
+            else if (cur == 1)
+                round(std::integral_constant<uint32_t, 1>{});
+            else
+                round(std::integral_constant<uint32_t, 2>{});
+            __syncthreads();
+            cur = cur == 2 ? 0 : cur + 1;
+        }
+        } else {
         for (int32_t j = 1; j <= ks; ++j) {
             const uint32_t nx = cur == 2 ? 0 : cur + 1, cl = nx == 2 ? 0 : nx + 1;
             const uint32_t *src = s_buf + cur * WORDS;
@@ -1045,6 +1142,7 @@ __device__ __forceinline__ void tile_bodyR(const TileArgs &A, const ResidentArgs
             }
             __syncthreads();
             cur = nx;
+        }
         }
         done += ks;
         if (done >= P.steps) break;

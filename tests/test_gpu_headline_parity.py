@@ -3,9 +3,8 @@ level-10 triangle tiles that sqz_compact_run uses from level 16 up (Section
 "Moving from Thread-level to Block-level"; the Life workload of Section
 "Experimental Setup and Results"), in both run forms: the resident run (one
 launch, all 729 tiles of the level-16 triangle held in LDS at once, ring
-cells exchanged every ten steps; the default at level 16 from 25 steps) and
-launches of ten steps (the form of every larger level, and of level 16 for
-fewer steps, 20 included).
+cells exchanged every ten steps; the default at level 16 from 10 steps) and
+launches of ten steps (the form of every larger level).
 
 * Level 16, seed 2201, Bernoulli(0.5): all 43,046,721 cells after 20 steps
   and after 100 steps, in each run form, against the oracle's neighbour-table

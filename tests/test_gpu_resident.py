@@ -130,7 +130,7 @@ def _launch_count(steps, K):
 
 
 def test_zero_steps_and_auto_choice():
-    """The auto form is the resident run for 25 steps and more, and below that where the
+    """The auto form is the resident run for 10 steps and more, and below that where the
     launches form needs an extra one-step launch for the result's buffer (never for
     fewer than two steps); either way the results equal the explicit forms'."""
     torch = torch_or_skip()
@@ -144,9 +144,9 @@ def test_zero_steps_and_auto_choice():
     assert F.compact_run(a, torch.empty_like(a), 0, form="resident") is a
     assert torch.equal(a, keep)
     for steps in range(0, 61):
-        want = steps >= 2 and (steps >= 25 or _launch_count(steps, K) > -(-steps // K))
+        want = steps >= 2 and (steps >= 10 or _launch_count(steps, K) > -(-steps // K))
         assert F.auto_run_form(steps) == ("resident" if want else "launches"), steps
-    for steps in (5, 10, 20, 23, 24, 25, 31):
+    for steps in (5, 9, 10, 11, 20, 25, 31):
         r_auto = F.compact_run(a.clone(), torch.empty_like(a), steps)
         r_res = F.compact_run(a.clone(), torch.empty_like(a), steps, form="resident")
         r_lau = F.compact_run(a.clone(), torch.empty_like(a), steps, form="launches")
