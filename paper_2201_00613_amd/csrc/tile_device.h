@@ -576,10 +576,11 @@ struct NbRegs {
 #ifndef SQZ_RES_UNPACK  // slots whose offsets the resident rounds hold unpacked (the rest stay packed)
 #define SQZ_RES_UNPACK 3
 #endif
-// The same offsets one per register (twice the registers): with the state
-// buffer at a fixed LDS address, a block's neighbour word is then read with
-// the offset register as the address and the buffer in the instruction's
-// offset field, without an add per read.
+// The same offsets, those of the first SQZ_RES_UNPACK slots one per register
+// (the rest packed as in NbRegs): with the state buffer at a fixed LDS
+// address, a neighbour word of an unpacked slot is read with its offset
+// register as the address and the buffer in the instruction's offset field,
+// without the add that unpacks and rebases a packed offset.
 template <class Pat, int NT>
 struct NbOffs {
     static constexpr int NSLOT = NbRegs<Pat, NT>::NSLOT;
