@@ -274,3 +274,42 @@ def test_error_paths():
     # a handle used on the wrong device is refused (only one device here: nothing to test)
     info = sqz._lib.Info()
     assert L.sqz_fractal_info(F._h, ctypes.byref(info)) == 0 and info.cells == 3 ** 6
+
+
+# A 4 x 4 frame: the twelve border cells of the box are the replicas.
+FRAME4 = (4, tuple((x, y) for y in range(4) for x in range(4) if x in (0, 3) or y in (0, 3)))
+
+
+def test_thread_level_step_and_nu_with_large_map_tables():
+    """The thread-level step copies all four map tables into LDS and the nu kernel its
+    two: on the 4 x 4 frame at level 6 (2,985,984 cells) they are 11,648 words (46.6 KB)
+    and 8,192 words (32 KB).  One and three thread-level steps over the whole array
+    against the oracle's neighbour-table steps; nu over every point of a 1,030 x 1,030
+    window of the box and its surroundings against the oracle's nu, and nu(lambda(c)) = c
+    for every cell."""
+    torch = torch_or_skip()
+    import oracle
+    import paper_2201_00613_amd as sqz
+
+    s, offs = FRAME4
+    F, O = sqz.Fractal(s, offs, 6), oracle.Fractal(s, offs, 6)
+    assert F.cells == 12 ** 6
+    start = O.fill_compact(5, 0.35)
+    a = F.fill_bernoulli(5, 0.35)
+    mismatch(to_np(a), start, "frame fill")
+    nb = O.neighbour_table()
+    b = torch.empty_like(a)
+    F.compact_step(a, b, impl="cell")
+    mismatch(to_np(b), O.life_steps(start, 1, nb), "frame: one thread-level step")
+    x, y = b, a
+    for _ in range(2):
+        F.compact_step(x, y, impl="cell")
+        x, y = y, x
+    mismatch(to_np(x), O.life_steps(start, 3, nb), "frame: three thread-level steps")
+    del nb
+    idx = torch.arange(F.cells, dtype=torch.int64, device="cuda")
+    mismatch(to_np(F.nu_map(F.lambda_map(idx))), np.arange(F.cells), "frame: nu o lambda")
+    ys, xs = np.mgrid[-1:1029, F.n - 1029:F.n + 1]
+    pts = np.stack([xs.ravel(), ys.ravel()], 1).astype(np.int32)
+    got = to_np(F.nu_map(torch.from_numpy(pts).cuda()))
+    mismatch(got, O.nu(pts.astype(np.int64)), "frame: nu over a window")
